@@ -1,0 +1,416 @@
+/*
+ * vbdr_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT PATH.
+ *
+ * A plain, slow, single-threaded CPU reference of the VBDR method of
+ * J. Xu, "Cardinalities estimation under sliding time window by sharing
+ * HyperLogLog Counter" (arXiv:1810.13132).  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load this library.
+ * It shares no code, header or table with the HIP library.
+ *
+ * Every routine follows the paper's steps in the paper's order, written for
+ * clarity rather than speed: getPhyIdx recomputes its seed hash on every
+ * call, GetLBP1BDR walks the recorder vector from the top, and the scan
+ * touches one pair at a time.  Integer state is exact; estimates are FP64.
+ *
+ * Readings of the paper taken here (the paper is silent or garbled):
+ *  - The pool size is called m (the paper reuses the letter z for it and for
+ *    the recorder width).  A distance recorder (DR) is one byte, z = 8, so
+ *    InitDR stores 255 and SlideDR saturates at 255 (Sec. 3 defines SlideDR
+ *    with a bound that would let a z-bit counter wrap; saturation is the only
+ *    reading under which an old LBP1 never turns active again).
+ *  - The recorder vector covers every LBP1 value the hash can produce,
+ *    L = 33 - b values (1..L), instead of ceil(log2(n/g)) values; no clamp.
+ *  - LBP1 of an all-zero (32-b)-bit suffix is (32-b)+1, the HyperLogLog
+ *    convention.
+ *  - H(x, N, A) is MurmurHash3_x86_32 of the 4-byte little-endian x with
+ *    seed A, reduced to [0, N) by the multiply-shift map (h * N) >> 32; for
+ *    N = 2^32 this is the hash itself.  The bip hash uses seed A1 and the
+ *    virtual-index seeds use A0 (Alg. 3, Alg. 4).  A0 and A1 are the low and
+ *    high halves of one SplitMix64 output drawn from the user's hash seed.
+ *  - Serial layout: nowLBP1 is cleared after each end-of-slice update.
+ *  - Fast GPU layout (Alg. 6): the slice's LBP1 is the highest set bit of
+ *    bsLBP1 (bit r-1 records LBP1 = r), and an empty slice sets no DR.
+ *  - Small GPU layout (Alg. 8/9): the close of slice t and the beginning of
+ *    slice t+1 are the same moment; the registers of the closed window are
+ *    read (Alg. 2, dr < k) and then every DR slides for the next slice.
+ *  - Estimation (Alg. 5 and the HyperLogLog estimator it points to): the
+ *    register histogram of a host's g recorders gives the harmonic sum; the
+ *    HyperLogLog constants alpha_q and its small-range (linear counting)
+ *    correction apply; the noise of pool sharing is removed with
+ *    n = (m*E_s - g*E_m)/(m - g), E_m being the same estimator over the whole
+ *    pool.  The result is clamped at 0 and rounded to FP32.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define VBDRO_SERIAL 0
+#define VBDRO_GFAST 1
+#define VBDRO_GSMALL 2
+
+#define DR_BITS 8u
+#define DR_INIT 255u /* InitDR: 2^z - 1 with z = 8 */
+#define NBINS 33u    /* register values 0..32 */
+
+/* ------------------------------------------------------------------ */
+/* Hash primitives                                                     */
+/* ------------------------------------------------------------------ */
+
+static uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
+
+/* MurmurHash3_x86_32 (A. Appleby, public domain), written from its
+ * published description: 4-byte blocks mixed with two odd constants and
+ * rotations, a tail block, the length, then the final avalanche. */
+uint32_t vbdro_murmur3_32(const uint8_t *data, uint64_t len, uint32_t seed)
+{
+    const uint32_t c1 = 0xcc9e2d51u, c2 = 0x1b873593u;
+    uint32_t h = seed;
+    uint64_t nblocks = len / 4;
+    for (uint64_t i = 0; i < nblocks; i++) {
+        uint32_t k = (uint32_t)data[4 * i] | ((uint32_t)data[4 * i + 1] << 8) |
+                     ((uint32_t)data[4 * i + 2] << 16) | ((uint32_t)data[4 * i + 3] << 24);
+        k *= c1;
+        k = rotl32(k, 15);
+        k *= c2;
+        h ^= k;
+        h = rotl32(h, 13);
+        h = h * 5u + 0xe6546b64u;
+    }
+    const uint8_t *tail = data + 4 * nblocks;
+    uint32_t k1 = 0;
+    switch (len & 3) {
+    case 3:
+        k1 ^= (uint32_t)tail[2] << 16; /* fall through */
+    case 2:
+        k1 ^= (uint32_t)tail[1] << 8; /* fall through */
+    case 1:
+        k1 ^= (uint32_t)tail[0];
+        k1 *= c1;
+        k1 = rotl32(k1, 15);
+        k1 *= c2;
+        h ^= k1;
+    }
+    h ^= (uint32_t)len;
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+/* H(x, N, A) of Sec. 4.1: a seeded random hash of x into [0, N). */
+uint32_t vbdro_H(uint32_t x, uint64_t N, uint32_t A)
+{
+    uint8_t key[4] = {(uint8_t)x, (uint8_t)(x >> 8), (uint8_t)(x >> 16), (uint8_t)(x >> 24)};
+    uint32_t h = vbdro_murmur3_32(key, 4, A);
+    return (uint32_t)(((uint64_t)h * N) >> 32);
+}
+
+/* SplitMix64 (Steele, Lea, Flood 2014): one output from state *s. */
+uint64_t vbdro_splitmix64(uint64_t *s)
+{
+    uint64_t z = (*s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+/* LB(x, i): the left i bits of the 32-bit x (Sec. 4.1). */
+static uint32_t LB(uint32_t x, uint32_t i) { return i == 0 ? 0u : x >> (32 - i); }
+
+/* LBP1 of the (32-b)-bit string held in the top bits of w (Sec. 3, the
+ * HyperLogLog rho): the position, counted from 1 at the left, of the
+ * leftmost 1 bit; (32-b)+1 when all 32-b bits are 0. */
+uint32_t vbdro_lbp1(uint32_t w, uint32_t b)
+{
+    uint32_t width = 32 - b;
+    for (uint32_t pos = 1; pos <= width; pos++)
+        if ((w >> (32 - pos)) & 1u)
+            return pos;
+    return width + 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sketch state                                                        */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t m;       /* BDRs in the pool BDRP */
+    uint32_t g, b, L; /* g = 2^b recorders per host; L = 33-b LBP1 values */
+    uint32_t k;       /* window length in slices */
+    int layout;
+    uint32_t A0, A1;
+    uint8_t *drv;     /* DRV of BDR p at drv[p*(L+1) + i], i = 1..L */
+    uint8_t *now;     /* serial: nowLBP1 per BDR */
+    uint32_t *bs;     /* fast GPU layout: bsLBP1 per BDR, bit r-1 <-> LBP1 r */
+    uint8_t *reg;     /* register of each BDR over the last closed window */
+    uint64_t pool_hist[NBINS];
+    uint64_t t;       /* closed slices */
+} vbdro_sketch;
+
+static int is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+vbdro_sketch *vbdro_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout)
+{
+    if (!is_pow2(g) || g < 2 || g > 65536u || m <= g || m >= (1ull << 32) || k < 1 || k > 254 ||
+        layout < VBDRO_SERIAL || layout > VBDRO_GSMALL)
+        return NULL;
+    vbdro_sketch *s = (vbdro_sketch *)calloc(1, sizeof(*s));
+    if (!s)
+        return NULL;
+    s->m = m;
+    s->g = g;
+    s->b = 0;
+    while ((1u << s->b) < g)
+        s->b++;
+    s->L = 33 - s->b;
+    s->k = k;
+    s->layout = layout;
+    uint64_t st = hash_seed;
+    uint64_t x = vbdro_splitmix64(&st);
+    s->A0 = (uint32_t)x;
+    s->A1 = (uint32_t)(x >> 32);
+    s->drv = (uint8_t *)malloc(m * (s->L + 1));
+    s->reg = (uint8_t *)calloc(m, 1);
+    if (layout == VBDRO_SERIAL)
+        s->now = (uint8_t *)calloc(m, 1);
+    if (layout == VBDRO_GFAST)
+        s->bs = (uint32_t *)calloc(m, sizeof(uint32_t));
+    if (!s->drv || !s->reg || (layout == VBDRO_SERIAL && !s->now) || (layout == VBDRO_GFAST && !s->bs)) {
+        free(s->drv), free(s->reg), free(s->now), free(s->bs), free(s);
+        return NULL;
+    }
+    for (uint64_t p = 0; p < m; p++)
+        for (uint32_t i = 0; i <= s->L; i++)
+            s->drv[p * (s->L + 1) + i] = (uint8_t)DR_INIT; /* InitDR */
+    s->pool_hist[0] = m;
+    s->t = 0;
+    return s;
+}
+
+void vbdro_destroy(vbdro_sketch *s)
+{
+    if (!s)
+        return;
+    free(s->drv), free(s->reg), free(s->now), free(s->bs), free(s);
+}
+
+/* DR operations of Sec. 3. */
+static void SetDR(uint8_t *dr) { *dr = 0; }
+static void SlideDR(uint8_t *dr)
+{
+    if (*dr < DR_INIT)
+        (*dr)++;
+}
+static int IsActiveDR(uint8_t dr, uint32_t k) { return dr < k; }
+
+static uint8_t *DRV(vbdro_sketch *s, uint64_t p) { return s->drv + p * (s->L + 1); }
+
+/* Alg. 3 getPhyIdx: seed s1 from the virtual index, then hash the host. */
+uint32_t vbdro_phy_idx(const vbdro_sketch *s, uint32_t aip, uint32_t i)
+{
+    uint32_t s1 = vbdro_H(i, 1ull << 32, s->A0);
+    return vbdro_H(aip, s->m, s1);
+}
+
+/* Steps shared by Alg. 4, 7 and 9: from a pair to (pidx, LBP1). */
+static void map_pair(const vbdro_sketch *s, uint32_t aip, uint32_t bip, uint32_t *pidx, uint32_t *r)
+{
+    uint32_t bh = vbdro_H(bip, 1ull << 32, s->A1);
+    uint32_t vidx = LB(bh, s->b);
+    bh = bh << s->b;
+    *pidx = vbdro_phy_idx(s, aip, vidx);
+    *r = vbdro_lbp1(bh, s->b);
+}
+
+void vbdro_pair_map(const vbdro_sketch *s, const uint32_t *pairs, uint64_t n, uint32_t *pidx, uint8_t *rho)
+{
+    for (uint64_t j = 0; j < n; j++) {
+        uint32_t p, r;
+        map_pair(s, pairs[2 * j], pairs[2 * j + 1], &p, &r);
+        pidx[j] = p;
+        rho[j] = (uint8_t)r;
+    }
+}
+
+/* The same mapping without a pool, for pools too large to hold here. */
+int vbdro_map_pairs(uint64_t m, uint32_t g, uint64_t hash_seed, const uint32_t *pairs, uint64_t n, uint32_t *pidx,
+                    uint8_t *rho)
+{
+    if (!is_pow2(g) || g < 2 || g > 65536u || m <= g || m >= (1ull << 32))
+        return -1;
+    vbdro_sketch s;
+    memset(&s, 0, sizeof(s));
+    s.m = m, s.g = g;
+    while ((1u << s.b) < g)
+        s.b++;
+    s.L = 33 - s.b;
+    uint64_t st = hash_seed, x = vbdro_splitmix64(&st);
+    s.A0 = (uint32_t)x, s.A1 = (uint32_t)(x >> 32);
+    vbdro_pair_map(&s, pairs, n, pidx, rho);
+    return 0;
+}
+
+/* Scan the pairs of the open slice: Alg. 4 (serial), Alg. 7 (fast GPU
+ * layout), Alg. 9 (small GPU layout), one pair at a time. */
+void vbdro_scan(vbdro_sketch *s, const uint32_t *pairs, uint64_t n)
+{
+    for (uint64_t j = 0; j < n; j++) {
+        uint32_t p, r;
+        map_pair(s, pairs[2 * j], pairs[2 * j + 1], &p, &r);
+        if (s->layout == VBDRO_SERIAL) {
+            if (r > s->now[p])
+                s->now[p] = (uint8_t)r;
+        } else if (s->layout == VBDRO_GFAST) {
+            s->bs[p] |= 1u << (r - 1);
+        } else {
+            SetDR(&DRV(s, p)[r]);
+        }
+    }
+}
+
+/* Alg. 2 GetLBP1BDR: the largest LBP1 whose DR is active, else 0. */
+static uint32_t GetLBP1BDR(vbdro_sketch *s, uint64_t p)
+{
+    uint8_t *v = DRV(s, p);
+    for (uint32_t lbp1 = s->L; lbp1 >= 1; lbp1--)
+        if (IsActiveDR(v[lbp1], s->k))
+            return lbp1;
+    return 0;
+}
+
+/* Close the open slice. */
+void vbdro_advance(vbdro_sketch *s)
+{
+    for (uint64_t p = 0; p < s->m; p++) {
+        uint8_t *v = DRV(s, p);
+        if (s->layout == VBDRO_SERIAL) {
+            /* Alg. 1 EndSliceUpdateBDR, then nowLBP1 starts the next slice at 0. */
+            for (uint32_t i = 1; i <= s->L; i++)
+                SlideDR(&v[i]);
+            if (s->now[p] > 0)
+                SetDR(&v[s->now[p]]);
+            s->now[p] = 0;
+            s->reg[p] = (uint8_t)GetLBP1BDR(s, p);
+        } else if (s->layout == VBDRO_GFAST) {
+            /* Alg. 6 EndSliceUpdateBDRGpu: the slice's LBP1 is the highest
+             * set bit of bsLBP1; bsLBP1 is reset for the next slice. */
+            for (uint32_t i = 1; i <= s->L; i++)
+                SlideDR(&v[i]);
+            uint32_t lbp1 = 0;
+            for (uint32_t i = 1; i <= s->L; i++)
+                if ((s->bs[p] >> (i - 1)) & 1u)
+                    lbp1 = i;
+            if (lbp1 > 0)
+                SetDR(&v[lbp1]);
+            s->bs[p] = 0;
+            s->reg[p] = (uint8_t)GetLBP1BDR(s, p);
+        } else {
+            /* Small layout: read the closed window first (Alg. 2), then
+             * Alg. 8 BeginSliceUpdateDRV for the next slice. */
+            s->reg[p] = (uint8_t)GetLBP1BDR(s, p);
+            for (uint32_t i = 1; i <= s->L; i++)
+                SlideDR(&v[i]);
+        }
+    }
+    memset(s->pool_hist, 0, sizeof(s->pool_hist));
+    for (uint64_t p = 0; p < s->m; p++)
+        s->pool_hist[s->reg[p]]++;
+    s->t++;
+}
+
+/* HyperLogLog bias constant alpha_q (Flajolet et al. 2007). */
+double vbdro_alpha(double q)
+{
+    if (q == 16.0)
+        return 0.673;
+    if (q == 32.0)
+        return 0.697;
+    if (q == 64.0)
+        return 0.709;
+    return 0.7213 / (1.0 + 1.079 / q);
+}
+
+/* HyperLogLog estimate of q registers given their histogram hist[0..32]:
+ * E = alpha_q q^2 / sum_j 2^-M_j, replaced by linear counting q ln(q/V) when
+ * E <= 2.5 q and V = hist[0] > 0.  The harmonic sum is formed exactly as the
+ * integer U = sum_r hist[r] 2^(32-r) (sum_j 2^-M_j = U 2^-32); q < 2^32. */
+double vbdro_hll_from_hist(const uint64_t *hist, double q)
+{
+    uint64_t U = 0;
+    for (uint32_t r = 0; r < NBINS; r++)
+        U += hist[r] << (32 - r);
+    double S = (double)U * 0x1p-32;
+    double E = vbdro_alpha(q) * q * q / S;
+    if (E <= 2.5 * q && hist[0] > 0)
+        E = q * log(q / (double)hist[0]);
+    return E;
+}
+
+/* Alg. 5 getSumLBP1, generalised from the sum of LBP1 values to their
+ * histogram, then the noise-removed estimate.  hist_out (n*33, nullable)
+ * receives each host's histogram; raw_es (nullable) its E_s. */
+void vbdro_estimate(vbdro_sketch *s, const uint32_t *hosts, uint64_t n, float *out, double *raw_es,
+                    uint32_t *hist_out)
+{
+    double Em = vbdro_hll_from_hist(s->pool_hist, (double)s->m);
+    for (uint64_t h = 0; h < n; h++) {
+        uint64_t hist[NBINS];
+        memset(hist, 0, sizeof(hist));
+        for (uint32_t i = 0; i < s->g; i++) {
+            uint32_t pidx = vbdro_phy_idx(s, hosts[h], i);
+            hist[s->reg[pidx]]++; /* the register GetLBP1BDR gave at the close */
+        }
+        double Es = vbdro_hll_from_hist(hist, (double)s->g);
+        double nh = ((double)s->m * Es - (double)s->g * Em) / ((double)s->m - (double)s->g);
+        out[h] = (float)(nh > 0.0 ? nh : 0.0);
+        if (raw_es)
+            raw_es[h] = Es;
+        if (hist_out)
+            for (uint32_t r = 0; r < NBINS; r++)
+                hist_out[h * NBINS + r] = (uint32_t)hist[r];
+    }
+}
+
+/* Literal Alg. 5: the sum of the g LBP1 values of a host. */
+uint64_t vbdro_sum_lbp1(vbdro_sketch *s, uint32_t aip)
+{
+    uint64_t sum = 0;
+    for (uint32_t i = 0; i < s->g; i++)
+        sum += s->reg[vbdro_phy_idx(s, aip, i)];
+    return sum;
+}
+
+/* ------------------------------------------------------------------ */
+/* Introspection for tests                                             */
+/* ------------------------------------------------------------------ */
+
+/* out[0..8] = m, g, b, L, k, layout, A0, A1, t */
+void vbdro_params(const vbdro_sketch *s, uint64_t *out)
+{
+    out[0] = s->m, out[1] = s->g, out[2] = s->b, out[3] = s->L, out[4] = s->k;
+    out[5] = (uint64_t)s->layout, out[6] = s->A0, out[7] = s->A1, out[8] = s->t;
+}
+
+/* Canonical state: dr[p*L + (i-1)] = DRV[i] of BDR p; bs[p] (fast layout)
+ * and now[p] (serial layout) when the sketch has them; reg[p]; hist[33].
+ * Any output pointer may be NULL. */
+void vbdro_get_state(const vbdro_sketch *s, uint8_t *dr, uint32_t *bs, uint8_t *now, uint8_t *reg,
+                     uint64_t *hist)
+{
+    for (uint64_t p = 0; p < s->m; p++) {
+        if (dr)
+            for (uint32_t i = 1; i <= s->L; i++)
+                dr[p * s->L + (i - 1)] = s->drv[p * (s->L + 1) + i];
+        if (bs)
+            bs[p] = s->bs ? s->bs[p] : 0u;
+        if (now)
+            now[p] = s->now ? s->now[p] : 0u;
+        if (reg)
+            reg[p] = s->reg[p];
+    }
+    if (hist)
+        memcpy(hist, s->pool_hist, sizeof(s->pool_hist));
+}
