@@ -1,0 +1,163 @@
+/*
+ * vbdr.h -- C ABI of libvbdr.so, the gfx950 (MI355X) implementation of the
+ * VBDR sliding-window host-cardinality estimator of J. Xu, "Cardinalities
+ * estimation under sliding time window by sharing HyperLogLog Counter"
+ * (arXiv:1810.13132).
+ *
+ * Model.  Traffic arrives as (aip, bip) IP pairs in time slices (Sec. 2.1,
+ * Sec. 2.3).  A sketch holds a pool BDRP of m bit distance recorders (BDRs,
+ * Sec. 3); every host aip owns a virtual vector of g = 2^b of them chosen by
+ * getPhyIdx (Alg. 3).  Each BDR keeps one distance recorder (DR) per LBP1
+ * value r = 1..L, L = 33 - b: the number of slices since r was last recorded
+ * there, one byte, saturating at 255 (Sec. 3, DR operations).  The window
+ * W(t, k) is the k most recently closed slices.
+ *
+ * Calling sequence per slice:  vbdr_scan_slice()*  ->  vbdr_advance_slice()
+ * ->  vbdr_estimate().  Scans of one slice may be split over any number of
+ * calls; their result does not depend on pair order or on repeated pairs.
+ *
+ * Two layouts (Sec. 4.2, Table 1):
+ *   VBDR_LAYOUT_FAST  -- the scan records each pair's LBP1 as one bit of a
+ *                        per-slice bit string (bsLBP1, Alg. 7) with an
+ *                        atomic OR; the advance folds the highest bit into
+ *                        the DRs (Alg. 6).  More memory, fastest scan.
+ *   VBDR_LAYOUT_SMALL -- the scan zeroes the DR of the pair's LBP1 directly
+ *                        (Alg. 9, a plain byte store); the advance slides
+ *                        every DR (Alg. 8).  Least memory.
+ * Both give identical registers and estimates.
+ *
+ * Hashing (the paper leaves H(x, N, A) open): H(x, N, A) is
+ * MurmurHash3_x86_32 of the 4-byte little-endian x with seed A, mapped to
+ * [0, N) as (h * N) >> 32.  A0 and A1 are the low and high 32-bit halves of
+ * the first SplitMix64 output from state hash_seed.
+ *
+ * Memory and streams.  A sketch owns its device memory (allocated in
+ * vbdr_sketch_create on the device current at that time).  Every other
+ * device pointer belongs to the caller and must stay valid until the work
+ * enqueued on `stream` finishes.  `stream` is a hipStream_t (NULL = the
+ * default stream); all device work of a call is enqueued on it without any
+ * host synchronisation, except where a function says "synchronous".  The
+ * calls of one sketch must be made from the device it was created on, and a
+ * sketch is not thread-safe.  scan_slice, advance_slice and the estimate
+ * calls allocate no memory.
+ *
+ * Errors.  Every int-returning function returns VBDR_OK (0) or a negative
+ * vbdr_status; vbdr_last_error() then describes the last failure of the
+ * calling thread.  On error no device work has been enqueued unless the
+ * status is VBDR_EHIP (a HIP call failed; the sketch may be unusable).
+ */
+#ifndef VBDR_H
+#define VBDR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VBDR_NBINS 33 /* register values 0..32 */
+
+typedef struct vbdr_sketch vbdr_sketch;
+
+enum vbdr_layout { VBDR_LAYOUT_FAST = 0, VBDR_LAYOUT_SMALL = 1 };
+
+enum vbdr_status {
+    VBDR_OK = 0,
+    VBDR_EINVAL = -1, /* bad argument (range, NULL, alignment, wrong device) */
+    VBDR_ENOMEM = -2, /* device allocation failed at create */
+    VBDR_EHIP = -3,   /* a HIP runtime call or kernel launch failed */
+    VBDR_ESTATE = -4  /* call not valid in the sketch's current state */
+};
+
+typedef struct vbdr_info {
+    uint64_t m;           /* BDRs in the pool */
+    uint32_t g, b, L, k;  /* g = 2^b recorders per host, L = 33 - b, window k */
+    int32_t layout;       /* enum vbdr_layout */
+    uint32_t A0, A1;      /* hash seeds derived from hash_seed */
+    uint64_t t;           /* slices closed so far */
+    uint64_t state_bytes; /* device bytes held by the sketch */
+} vbdr_info;
+
+/*
+ * Create a sketch: pool of m BDRs (BDRP, Sec. 4.1), g = 2^b recorders per
+ * host (power of two, 2 <= g <= 65536), g < m < 2^32, window of 1 <= k <= 254
+ * slices, hash seed as above.  Slice 0 is open; every DR holds its initial
+ * value 255 (InitDR), every register is 0.  vbdr_sketch_create uses the fast
+ * layout.  *out receives the handle (owned by the caller; free with
+ * vbdr_sketch_destroy).  Synchronous.
+ */
+int vbdr_sketch_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, vbdr_sketch **out);
+int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout,
+                              vbdr_sketch **out);
+
+/* Free a sketch and its device memory after synchronising the device.  NULL is a no-op. */
+void vbdr_sketch_destroy(vbdr_sketch *sk);
+
+/*
+ * Scan n pairs into the open slice (Alg. 7 for the fast layout, Alg. 9 for
+ * the small one, with the pair hashing of Alg. 4 and getPhyIdx of Alg. 3).
+ * pairs_dev: device array of 2n uint32, interleaved aip0, bip0, aip1, bip1,
+ * ..., 8-byte aligned; read only.  n = 0 is a no-op (pairs_dev may be NULL).
+ */
+int vbdr_scan_slice(vbdr_sketch *sk, const uint32_t *pairs_dev, uint64_t n, void *stream);
+
+/*
+ * Close the open slice and open the next (Alg. 6 or Alg. 8 over every BDR),
+ * then derive each BDR's register for the window of the k most recently
+ * closed slices (Alg. 2) and the pool's register histogram.
+ */
+int vbdr_advance_slice(vbdr_sketch *sk, void *stream);
+
+/*
+ * Estimate |OP(aip, t, k)| (Definition 1) over the window of the k most
+ * recently closed slices for n_hosts hosts: each host's g registers
+ * (Alg. 5, taken as a histogram) give the HyperLogLog estimate E_s of its
+ * virtual vector, E_m is the same estimate over the whole pool, and the
+ * sharing noise is removed as (m E_s - g E_m) / (m - g), clamped at 0.
+ * Computed in FP64, stored as FP32 (round to nearest).  Before the first
+ * advance every estimate is 0.
+ * hosts_dev: device array of n_hosts uint32 addresses; out_dev: device
+ * array of n_hosts float.  n_hosts = 0 is a no-op.
+ */
+int vbdr_estimate(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_hosts, float *out_dev, void *stream);
+
+/*
+ * vbdr_estimate plus optional per-host outputs: raw_es_dev (n_hosts double,
+ * the un-corrected E_s) and hist_dev (n_hosts x 33 uint32, the histogram of
+ * the host's g register values).  Either may be NULL.
+ */
+int vbdr_estimate_ex(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_hosts, float *out_dev,
+                     double *raw_es_dev, uint32_t *hist_dev, void *stream);
+
+/* Parameters and slice counter of a sketch.  Host only, no device work. */
+int vbdr_sketch_info(const vbdr_sketch *sk, vbdr_info *out);
+
+/*
+ * Copy the sketch state to host memory in canonical form (synchronous:
+ * waits for `stream`).  Any pointer may be NULL.
+ *   dr_host   m*L bytes, dr_host[p*L + (r-1)] = DR of LBP1 r in BDR p;
+ *   bs_host   m uint32, the open slice's bsLBP1 of BDR p, bit r-1 <-> r
+ *             (all zero for the small layout);
+ *   reg_host  m bytes, register of BDR p for the last closed window;
+ *   hist_host 33 uint64, histogram of reg over the pool.
+ */
+int vbdr_export_state(vbdr_sketch *sk, uint8_t *dr_host, uint32_t *bs_host, uint8_t *reg_host,
+                      uint64_t *hist_host, void *stream);
+
+/*
+ * Load a canonical state (same layout as vbdr_export_state; dr_host, reg_host
+ * and hist_host required, bs_host may be NULL = all zero) and the slice
+ * counter t into a sketch with the same parameters, for checkpoint/resume.
+ * Synchronous.
+ */
+int vbdr_import_state(vbdr_sketch *sk, const uint8_t *dr_host, const uint32_t *bs_host, const uint8_t *reg_host,
+                      const uint64_t *hist_host, uint64_t t, void *stream);
+
+/* Message of the calling thread's last error ("" if none).  Valid until the next call. */
+const char *vbdr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VBDR_H */

@@ -1,0 +1,569 @@
+// libvbdr.so: gfx950 kernels and C ABI of the VBDR sliding-window host
+// cardinality estimator (arXiv:1810.13132).  The ABI is documented in
+// include/vbdr.h.
+//
+// Device layout of a sketch (m BDRs, L = 33 - b LBP1 values):
+//   dr    L planes of mstride bytes: plane r-1 holds DR[r] of every BDR, so
+//         an advance streams each plane contiguously and a scan update of
+//         LBP1 r touches plane r-1 only (most updates hit the small planes
+//         r = 1, 2, 3, which stay cache resident);
+//   seen  (fast layout) L bit-planes of wstride words: bit p of plane r-1 is
+//         the bsLBP1 bit r of BDR p for the open slice (Alg. 7);
+//   reg   mstride bytes, the register of each BDR for the last closed window;
+//   hist  33 uint64, histogram of reg over the m BDRs;
+//   s1    g uint32, the virtual-index seeds s1[i] = H(i, 2^32, A0) (Alg. 3).
+// mstride is m rounded up to a multiple of 4096; padding BDRs are never
+// scanned (pidx < m), keep DR = 255 and register 0, and are not counted.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vbdr.h"
+#include "vbdr_device.h"
+
+using namespace vbdr;
+
+struct vbdr_sketch {
+  int device;
+  int n_cu;
+  uint64_t m;
+  uint32_t g, b, L, k;
+  int layout;
+  uint32_t A0, A1;
+  uint64_t t;
+  uint64_t mstride, wstride;
+  uint8_t* dr;
+  uint32_t* seen;
+  uint8_t* reg;
+  unsigned long long* hist;
+  uint32_t* s1;
+  uint64_t bytes;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define VBDR_HIP(call)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(VBDR_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define VBDR_LAUNCHED(name)                                                                    \
+  do {                                                                                         \
+    hipError_t e_ = hipGetLastError();                                                         \
+    if (e_ != hipSuccess) return fail(VBDR_EHIP, "launch of %s: %s", name, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr uint64_t kPad = 4096;          // BDR padding granule of a plane
+constexpr uint32_t kStageMaxG = 8192;    // s1 staged in LDS up to 32 KiB
+
+// ----------------------------------------------------------------- init
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_seeds(uint32_t* __restrict__ s1, uint32_t g, uint32_t A0) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < g) s1[i] = mm3(i, A0);
+}
+
+__global__ void k_hist_reset(unsigned long long* __restrict__ hist, unsigned long long first) {
+  if (threadIdx.x < kBins) hist[threadIdx.x] = threadIdx.x == 0 ? first : 0ull;
+}
+
+// ----------------------------------------------------------------- scan
+// One pair per lane per step, kScanUnroll independent loads in flight; the
+// pair stream is read once (non-temporal).  Fast layout: atomic OR of the
+// LBP1 bit (Alg. 7, bsLBP1[LBP1] = 1).  Small layout: byte store DR = 0
+// (Alg. 9, SetDR).  Both updates are idempotent, so pair order and repeats
+// do not matter (Sec. 4.2).  TEST: read first and skip updates already made.
+
+constexpr int kScanBlock = 256;
+constexpr int kScanUnroll = 4;
+
+template <bool FAST, bool STAGE, bool TEST>
+__global__ __launch_bounds__(kScanBlock) void k_scan(const u32x2* __restrict__ pairs, uint64_t n,
+                                                     const uint32_t* __restrict__ s1g, uint32_t g, uint32_t b,
+                                                     uint32_t A1, uint32_t m, uint8_t* __restrict__ dr,
+                                                     uint64_t mstride, uint32_t* __restrict__ seen, uint64_t wstride) {
+  extern __shared__ uint32_t s1_lds[];
+  const uint32_t* s1 = s1g;
+  if constexpr (STAGE) {
+    for (uint32_t i = threadIdx.x; i < g; i += kScanBlock) s1_lds[i] = s1g[i];
+    __syncthreads();
+    s1 = s1_lds;
+  }
+  const uint64_t step = (uint64_t)gridDim.x * kScanBlock * kScanUnroll;
+  for (uint64_t base = (uint64_t)blockIdx.x * kScanBlock * kScanUnroll + threadIdx.x; base < n; base += step) {
+    u32x2 p[kScanUnroll];
+#pragma unroll
+    for (int u = 0; u < kScanUnroll; ++u) {
+      const uint64_t i = base + (uint64_t)u * kScanBlock;
+      p[u] = i < n ? __builtin_nontemporal_load(pairs + i) : u32x2{0u, 0u};
+    }
+#pragma unroll
+    for (int u = 0; u < kScanUnroll; ++u) {
+      const uint64_t i = base + (uint64_t)u * kScanBlock;
+      if (i < n) {
+        uint32_t vidx, rho;
+        bip_map(p[u].y, A1, b, vidx, rho);
+        const uint32_t pidx = reduce_m(mm3(p[u].x, s1[vidx]), m);  // getPhyIdx (Alg. 3)
+        if constexpr (FAST) {
+          uint32_t* w = seen + (uint64_t)(rho - 1) * wstride + (pidx >> 5);
+          const uint32_t bit = 1u << (pidx & 31);
+          if (!TEST || !(*w & bit)) atomicOr(w, bit);
+        } else {
+          uint8_t* d = dr + (uint64_t)(rho - 1) * mstride + pidx;
+          if (!TEST || *d != 0) *d = 0;
+        }
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------- advance
+// One thread per 16 consecutive BDRs; planes visited from LBP1 = L down to 1.
+// Fast layout (Alg. 6): slide every DR, then zero the DR of the highest LBP1
+// whose bsLBP1 bit is set, and clear bsLBP1.  Small layout (Alg. 8): slide
+// every DR; the window's register is read before the slide.  Register of a
+// BDR: the largest LBP1 whose DR is active (Alg. 2), i.e. DR <= k-1 at the
+// moment the window is read.  Each block histograms its registers in LDS.
+
+constexpr int kAdvBlock = 256;
+constexpr int kAdvBpt = 16;
+static_assert(kPad % (kAdvBlock * kAdvBpt) == 0, "plane padding must cover whole advance blocks");
+
+template <bool FAST>
+__global__ __launch_bounds__(kAdvBlock) void k_advance(uint8_t* __restrict__ dr, uint64_t mstride,
+                                                       uint32_t* __restrict__ seen, uint64_t wstride,
+                                                       uint8_t* __restrict__ reg, uint64_t m, uint32_t L, uint32_t thr,
+                                                       unsigned long long* __restrict__ hist) {
+  __shared__ uint32_t lh[kAdvBlock / 64][kBins];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane < kBins) lh[wave][lane] = 0;
+  __syncthreads();
+  const uint64_t base = ((uint64_t)blockIdx.x * kAdvBlock + threadIdx.x) * kAdvBpt;
+  uint32_t regb[kAdvBpt];
+#pragma unroll
+  for (int j = 0; j < kAdvBpt; ++j) regb[j] = 0;
+  uint32_t found = 0, folded = 0;
+  for (int i = (int)L; i >= 1; --i) {
+    u32x4* pl = reinterpret_cast<u32x4*>(dr + (uint64_t)(i - 1) * mstride + base);
+    const u32x4 d = *pl;
+    uint32_t fold = 0;
+    if constexpr (FAST) {
+      uint32_t s = seen[(uint64_t)(i - 1) * wstride + (base >> 5)];
+      s = (s >> (base & 31)) & 0xFFFFu;
+      fold = s & ~folded;
+      folded |= s;
+    }
+    u32x4 nd;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t word = d[w];
+      uint32_t nword = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = w * 4 + e;
+        const uint32_t v = (word >> (8 * e)) & 0xFFu;
+        uint32_t nv = v + (v < kSat ? 1u : 0u);  // SlideDR, saturating
+        if (FAST && ((fold >> j) & 1u)) nv = 0;  // SetDR of the slice's LBP1
+        const bool act = FAST ? (nv <= thr) : (v <= thr);
+        if (act && !((found >> j) & 1u)) {
+          regb[j] = (uint32_t)i;
+          found |= 1u << j;
+        }
+        nword |= nv << (8 * e);
+      }
+      nd[w] = nword;
+    }
+    *pl = nd;
+  }
+  if constexpr (FAST) {
+    // The two threads sharing a bsLBP1 word are adjacent lanes of one wave
+    // and have both consumed it above; the even one clears it.
+    if ((base & 31) == 0)
+      for (uint32_t i = 0; i < L; ++i) seen[(uint64_t)i * wstride + (base >> 5)] = 0;
+  }
+  u32x4 rw;
+#pragma unroll
+  for (int w = 0; w < 4; ++w)
+    rw[w] = regb[4 * w] | (regb[4 * w + 1] << 8) | (regb[4 * w + 2] << 16) | (regb[4 * w + 3] << 24);
+  *reinterpret_cast<u32x4*>(reg + base) = rw;
+#pragma unroll
+  for (int j = 0; j < kAdvBpt; ++j)
+    if (base + j < m) atomicAdd(&lh[wave][regb[j]], 1u);
+  __syncthreads();
+  if (threadIdx.x < kBins) {
+    uint32_t s = 0;
+    for (int w = 0; w < kAdvBlock / 64; ++w) s += lh[w][threadIdx.x];
+    if (s) atomicAdd(hist + threadIdx.x, (unsigned long long)s);
+  }
+}
+
+// ------------------------------------------------------------- estimate
+// One wave per host: each lane hashes g/64 virtual indices (getPhyIdx,
+// Alg. 3), gathers their registers (Alg. 5) and accumulates the exact
+// harmonic sum U = sum 2^(32-R) and the zero count V; a wave reduction and an
+// FP64 epilogue give E_s, and with the pool estimate E_m the noise-removed
+// (m E_s - g E_m) / (m - g), clamped at 0.
+
+constexpr int kEstBlock = 256;
+constexpr int kEstWaves = kEstBlock / 64;
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t olo = __shfl_xor(lo, off), ohi = __shfl_xor(hi, off);
+    const uint64_t s = ((uint64_t)hi << 32 | lo) + ((uint64_t)ohi << 32 | olo);
+    lo = (uint32_t)s, hi = (uint32_t)(s >> 32);
+  }
+  return (uint64_t)hi << 32 | lo;
+}
+
+__device__ __forceinline__ double noise_removed(double Es, double Em, double m, double g) {
+#pragma clang fp contract(off)
+  return (m * Es - g * Em) / (m - g);
+}
+
+template <bool STAGE, bool EXTRA>
+__global__ __launch_bounds__(kEstBlock) void k_estimate(const uint32_t* __restrict__ hosts, uint64_t nh,
+                                                        const uint32_t* __restrict__ s1g, uint32_t g, uint32_t m,
+                                                        const uint8_t* __restrict__ reg,
+                                                        const unsigned long long* __restrict__ hist,
+                                                        float* __restrict__ out, double* __restrict__ raw,
+                                                        uint32_t* __restrict__ hout) {
+  extern __shared__ uint32_t s1_lds[];
+  __shared__ double em_sh;
+  __shared__ uint32_t lh[kEstWaves][kBins];
+  const uint32_t* s1 = s1g;
+  if constexpr (STAGE) {
+    for (uint32_t i = threadIdx.x; i < g; i += kEstBlock) s1_lds[i] = s1g[i];
+    s1 = s1_lds;
+  }
+  if (threadIdx.x == 0) {
+    uint64_t U = 0;
+    for (int r = 0; r < kBins; ++r) U += (uint64_t)hist[r] << (32 - r);
+    em_sh = hll_estimate(U, hist[0], (double)m);
+  }
+  __syncthreads();
+  const double Em = em_sh;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint64_t h = (uint64_t)blockIdx.x * kEstWaves + wave; h < nh; h += (uint64_t)gridDim.x * kEstWaves) {
+    const uint32_t aip = hosts[h];
+    if constexpr (EXTRA) {
+      if (lane < kBins) lh[wave][lane] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    uint64_t U = 0;
+    uint32_t V = 0;
+    for (uint32_t i = lane; i < g; i += 64) {
+      const uint32_t r = reg[reduce_m(mm3(aip, s1[i]), m)];
+      U += 1ull << (32 - r);
+      V += r == 0;
+      if constexpr (EXTRA) atomicAdd(&lh[wave][r], 1u);
+    }
+    U = wave_sum_u64(U);
+    V = (uint32_t)wave_sum_u64(V);
+    if (lane == 0) {
+      const double Es = hll_estimate(U, V, (double)g);
+      const double n = noise_removed(Es, Em, (double)m, (double)g);
+      out[h] = (float)(n > 0.0 ? n : 0.0);
+      if (EXTRA && raw) raw[h] = Es;
+    }
+    if constexpr (EXTRA) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (hout && lane < kBins) hout[h * kBins + lane] = lh[wave][lane];
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+// ------------------------------------------------------------- helpers
+
+int check_device(const vbdr_sketch* sk) {
+  int cur = -1;
+  VBDR_HIP(hipGetDevice(&cur));
+  if (cur != sk->device) return fail(VBDR_EINVAL, "sketch lives on device %d but device %d is current", sk->device, cur);
+  return VBDR_OK;
+}
+
+uint32_t grid_cap(const vbdr_sketch* sk, uint64_t want, uint32_t per_cu) {
+  const uint64_t cap = (uint64_t)sk->n_cu * per_cu;
+  if (want < 1) want = 1;
+  return (uint32_t)(want < cap ? want : cap);
+}
+
+uint64_t splitmix64_first(uint64_t state) {
+  uint64_t z = state + 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+int init_state(vbdr_sketch* sk, hipStream_t st) {
+  const uint32_t fill_grid = grid_cap(sk, (sk->L * sk->mstride / 4 + 255) / 256, 32);
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, reinterpret_cast<uint32_t*>(sk->dr),
+                     (uint64_t)sk->L * sk->mstride / 4, 0xFFFFFFFFu);  // InitDR: 255 in every byte
+  VBDR_LAUNCHED("k_fill_u32(dr)");
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, reinterpret_cast<uint32_t*>(sk->reg),
+                     sk->mstride / 4, 0u);
+  VBDR_LAUNCHED("k_fill_u32(reg)");
+  if (sk->seen) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, sk->seen, (uint64_t)sk->L * sk->wstride, 0u);
+    VBDR_LAUNCHED("k_fill_u32(seen)");
+  }
+  hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(64), 0, st, sk->hist, (unsigned long long)sk->m);
+  VBDR_LAUNCHED("k_hist_reset");
+  return VBDR_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+
+extern "C" {
+
+const char* vbdr_last_error(void) { return g_err.c_str(); }
+
+int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out) {
+  if (!out) return fail(VBDR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (g < 2 || g > 65536u || (g & (g - 1))) return fail(VBDR_EINVAL, "g=%u must be a power of two in [2, 65536]", g);
+  if (m <= g || m >= (1ull << 32)) return fail(VBDR_EINVAL, "m=%llu must satisfy g < m < 2^32", (unsigned long long)m);
+  if (k < 1 || k > 254) return fail(VBDR_EINVAL, "k=%u must be in [1, 254]", k);
+  if (layout != VBDR_LAYOUT_FAST && layout != VBDR_LAYOUT_SMALL) return fail(VBDR_EINVAL, "unknown layout %d", layout);
+  vbdr_sketch* sk = new (std::nothrow) vbdr_sketch();
+  if (!sk) return fail(VBDR_ENOMEM, "host allocation failed");
+  std::memset(sk, 0, sizeof(*sk));
+  int rc = VBDR_OK;
+  do {
+    if (hipGetDevice(&sk->device) != hipSuccess) { rc = fail(VBDR_EHIP, "hipGetDevice failed"); break; }
+    if (hipDeviceGetAttribute(&sk->n_cu, hipDeviceAttributeMultiprocessorCount, sk->device) != hipSuccess) {
+      rc = fail(VBDR_EHIP, "hipDeviceGetAttribute failed");
+      break;
+    }
+    sk->m = m, sk->g = g, sk->k = k, sk->layout = layout;
+    while ((1u << sk->b) < g) sk->b++;
+    sk->L = 33 - sk->b;
+    const uint64_t x = splitmix64_first(hash_seed);
+    sk->A0 = (uint32_t)x, sk->A1 = (uint32_t)(x >> 32);
+    sk->mstride = (m + kPad - 1) / kPad * kPad;
+    sk->wstride = sk->mstride / 32;
+    const uint64_t dr_bytes = (uint64_t)sk->L * sk->mstride;
+    const uint64_t seen_bytes = layout == VBDR_LAYOUT_FAST ? (uint64_t)sk->L * sk->wstride * 4 : 0;
+    if (hipMalloc(&sk->dr, dr_bytes) != hipSuccess || hipMalloc(&sk->reg, sk->mstride) != hipSuccess ||
+        hipMalloc(&sk->hist, 64 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&sk->s1, (uint64_t)g * 4) != hipSuccess ||
+        (seen_bytes && hipMalloc(&sk->seen, seen_bytes) != hipSuccess)) {
+      (void)hipGetLastError();
+      rc = fail(VBDR_ENOMEM, "device allocation of %llu bytes failed",
+                (unsigned long long)(dr_bytes + seen_bytes + sk->mstride));
+      break;
+    }
+    sk->bytes = dr_bytes + seen_bytes + sk->mstride + 64 * sizeof(unsigned long long) + (uint64_t)g * 4;
+    hipStream_t st = nullptr;
+    if ((rc = init_state(sk, st)) != VBDR_OK) break;
+    hipLaunchKernelGGL(k_seeds, dim3((g + 255) / 256), dim3(256), 0, st, sk->s1, g, sk->A0);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(VBDR_EHIP, "sketch initialisation failed");
+      break;
+    }
+  } while (0);
+  if (rc != VBDR_OK) {
+    vbdr_sketch_destroy(sk);
+    return rc;
+  }
+  *out = sk;
+  return VBDR_OK;
+}
+
+int vbdr_sketch_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, vbdr_sketch** out) {
+  return vbdr_sketch_create_layout(m, g, k, hash_seed, VBDR_LAYOUT_FAST, out);
+}
+
+void vbdr_sketch_destroy(vbdr_sketch* sk) {
+  if (!sk) return;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (prev != sk->device) (void)hipSetDevice(sk->device);
+  (void)hipDeviceSynchronize();
+  if (sk->dr) (void)hipFree(sk->dr);
+  if (sk->seen) (void)hipFree(sk->seen);
+  if (sk->reg) (void)hipFree(sk->reg);
+  if (sk->hist) (void)hipFree(sk->hist);
+  if (sk->s1) (void)hipFree(sk->s1);
+  if (prev >= 0 && prev != sk->device) (void)hipSetDevice(prev);
+  delete sk;
+}
+
+int vbdr_sketch_info(const vbdr_sketch* sk, vbdr_info* out) {
+  if (!sk || !out) return fail(VBDR_EINVAL, "NULL argument");
+  out->m = sk->m, out->g = sk->g, out->b = sk->b, out->L = sk->L, out->k = sk->k;
+  out->layout = sk->layout, out->A0 = sk->A0, out->A1 = sk->A1, out->t = sk->t;
+  out->state_bytes = sk->bytes;
+  return VBDR_OK;
+}
+
+int vbdr_scan_slice(vbdr_sketch* sk, const uint32_t* pairs_dev, uint64_t n, void* stream) {
+  if (!sk) return fail(VBDR_EINVAL, "sketch is NULL");
+  if (n == 0) return VBDR_OK;
+  if (!pairs_dev) return fail(VBDR_EINVAL, "pairs_dev is NULL");
+  if (reinterpret_cast<uintptr_t>(pairs_dev) & 7u) return fail(VBDR_EINVAL, "pairs_dev must be 8-byte aligned");
+  if (n >= (1ull << 40)) return fail(VBDR_EINVAL, "n=%llu too large", (unsigned long long)n);
+  if (int rc = check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool stage = sk->g <= kStageMaxG;
+  const size_t lds = stage ? (size_t)sk->g * 4 : 0;
+  const uint32_t grid = grid_cap(sk, (n + kScanBlock * kScanUnroll - 1) / (kScanBlock * kScanUnroll), 16);
+  const u32x2* p = reinterpret_cast<const u32x2*>(pairs_dev);
+  const uint32_t m32 = (uint32_t)sk->m;
+  if (sk->layout == VBDR_LAYOUT_FAST) {
+    auto kern = stage ? k_scan<true, true, false> : k_scan<true, false, false>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kScanBlock), lds, st, p, n, sk->s1, sk->g, sk->b, sk->A1, m32, sk->dr,
+                       sk->mstride, sk->seen, sk->wstride);
+  } else {
+    auto kern = stage ? k_scan<false, true, false> : k_scan<false, false, false>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kScanBlock), lds, st, p, n, sk->s1, sk->g, sk->b, sk->A1, m32, sk->dr,
+                       sk->mstride, sk->seen, sk->wstride);
+  }
+  VBDR_LAUNCHED("k_scan");
+  return VBDR_OK;
+}
+
+int vbdr_advance_slice(vbdr_sketch* sk, void* stream) {
+  if (!sk) return fail(VBDR_EINVAL, "sketch is NULL");
+  if (int rc = check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(64), 0, st, sk->hist, 0ull);
+  VBDR_LAUNCHED("k_hist_reset");
+  const uint32_t grid = (uint32_t)(sk->mstride / (kAdvBlock * kAdvBpt));
+  auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_advance<true> : k_advance<false>;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kAdvBlock), 0, st, sk->dr, sk->mstride, sk->seen, sk->wstride, sk->reg,
+                     sk->m, sk->L, sk->k - 1, sk->hist);
+  VBDR_LAUNCHED("k_advance");
+  sk->t++;
+  return VBDR_OK;
+}
+
+int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, float* out_dev, double* raw_es_dev,
+                     uint32_t* hist_dev, void* stream) {
+  if (!sk) return fail(VBDR_EINVAL, "sketch is NULL");
+  if (n_hosts == 0) return VBDR_OK;
+  if (!hosts_dev || !out_dev) return fail(VBDR_EINVAL, "hosts_dev and out_dev must not be NULL");
+  if (n_hosts >= (1ull << 40)) return fail(VBDR_EINVAL, "n_hosts too large");
+  if (int rc = check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool stage = sk->g <= kStageMaxG;
+  const bool extra = raw_es_dev || hist_dev;
+  const size_t lds = stage ? (size_t)sk->g * 4 : 0;
+  const uint32_t grid = grid_cap(sk, (n_hosts + kEstWaves - 1) / kEstWaves, 16);
+  auto kern = stage ? (extra ? k_estimate<true, true> : k_estimate<true, false>)
+                    : (extra ? k_estimate<false, true> : k_estimate<false, false>);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kEstBlock), lds, st, hosts_dev, n_hosts, sk->s1, sk->g, (uint32_t)sk->m,
+                     sk->reg, sk->hist, out_dev, raw_es_dev, hist_dev);
+  VBDR_LAUNCHED("k_estimate");
+  return VBDR_OK;
+}
+
+int vbdr_estimate(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, float* out_dev, void* stream) {
+  return vbdr_estimate_ex(sk, hosts_dev, n_hosts, out_dev, nullptr, nullptr, stream);
+}
+
+int vbdr_export_state(vbdr_sketch* sk, uint8_t* dr_host, uint32_t* bs_host, uint8_t* reg_host, uint64_t* hist_host,
+                      void* stream) {
+  if (!sk) return fail(VBDR_EINVAL, "sketch is NULL");
+  if (int rc = check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  VBDR_HIP(hipStreamSynchronize(st));
+  const uint64_t m = sk->m, L = sk->L;
+  if (dr_host) {
+    std::vector<uint8_t> plane(m);
+    for (uint64_t i = 0; i < L; ++i) {
+      VBDR_HIP(hipMemcpy(plane.data(), sk->dr + i * sk->mstride, m, hipMemcpyDeviceToHost));
+      for (uint64_t p = 0; p < m; ++p) dr_host[p * L + i] = plane[p];
+    }
+  }
+  if (bs_host) {
+    std::memset(bs_host, 0, m * sizeof(uint32_t));
+    if (sk->seen) {
+      std::vector<uint32_t> plane(sk->wstride);
+      for (uint64_t i = 0; i < L; ++i) {
+        VBDR_HIP(hipMemcpy(plane.data(), sk->seen + i * sk->wstride, sk->wstride * 4, hipMemcpyDeviceToHost));
+        for (uint64_t p = 0; p < m; ++p) bs_host[p] |= ((plane[p >> 5] >> (p & 31)) & 1u) << i;
+      }
+    }
+  }
+  if (reg_host) VBDR_HIP(hipMemcpy(reg_host, sk->reg, m, hipMemcpyDeviceToHost));
+  if (hist_host) VBDR_HIP(hipMemcpy(hist_host, sk->hist, kBins * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  return VBDR_OK;
+}
+
+int vbdr_import_state(vbdr_sketch* sk, const uint8_t* dr_host, const uint32_t* bs_host, const uint8_t* reg_host,
+                      const uint64_t* hist_host, uint64_t t, void* stream) {
+  if (!sk) return fail(VBDR_EINVAL, "sketch is NULL");
+  if (!dr_host || !reg_host || !hist_host) return fail(VBDR_EINVAL, "dr_host, reg_host and hist_host are required");
+  if (bs_host && !sk->seen) {
+    for (uint64_t p = 0; p < sk->m; ++p)
+      if (bs_host[p]) return fail(VBDR_EINVAL, "small-layout sketch cannot hold bsLBP1 bits");
+  }
+  uint64_t total = 0;
+  for (int r = 0; r < kBins; ++r) total += hist_host[r];
+  if (total != sk->m) return fail(VBDR_EINVAL, "histogram does not sum to m");
+  const uint64_t m = sk->m, L = sk->L;
+  for (uint64_t p = 0; p < m; ++p)
+    if (reg_host[p] > L) return fail(VBDR_EINVAL, "register %u of BDR %llu exceeds L", reg_host[p], (unsigned long long)p);
+  if (bs_host)
+    for (uint64_t p = 0; p < m; ++p)
+      if (L < 32 && (bs_host[p] >> L)) return fail(VBDR_EINVAL, "bsLBP1 of BDR %llu has bits above L", (unsigned long long)p);
+  if (int rc = check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  VBDR_HIP(hipStreamSynchronize(st));
+  {
+    std::vector<uint8_t> plane(sk->mstride, (uint8_t)kSat);
+    for (uint64_t i = 0; i < L; ++i) {
+      for (uint64_t p = 0; p < m; ++p) plane[p] = dr_host[p * L + i];
+      VBDR_HIP(hipMemcpy(sk->dr + i * sk->mstride, plane.data(), sk->mstride, hipMemcpyHostToDevice));
+    }
+  }
+  if (sk->seen) {
+    std::vector<uint32_t> plane(sk->wstride);
+    for (uint64_t i = 0; i < L; ++i) {
+      std::fill(plane.begin(), plane.end(), 0u);
+      if (bs_host)
+        for (uint64_t p = 0; p < m; ++p) plane[p >> 5] |= ((bs_host[p] >> i) & 1u) << (p & 31);
+      VBDR_HIP(hipMemcpy(sk->seen + i * sk->wstride, plane.data(), sk->wstride * 4, hipMemcpyHostToDevice));
+    }
+  }
+  {
+    std::vector<uint8_t> r(sk->mstride, 0);
+    std::memcpy(r.data(), reg_host, m);
+    VBDR_HIP(hipMemcpy(sk->reg, r.data(), sk->mstride, hipMemcpyHostToDevice));
+  }
+  VBDR_HIP(hipMemcpy(sk->hist, hist_host, kBins * sizeof(uint64_t), hipMemcpyHostToDevice));
+  sk->t = t;
+  return VBDR_OK;
+}
+
+}  // extern "C"

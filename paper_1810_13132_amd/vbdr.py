@@ -1,0 +1,186 @@
+"""Python binding of libvbdr.so (argument marshalling only).
+
+Every step of the hot path runs in the library's HIP kernels; torch provides
+device memory and the current HIP stream.  The library must be built
+(``python -m paper_1810_13132_amd.build``); there is no fallback.
+
+    sk = Sketch(m=1 << 18, g=256, k=4, hash_seed=0, layout="fast")
+    sk.scan_slice(pairs)        # (n, 2) uint32/int32 CUDA tensor of (aip, bip)
+    sk.advance_slice()
+    est = sk.estimate(hosts)    # (h,) float32 CUDA tensor
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime libvbdr.so then binds to
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libvbdr.so")
+
+LAYOUTS = {"fast": 0, "small": 1}
+NBINS = 33
+STATUS = {0: "VBDR_OK", -1: "VBDR_EINVAL", -2: "VBDR_ENOMEM", -3: "VBDR_EHIP", -4: "VBDR_ESTATE"}
+
+
+class VbdrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Info(C.Structure):
+    _fields_ = [("m", C.c_uint64), ("g", C.c_uint32), ("b", C.c_uint32), ("L", C.c_uint32), ("k", C.c_uint32),
+                ("layout", C.c_int32), ("A0", C.c_uint32), ("A1", C.c_uint32), ("t", C.c_uint64),
+                ("state_bytes", C.c_uint64)]
+
+
+EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_destroy", "vbdr_scan_slice",
+           "vbdr_advance_slice", "vbdr_estimate", "vbdr_estimate_ex", "vbdr_sketch_info", "vbdr_export_state",
+           "vbdr_import_state", "vbdr_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libvbdr.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1810_13132_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+        L.vbdr_sketch_create.argtypes = [u64, u32, u32, u64, C.POINTER(vp)]
+        L.vbdr_sketch_create_layout.argtypes = [u64, u32, u32, u64, i32, C.POINTER(vp)]
+        L.vbdr_sketch_destroy.argtypes = [vp]
+        L.vbdr_sketch_destroy.restype = None
+        L.vbdr_scan_slice.argtypes = [vp, vp, u64, vp]
+        L.vbdr_advance_slice.argtypes = [vp, vp]
+        L.vbdr_estimate.argtypes = [vp, vp, u64, vp, vp]
+        L.vbdr_estimate_ex.argtypes = [vp, vp, u64, vp, vp, vp, vp]
+        L.vbdr_sketch_info.argtypes = [vp, C.POINTER(Info)]
+        L.vbdr_export_state.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.vbdr_import_state.argtypes = [vp, vp, vp, vp, vp, u64, vp]
+        L.vbdr_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("vbdr_sketch_destroy", "vbdr_last_error"):
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise VbdrError(rc, lib().vbdr_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtypes, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+_U32 = (torch.int32, torch.uint32)
+
+
+class Sketch:
+    """A VBDR sketch living on the current device."""
+
+    def __init__(self, m: int, g: int, k: int, hash_seed: int = 0, layout: str = "fast"):
+        h = C.c_void_p()
+        _check(lib().vbdr_sketch_create_layout(m, g, k, hash_seed, LAYOUTS[layout], C.byref(h)))
+        self._h = h
+        self.layout = layout
+        i = self.info()
+        self.m, self.g, self.b, self.L, self.k = i.m, i.g, i.b, i.L, i.k
+        self.A0, self.A1 = i.A0, i.A1
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and h.value:
+            lib().vbdr_sketch_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> Info:
+        out = Info()
+        _check(lib().vbdr_sketch_info(self._h, C.byref(out)))
+        return out
+
+    @property
+    def t(self) -> int:
+        return int(self.info().t)
+
+    def scan_slice(self, pairs: torch.Tensor, stream=None):
+        n = pairs.numel() // 2
+        if pairs.numel() != 2 * n:
+            raise ValueError("pairs must hold an even number of uint32")
+        ptr = _dev_ptr(pairs, _U32, "pairs") if n else C.c_void_p()
+        _check(lib().vbdr_scan_slice(self._h, ptr, n, _stream(stream)))
+
+    def advance_slice(self, stream=None):
+        _check(lib().vbdr_advance_slice(self._h, _stream(stream)))
+
+    def estimate(self, hosts: torch.Tensor, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        n = hosts.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=hosts.device)
+        if n:
+            _check(lib().vbdr_estimate(self._h, _dev_ptr(hosts, _U32, "hosts"), n,
+                                       _dev_ptr(out, (torch.float32,), "out"), _stream(stream)))
+        return out
+
+    def estimate_ex(self, hosts: torch.Tensor, stream=None):
+        """(estimate float32, raw E_s float64, register histogram (n, 33) int32)."""
+        n = hosts.numel()
+        out = torch.empty(n, dtype=torch.float32, device=hosts.device)
+        raw = torch.empty(n, dtype=torch.float64, device=hosts.device)
+        hist = torch.empty((n, NBINS), dtype=torch.int32, device=hosts.device)
+        if n:
+            _check(lib().vbdr_estimate_ex(self._h, _dev_ptr(hosts, _U32, "hosts"), n,
+                                          _dev_ptr(out, (torch.float32,), "out"),
+                                          _dev_ptr(raw, (torch.float64,), "raw"),
+                                          _dev_ptr(hist, (torch.int32,), "hist"), _stream(stream)))
+        return out, raw, hist
+
+    def state(self, stream=None) -> dict:
+        """Canonical state as numpy arrays: dr (m, L) uint8, bs (m,) uint32, reg (m,) uint8, hist (33,) uint64."""
+        m, L = self.m, self.L
+        dr = np.empty((m, L), dtype=np.uint8)
+        bs = np.empty(m, dtype=np.uint32)
+        reg = np.empty(m, dtype=np.uint8)
+        hist = np.empty(NBINS, dtype=np.uint64)
+        _check(lib().vbdr_export_state(self._h, dr.ctypes.data, bs.ctypes.data, reg.ctypes.data, hist.ctypes.data,
+                                       _stream(stream)))
+        return {"dr": dr, "bs": bs, "reg": reg, "hist": hist, "t": self.t}
+
+    def load_state(self, state: dict, stream=None):
+        dr = np.ascontiguousarray(state["dr"], dtype=np.uint8)
+        reg = np.ascontiguousarray(state["reg"], dtype=np.uint8)
+        hist = np.ascontiguousarray(state["hist"], dtype=np.uint64)
+        bs = state.get("bs")
+        bs = None if bs is None else np.ascontiguousarray(bs, dtype=np.uint32)
+        if dr.shape != (self.m, self.L) or reg.shape != (self.m,) or hist.shape != (NBINS,):
+            raise ValueError("state shapes do not match the sketch")
+        _check(lib().vbdr_import_state(self._h, dr.ctypes.data, None if bs is None else bs.ctypes.data,
+                                       reg.ctypes.data, hist.ctypes.data, int(state["t"]), _stream(stream)))
+
+
+def to_device_u32(a: np.ndarray, device="cuda") -> torch.Tensor:
+    """Copy a uint32 numpy array to the device (as int32 storage, same bits)."""
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    return torch.from_numpy(a.view(np.int32)).to(device)

@@ -1,0 +1,201 @@
+"""HIP path vs CPU oracle, element by element, through the C ABI.
+
+BDR state (every DR, the open slice's bsLBP1, every register, the pool
+histogram) must match bit for bit after every scan and every advance;
+register histograms per host bit for bit; FP32 estimates within 1e-6
+relative of the FP64 oracle, plus an absolute floor for the cancellation in
+(m E_s - g E_m) / (m - g): the two sides run the same FP64 operations in the
+same order and differ only in the last bit of log(), so the floor is a few
+FP64 ulps of the cancelled terms.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+LAYOUT_CODE = {"fast": 1, "small": 2}  # oracle layout codes
+
+
+@pytest.fixture(scope="module")
+def V():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_13132_amd import vbdr
+    vbdr.lib()
+    return vbdr
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def _dev(V, a):
+    return V.to_device_u32(a)
+
+
+def _random_slices(seed, n_slices, max_pairs, n_aip, n_bip, empty_prob=0.1):
+    rng = np.random.default_rng(seed)
+    aips = rng.integers(0, 2**32, n_aip, dtype=np.uint64).astype(np.uint32)
+    bips = rng.integers(0, 2**32, n_bip, dtype=np.uint64).astype(np.uint32)
+    out = []
+    for _ in range(n_slices):
+        n = 0 if rng.random() < empty_prob else int(rng.integers(1, max_pairs + 1))
+        out.append(np.stack([aips[rng.integers(0, n_aip, n)], bips[rng.integers(0, n_bip, n)]], 1)
+                   .astype(np.uint32).reshape(-1, 2))
+    return aips, out
+
+
+def assert_state_equal(gs, os_, layout, where):
+    assert gs["t"] == os_["t"], where
+    assert np.array_equal(gs["dr"], os_["dr"]), f"DR mismatch {where}: {np.argwhere(gs['dr'] != os_['dr'])[:5]}"
+    if layout == "fast":
+        assert np.array_equal(gs["bs"], os_["bs"]), f"bsLBP1 mismatch {where}"
+    else:
+        assert not gs["bs"].any()
+    assert np.array_equal(gs["reg"], os_["reg"]), f"register mismatch {where}"
+    assert np.array_equal(gs["hist"], os_["hist"]), f"pool histogram mismatch {where}"
+
+
+def assert_estimates_close(V, O, sk, osk, hosts):
+    hd = _dev(V, hosts)
+    out, raw, hist = sk.estimate_ex(hd)
+    plain = sk.estimate(hd)
+    torch.cuda.synchronize()
+    out, raw, hist, plain = out.cpu().numpy(), raw.cpu().numpy(), hist.cpu().numpy(), plain.cpu().numpy()
+    ref, ref_raw, ref_hist = osk.estimate(hosts, with_raw=True, with_hist=True)
+    assert np.array_equal(hist.astype(np.uint32), ref_hist), "per-host register histogram mismatch"
+    assert np.array_equal(out, plain), "estimate and estimate_ex disagree"
+    np.testing.assert_allclose(raw, ref_raw, rtol=1e-13, atol=0)
+    em = O.hll_from_hist(osk.state()["hist"], osk.m)
+    m, g = float(osk.m), float(osk.g)
+    floor = 1e-12 * (m * np.abs(ref_raw) + g * em) / (m - g)
+    err = np.abs(out.astype(np.float64) - ref.astype(np.float64))
+    bad = err > 1e-6 * np.abs(ref.astype(np.float64)) + floor
+    assert not bad.any(), f"estimates off at {np.nonzero(bad)[0][:5]}: gpu {out[bad][:5]} ref {ref[bad][:5]}"
+    return ref
+
+
+def run_parity(V, O, layout, m, g, k, seed, slices, hosts, split=1):
+    sk = V.Sketch(m, g, k, seed, layout)
+    osk = O.Sketch(m, g, k, seed, LAYOUT_CODE[layout])
+    for t, pairs in enumerate(slices):
+        pd = _dev(V, pairs.reshape(-1))
+        n = len(pairs)
+        cuts = np.linspace(0, n, split + 1).astype(int)
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            sk.scan_slice(pd[2 * a: 2 * b])
+        osk.scan(pairs)
+        assert_state_equal(sk.state(), osk.state(), layout, f"after scan of slice {t}")
+        sk.advance_slice()
+        osk.advance()
+        assert_state_equal(sk.state(), osk.state(), layout, f"after advance of slice {t}")
+        if len(hosts):
+            assert_estimates_close(V, O, sk, osk, hosts)
+    return sk, osk
+
+
+@pytest.mark.parametrize("layout", ["fast", "small"])
+@pytest.mark.parametrize("m,g,k,seed", [
+    (3 * 4096 + 123, 64, 3, 1),      # ragged pool, several advance tiles
+    (5000, 2, 1, 2),                 # b = 1: L = 32, discrete window
+    (70001, 65536, 7, 3),            # g above the LDS-staged seed table
+    (4097, 16, 254, 4),              # largest window
+])
+def test_parity_random_streams(V, O, layout, m, g, k, seed):
+    aips, slices = _random_slices(seed, 9, 6000, 40, 3000)
+    hosts = np.concatenate([aips[:33], np.array([12345, 0, 0xFFFFFFFF], np.uint32)])
+    run_parity(V, O, layout, m, g, k, seed, slices, hosts, split=3)
+
+
+@pytest.mark.parametrize("layout", ["fast", "small"])
+def test_parity_saturation_long_history(V, O, layout):
+    """300 slices: DRs climb to 255 and stay (no wrap)."""
+    aips, slices = _random_slices(7, 300, 20, 3, 50, empty_prob=0.8)
+    sk = V.Sketch(4096 + 5, 8, 5, 9, layout)
+    osk = O.Sketch(4096 + 5, 8, 5, 9, LAYOUT_CODE[layout])
+    for pairs in slices:
+        if len(pairs):
+            sk.scan_slice(_dev(V, pairs.reshape(-1)))
+        osk.scan(pairs)
+        sk.advance_slice()
+        osk.advance()
+    gs, os_ = sk.state(), osk.state()
+    assert_state_equal(gs, os_, layout, "after 300 slices")
+    assert (gs["dr"] == 255).any()
+    assert_estimates_close(V, O, sk, osk, aips)
+
+
+def test_empty_inputs(V, O):
+    sk = V.Sketch(10000, 32, 3, 5, "fast")
+    empty = torch.empty(0, dtype=torch.int32, device="cuda")
+    sk.scan_slice(empty)
+    out = sk.estimate(empty)
+    assert out.numel() == 0
+    hosts = _dev(V, np.arange(100, dtype=np.uint32))
+    assert not sk.estimate(hosts).cpu().numpy().any()  # before any advance
+    sk.advance_slice()
+    sk.advance_slice()
+    assert not sk.estimate(hosts).cpu().numpy().any()
+    s = sk.state()
+    assert s["t"] == 2 and s["hist"][0] == 10000 and (s["dr"] == 255).all() and not s["reg"].any()
+
+
+@pytest.mark.parametrize("layout", ["fast", "small"])
+def test_parity_tiny_workload(V, O, layout):
+    """The tiny workload at its full size: 2^12 hosts, 2^20 pairs per slice,
+    12 slices, m = 2^18, g = 256, k = 4; every host estimated each slice."""
+    from paper_1810_13132_amd import synth
+    w = synth.TINY
+    st = synth.Stream(w)
+    sk = V.Sketch(w.m, w.g, w.k, w.seed, layout)
+    osk = O.Sketch(w.m, w.g, w.k, w.seed, LAYOUT_CODE[layout])
+    hosts = st.aip
+    for t in range(w.slices):
+        pairs = st.slice(t)
+        sk.scan_slice(_dev(V, pairs.reshape(-1)))
+        osk.scan(pairs)
+        sk.advance_slice()
+        osk.advance()
+        if t in (0, 3, w.slices - 1):
+            assert_state_equal(sk.state(), osk.state(), layout, f"slice {t}")
+        assert_estimates_close(V, O, sk, osk, hosts)
+
+
+def test_resume_from_exported_state(V, O):
+    """Export after 5 slices, import into a fresh sketch, continue: identical
+    to an uninterrupted run."""
+    aips, slices = _random_slices(11, 10, 3000, 30, 2000)
+    m, g, k = 9000, 32, 4
+    a = V.Sketch(m, g, k, 21, "fast")
+    for i, pairs in enumerate(slices):
+        if len(pairs):
+            a.scan_slice(_dev(V, pairs.reshape(-1)))
+        if i == 5:
+            mid = a.state()  # open slice with bsLBP1 bits set
+        a.advance_slice()
+    b = V.Sketch(m, g, k, 21, "fast")
+    b.load_state(mid)
+    assert_state_equal(b.state(), mid, "fast", "after import")
+    b.advance_slice()
+    for pairs in slices[6:]:
+        if len(pairs):
+            b.scan_slice(_dev(V, pairs.reshape(-1)))
+        b.advance_slice()
+    assert_state_equal(b.state(), a.state(), "fast", "resumed vs continuous")
+
+
+def test_bad_arguments_on_device(V):
+    sk = V.Sketch(5000, 16, 3, 1, "small")
+    pairs = torch.zeros(8, dtype=torch.int32, device="cuda")
+    with pytest.raises(V.VbdrError):
+        sk.scan_slice(pairs[1:7])  # misaligned pointer
+    with pytest.raises(ValueError):
+        sk.scan_slice(pairs.cpu())
+    with pytest.raises(V.VbdrError):
+        sk.load_state({"dr": np.zeros((5000, sk.L), np.uint8), "reg": np.zeros(5000, np.uint8),
+                       "hist": np.zeros(33, np.uint64), "t": 0})  # histogram does not sum to m
