@@ -1,0 +1,217 @@
+#!/usr/bin/env python
+"""Throughput of the VBDR per-slice hot path on one MI355X.
+
+One step = one time slice of the line-rate workload: scan its 2^26 (aip, bip)
+pairs into the BDR pool (m = 2^26, g = 1024), advance the window (k = 60),
+and estimate every host active in the window (of 2^20 hosts).  Pairs and
+host lists are resident in HBM before timing starts.
+
+    python bench.py [--steps K] [--warmup W] [--layout small|fast]
+
+Prints one JSON line.  value = IP pairs per second through whole steps.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "IP pairs/s scanned + hosts estimated/s at 1 GPU; learned vs plain RMS rel. error"
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
+CSRC = os.path.join(ROOT, "paper_1810_13132_amd", "csrc")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kind, w, layout, L, n_hosts):
+    """Bytes a launch must move at minimum (per unit x units)."""
+    if kind == "scan":  # pair read + one state update (fast: 4 B word read-modify-write; small: 1 B store)
+        return w.pairs_per_slice * (16 if layout == "fast" else 9)
+    if kind == "advance":  # every DR read and written, register written; fast: bsLBP1 bits read and cleared
+        per = 2 * L + 1 + (2 * L / 8 if layout == "fast" else 0)
+        return w.m * per
+    if kind == "estimate":  # g register gathers + host id + estimate
+        return n_hosts * (w.g + 8)
+    raise ValueError(kind)
+
+
+def traffic_from_counters(kernel_name, n_launch_units):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs,
+    if they were taken on the current kernel sources; else None."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("src_sha") != kernel_source_hash():
+        return None
+    k = c.get("kernels", {}).get(kernel_name)
+    if not k:
+        return None
+    return (k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"]) * 1024.0
+
+
+def cpu_baseline(w, layout, slice0, hosts_sample, n_active):
+    """Time the CPU oracle (single thread, as it stands) on a bounded sample."""
+    import numpy as np
+    from oracle import oracle
+    code = oracle.GFAST if layout == "fast" else oracle.GSMALL
+    S = min(len(slice0), 1 << 22)
+    t0 = time.perf_counter()
+    osk = oracle.Sketch(w.m, w.g, w.k, w.seed, code)
+    t_create = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    osk.scan(slice0[:S])
+    t_scan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    osk.advance()
+    t_adv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    osk.estimate(hosts_sample)
+    t_est = time.perf_counter() - t0
+    step = t_scan * (w.pairs_per_slice / S) + t_adv + t_est * (n_active / len(hosts_sample))
+    del osk
+    return {"value": w.pairs_per_slice / step, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"one slice: scan of the first {S} of {w.pairs_per_slice} pairs, one full advance of "
+                      f"{w.m} BDRs, estimate of {len(hosts_sample)} of {n_active} active hosts; scaled to a "
+                      f"whole step (scan x{w.pairs_per_slice // S}, estimate x{n_active / len(hosts_sample):.0f})",
+            "seconds": {"create": round(t_create, 3), "scan": round(t_scan, 3), "advance": round(t_adv, 3),
+                        "estimate": round(t_est, 3)}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--layout", default="small", choices=["small", "fast"])
+    ap.add_argument("--workload", default="line_rate", choices=["line_rate", "tiny"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1810_13132_amd import synth, vbdr
+
+    w = synth.LINE_RATE if args.workload == "line_rate" else synth.TINY
+    K, W = args.steps, args.warmup
+    n_slices = W + K
+    if n_slices > w.slices:
+        raise SystemExit(f"at most {w.slices} slices in this workload")
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+
+    # ---- inputs: generated on the host, resident in HBM before timing
+    st = synth.Stream(w)
+    hosts_all = st.aip
+    slices_dev, active_dev, n_active = [], [], []
+    window = []
+    buf = np.empty((w.pairs_per_slice, 2), dtype=np.uint32)
+    slice0 = None
+    t0 = time.time()
+    for t in range(n_slices):
+        counts = np.zeros(w.hosts, dtype=np.uint32)
+        st.slice(t, host_pairs=counts, out=buf)
+        if t == W:
+            slice0 = buf.copy() if not args.no_cpu_baseline else None
+        slices_dev.append(vbdr.to_device_u32(buf.reshape(-1), dev))
+        window.append(counts > 0)
+        window = window[-w.k:]
+        act = np.nonzero(np.logical_or.reduce(window))[0]
+        active_dev.append(vbdr.to_device_u32(hosts_all[act], dev))
+        n_active.append(len(act))
+        log(f"slice {t}: generated and copied ({time.time() - t0:.1f}s), {len(act)} active hosts")
+    outs = [torch.empty(n, dtype=torch.float32, device=dev) for n in n_active]
+
+    sk = vbdr.Sketch(w.m, w.g, w.k, w.seed, args.layout)
+    L = sk.L
+
+    def step(i):
+        sk.scan_slice(slices_dev[i])
+        sk.advance_slice()
+        sk.estimate(active_dev[i], outs[i])
+
+    for i in range(W):
+        step(i)
+    torch.cuda.synchronize()
+    log(f"warmup done ({W} steps)")
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for j in range(K):
+        i = W + j
+        e = ev[j]
+        e[0].record()
+        sk.scan_slice(slices_dev[i])
+        e[1].record()
+        sk.advance_slice()
+        e[2].record()
+        sk.estimate(active_dev[i], outs[i])
+        e[3].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    log(f"timed {K} steps in {elapsed:.3f}s")
+
+    kms = {"scan": [], "advance": [], "estimate": []}
+    for e in ev:
+        kms["scan"].append(e[0].elapsed_time(e[1]))
+        kms["advance"].append(e[1].elapsed_time(e[2]))
+        kms["estimate"].append(e[2].elapsed_time(e[3]))
+    avg = {k: float(np.mean(v)) for k, v in kms.items()}
+    timed_active = n_active[W:]
+    ms_per_step = elapsed * 1e3 / K
+    value = w.pairs_per_slice * K / elapsed
+
+    dom = max(avg, key=avg.get)
+    units = float(np.mean(timed_active))
+    alg = algorithmic_bytes(dom, w, args.layout, L, units)
+    achieved = alg / (avg[dom] * 1e-3) / 1e9
+    kernel_names = {"scan": "k_scan", "advance": "k_advance", "estimate": "k_estimate"}
+    traffic = traffic_from_counters(f"{kernel_names[dom]}:{args.layout}:{w.name}", units)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel_names[dom],
+                "algorithmic_bytes_per_launch": alg}
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": w.name, "pairs_per_slice": w.pairs_per_slice, "hosts": w.hosts, "m": w.m,
+                   "g": w.g, "k": w.k, "layout": args.layout, "active_hosts_per_step": int(units)},
+        "hosts_per_s": float(np.sum(timed_active) / (np.sum(kms["estimate"]) * 1e-3)),
+        "scan_pairs_per_s": w.pairs_per_slice / (avg["scan"] * 1e-3),
+        "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(0)
+        act_last = hosts_all[np.nonzero(np.logical_or.reduce(window))[0]]
+        sample = rng.choice(act_last, size=min(2048, len(act_last)), replace=False)
+        log("timing the CPU oracle on a sample")
+        res["cpu_baseline"] = cpu_baseline(w, args.layout, slice0, sample, int(units))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -133,6 +133,23 @@ int vbdr_estimate_ex(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_host
 int vbdr_sketch_info(const vbdr_sketch *sk, vbdr_info *out);
 
 /*
+ * Launch shape and kernel variant of a sketch's hot-path calls.  None of
+ * these changes any result, only speed.  Zero fields mean "default".
+ *   scan_test_first    1: the scan reads the bit or DR first and skips the
+ *                      update when it is already made; 2: always update
+ *                      (default: the variant measured faster for the layout);
+ *   scan_blocks_per_cu workgroups per compute unit of the scan (1..64);
+ *   est_blocks_per_cu  workgroups per compute unit of the estimate (1..64).
+ */
+typedef struct vbdr_tuning {
+    int32_t scan_test_first;
+    uint32_t scan_blocks_per_cu;
+    uint32_t est_blocks_per_cu;
+} vbdr_tuning;
+int vbdr_sketch_set_tuning(vbdr_sketch *sk, const vbdr_tuning *tuning);
+int vbdr_sketch_get_tuning(const vbdr_sketch *sk, vbdr_tuning *tuning);
+
+/*
  * Copy the sketch state to host memory in canonical form (synchronous:
  * waits for `stream`).  Any pointer may be NULL.
  *   dr_host   m*L bytes, dr_host[p*L + (r-1)] = DR of LBP1 r in BDR p;

@@ -42,7 +42,16 @@ struct vbdr_sketch {
   unsigned long long* hist;
   uint32_t* s1;
   uint64_t bytes;
+  vbdr_tuning tune;
 };
+
+static vbdr_tuning default_tuning(int layout) {
+  vbdr_tuning t;
+  t.scan_test_first = layout == VBDR_LAYOUT_FAST ? 1 : 2;
+  t.scan_blocks_per_cu = 16;
+  t.est_blocks_per_cu = 16;
+  return t;
+}
 
 namespace {
 
@@ -245,6 +254,8 @@ __device__ __forceinline__ double noise_removed(double Es, double Em, double m, 
   return (m * Es - g * Em) / (m - g);
 }
 
+constexpr int kEstUnroll = 8;  // gathers in flight per lane
+
 template <bool STAGE, bool EXTRA>
 __global__ __launch_bounds__(kEstBlock) void k_estimate(const uint32_t* __restrict__ hosts, uint64_t nh,
                                                         const uint32_t* __restrict__ s1g, uint32_t g, uint32_t m,
@@ -269,7 +280,7 @@ __global__ __launch_bounds__(kEstBlock) void k_estimate(const uint32_t* __restri
   const double Em = em_sh;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (uint64_t h = (uint64_t)blockIdx.x * kEstWaves + wave; h < nh; h += (uint64_t)gridDim.x * kEstWaves) {
-    const uint32_t aip = hosts[h];
+    const uint32_t kmix = mm3_key(hosts[h]);  // seed-independent half of H(aip, m, s1[i])
     if constexpr (EXTRA) {
       if (lane < kBins) lh[wave][lane] = 0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -277,11 +288,21 @@ __global__ __launch_bounds__(kEstBlock) void k_estimate(const uint32_t* __restri
     }
     uint64_t U = 0;
     uint32_t V = 0;
-    for (uint32_t i = lane; i < g; i += 64) {
-      const uint32_t r = reg[reduce_m(mm3(aip, s1[i]), m)];
-      U += 1ull << (32 - r);
-      V += r == 0;
-      if constexpr (EXTRA) atomicAdd(&lh[wave][r], 1u);
+    for (uint32_t i0 = lane; i0 < g; i0 += 64 * kEstUnroll) {
+      uint32_t r[kEstUnroll];
+#pragma unroll
+      for (int u = 0; u < kEstUnroll; ++u) {
+        const uint32_t i = i0 + 64u * u;
+        r[u] = i < g ? (uint32_t)reg[reduce_m(mm3_seeded(kmix, s1[i]), m)] : 255u;
+      }
+#pragma unroll
+      for (int u = 0; u < kEstUnroll; ++u) {
+        if (r[u] != 255u) {
+          U += 1ull << (32 - r[u]);
+          V += r[u] == 0;
+          if constexpr (EXTRA) atomicAdd(&lh[wave][r[u]], 1u);
+        }
+      }
     }
     U = wave_sum_u64(U);
     V = (uint32_t)wave_sum_u64(V);
@@ -365,6 +386,7 @@ int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_
       break;
     }
     sk->m = m, sk->g = g, sk->k = k, sk->layout = layout;
+    sk->tune = default_tuning(layout);
     while ((1u << sk->b) < g) sk->b++;
     sk->L = 33 - sk->b;
     const uint64_t x = splitmix64_first(hash_seed);
@@ -418,6 +440,24 @@ void vbdr_sketch_destroy(vbdr_sketch* sk) {
   delete sk;
 }
 
+int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
+  if (!sk || !tuning) return fail(VBDR_EINVAL, "NULL argument");
+  if (tuning->scan_test_first < 0 || tuning->scan_test_first > 2) return fail(VBDR_EINVAL, "scan_test_first must be 0, 1 or 2");
+  if (tuning->scan_blocks_per_cu > 64 || tuning->est_blocks_per_cu > 64)
+    return fail(VBDR_EINVAL, "blocks per CU must be at most 64");
+  sk->tune = default_tuning(sk->layout);
+  if (tuning->scan_test_first) sk->tune.scan_test_first = tuning->scan_test_first;
+  if (tuning->scan_blocks_per_cu) sk->tune.scan_blocks_per_cu = tuning->scan_blocks_per_cu;
+  if (tuning->est_blocks_per_cu) sk->tune.est_blocks_per_cu = tuning->est_blocks_per_cu;
+  return VBDR_OK;
+}
+
+int vbdr_sketch_get_tuning(const vbdr_sketch* sk, vbdr_tuning* tuning) {
+  if (!sk || !tuning) return fail(VBDR_EINVAL, "NULL argument");
+  *tuning = sk->tune;
+  return VBDR_OK;
+}
+
 int vbdr_sketch_info(const vbdr_sketch* sk, vbdr_info* out) {
   if (!sk || !out) return fail(VBDR_EINVAL, "NULL argument");
   out->m = sk->m, out->g = sk->g, out->b = sk->b, out->L = sk->L, out->k = sk->k;
@@ -436,18 +476,20 @@ int vbdr_scan_slice(vbdr_sketch* sk, const uint32_t* pairs_dev, uint64_t n, void
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool stage = sk->g <= kStageMaxG;
   const size_t lds = stage ? (size_t)sk->g * 4 : 0;
-  const uint32_t grid = grid_cap(sk, (n + kScanBlock * kScanUnroll - 1) / (kScanBlock * kScanUnroll), 16);
+  const uint32_t grid =
+      grid_cap(sk, (n + kScanBlock * kScanUnroll - 1) / (kScanBlock * kScanUnroll), sk->tune.scan_blocks_per_cu);
   const u32x2* p = reinterpret_cast<const u32x2*>(pairs_dev);
   const uint32_t m32 = (uint32_t)sk->m;
-  if (sk->layout == VBDR_LAYOUT_FAST) {
-    auto kern = stage ? k_scan<true, true, false> : k_scan<true, false, false>;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kScanBlock), lds, st, p, n, sk->s1, sk->g, sk->b, sk->A1, m32, sk->dr,
-                       sk->mstride, sk->seen, sk->wstride);
-  } else {
-    auto kern = stage ? k_scan<false, true, false> : k_scan<false, false, false>;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kScanBlock), lds, st, p, n, sk->s1, sk->g, sk->b, sk->A1, m32, sk->dr,
-                       sk->mstride, sk->seen, sk->wstride);
-  }
+  const bool test = sk->tune.scan_test_first == 1;
+  decltype(&k_scan<true, true, true>) kern;
+  if (sk->layout == VBDR_LAYOUT_FAST)
+    kern = stage ? (test ? k_scan<true, true, true> : k_scan<true, true, false>)
+                 : (test ? k_scan<true, false, true> : k_scan<true, false, false>);
+  else
+    kern = stage ? (test ? k_scan<false, true, true> : k_scan<false, true, false>)
+                 : (test ? k_scan<false, false, true> : k_scan<false, false, false>);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kScanBlock), lds, st, p, n, sk->s1, sk->g, sk->b, sk->A1, m32, sk->dr,
+                     sk->mstride, sk->seen, sk->wstride);
   VBDR_LAUNCHED("k_scan");
   return VBDR_OK;
 }
@@ -478,7 +520,7 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
   const bool stage = sk->g <= kStageMaxG;
   const bool extra = raw_es_dev || hist_dev;
   const size_t lds = stage ? (size_t)sk->g * 4 : 0;
-  const uint32_t grid = grid_cap(sk, (n_hosts + kEstWaves - 1) / kEstWaves, 16);
+  const uint32_t grid = grid_cap(sk, (n_hosts + kEstWaves - 1) / kEstWaves, sk->tune.est_blocks_per_cu);
   auto kern = stage ? (extra ? k_estimate<true, true> : k_estimate<true, false>)
                     : (extra ? k_estimate<false, true> : k_estimate<false, false>);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kEstBlock), lds, st, hosts_dev, n_hosts, sk->s1, sk->g, (uint32_t)sk->m,

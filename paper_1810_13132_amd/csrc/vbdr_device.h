@@ -30,6 +30,26 @@ __device__ __forceinline__ uint32_t mm3(uint32_t x, uint32_t seed) {
   return h;
 }
 
+// MurmurHash3_x86_32 split for many seeds over one key: mm3_key(x) is the
+// seed-independent block mix, mm3_seeded(mm3_key(x), A) == mm3(x, A).
+__device__ __forceinline__ uint32_t mm3_key(uint32_t x) {
+  uint32_t k = x * 0xcc9e2d51u;
+  k = (k << 15) | (k >> 17);
+  return k * 0x1b873593u;
+}
+__device__ __forceinline__ uint32_t mm3_seeded(uint32_t kmix, uint32_t seed) {
+  uint32_t h = seed ^ kmix;
+  h = (h << 13) | (h >> 19);
+  h = h * 5u + 0xe6546b64u;
+  h ^= 4u;
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
 // H(x, m, A) for m < 2^32: the top 32 bits of the 64-bit product h * m.
 __device__ __forceinline__ uint32_t reduce_m(uint32_t h, uint32_t m) { return __umulhi(h, m); }
 

@@ -106,8 +106,11 @@ class Stream:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            _load().synth_destroy(h)
+        if h and _lib is not None:
+            try:
+                _lib.synth_destroy(h)
+            except Exception:
+                pass
             self._h = None
 
     def slice(self, t: int, with_hidx: bool = False, host_pairs: np.ndarray = None, out: np.ndarray = None):

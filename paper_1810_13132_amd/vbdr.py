@@ -35,9 +35,14 @@ class Info(C.Structure):
                 ("state_bytes", C.c_uint64)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("scan_test_first", C.c_int32), ("scan_blocks_per_cu", C.c_uint32),
+                ("est_blocks_per_cu", C.c_uint32)]
+
+
 EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_destroy", "vbdr_scan_slice",
            "vbdr_advance_slice", "vbdr_estimate", "vbdr_estimate_ex", "vbdr_sketch_info", "vbdr_export_state",
-           "vbdr_import_state", "vbdr_last_error"]
+           "vbdr_import_state", "vbdr_last_error", "vbdr_sketch_set_tuning", "vbdr_sketch_get_tuning"]
 
 _lib = None
 
@@ -61,6 +66,8 @@ def lib():
         L.vbdr_sketch_info.argtypes = [vp, C.POINTER(Info)]
         L.vbdr_export_state.argtypes = [vp, vp, vp, vp, vp, vp]
         L.vbdr_import_state.argtypes = [vp, vp, vp, vp, vp, u64, vp]
+        L.vbdr_sketch_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.vbdr_sketch_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.vbdr_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("vbdr_sketch_destroy", "vbdr_last_error"):
@@ -120,6 +127,16 @@ class Sketch:
         out = Info()
         _check(lib().vbdr_sketch_info(self._h, C.byref(out)))
         return out
+
+    def set_tuning(self, scan_test_first: int = 0, scan_blocks_per_cu: int = 0, est_blocks_per_cu: int = 0):
+        t = Tuning(scan_test_first, scan_blocks_per_cu, est_blocks_per_cu)
+        _check(lib().vbdr_sketch_set_tuning(self._h, C.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().vbdr_sketch_get_tuning(self._h, C.byref(t)))
+        return {"scan_test_first": t.scan_test_first, "scan_blocks_per_cu": t.scan_blocks_per_cu,
+                "est_blocks_per_cu": t.est_blocks_per_cu}
 
     @property
     def t(self) -> int:
