@@ -41,6 +41,10 @@ struct vbdr_sketch {
   uint8_t* reg;
   unsigned long long* hist;
   uint32_t* s1;
+  uint8_t* reg4;                 // registers as nibbles, min(reg, 15); 15 = read reg
+  int parts;                     // XCD partitions of the estimate (1 = direct gather)
+  unsigned long long* part_u;    // [parts][kPartChunk] partial harmonic sums
+  uint32_t* part_v;              // [parts][kPartChunk] partial zero counts
   uint64_t bytes;
   vbdr_tuning tune;
 };
@@ -49,7 +53,7 @@ static vbdr_tuning default_tuning(int layout) {
   vbdr_tuning t;
   t.scan_test_first = layout == VBDR_LAYOUT_FAST ? 1 : 2;
   t.scan_blocks_per_cu = 16;
-  t.est_blocks_per_cu = 16;
+  t.est_blocks_per_cu = 32;
   return t;
 }
 
@@ -81,6 +85,9 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr uint64_t kPad = 4096;          // BDR padding granule of a plane
 constexpr uint32_t kStageMaxG = 8192;    // s1 staged in LDS up to 32 KiB
+constexpr uint32_t kCusPerXcd = 32;      // gfx950: 8 XCDs x 32 CUs
+constexpr uint64_t kPartMinM = 1ull << 22;  // pools whose registers outgrow one XCD's L2
+constexpr uint32_t kPartChunk = 1u << 17;   // hosts per partitioned-estimate pass
 
 // ----------------------------------------------------------------- init
 
@@ -163,48 +170,48 @@ static_assert(kPad % (kAdvBlock * kAdvBpt) == 0, "plane padding must cover whole
 template <bool FAST>
 __global__ __launch_bounds__(kAdvBlock) void k_advance(uint8_t* __restrict__ dr, uint64_t mstride,
                                                        uint32_t* __restrict__ seen, uint64_t wstride,
-                                                       uint8_t* __restrict__ reg, uint64_t m, uint32_t L, uint32_t thr,
+                                                       uint8_t* __restrict__ reg, uint8_t* __restrict__ reg4,
+                                                       uint64_t m, uint32_t L, uint32_t thr,
                                                        unsigned long long* __restrict__ hist) {
   __shared__ uint32_t lh[kAdvBlock / 64][kBins];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane < kBins) lh[wave][lane] = 0;
   __syncthreads();
   const uint64_t base = ((uint64_t)blockIdx.x * kAdvBlock + threadIdx.x) * kAdvBpt;
-  uint32_t regb[kAdvBpt];
-#pragma unroll
-  for (int j = 0; j < kAdvBpt; ++j) regb[j] = 0;
-  uint32_t found = 0, folded = 0;
+  const uint32_t gt_bias = swar_gt_bias(thr);
+  // Four DR bytes per 32-bit word: R = registers found so far, M = 0xFF for
+  // BDRs whose register is already known (planes are visited downwards).
+  uint32_t R[4] = {0, 0, 0, 0}, M[4] = {0, 0, 0, 0};
+  uint32_t folded = 0;
+  const uint8_t* top = dr + (uint64_t)(L - 1) * mstride + base;
+  u32x4 dn = *reinterpret_cast<const u32x4*>(top);
+  uint32_t sn = 0;
+  if constexpr (FAST) sn = seen[(uint64_t)(L - 1) * wstride + (base >> 5)];
   for (int i = (int)L; i >= 1; --i) {
-    u32x4* pl = reinterpret_cast<u32x4*>(dr + (uint64_t)(i - 1) * mstride + base);
-    const u32x4 d = *pl;
+    const u32x4 d = dn;
+    const uint32_t s = sn;
+    if (i > 1) {  // prefetch the next plane down
+      dn = *reinterpret_cast<const u32x4*>(dr + (uint64_t)(i - 2) * mstride + base);
+      if constexpr (FAST) sn = seen[(uint64_t)(i - 2) * wstride + (base >> 5)];
+    }
     uint32_t fold = 0;
     if constexpr (FAST) {
-      uint32_t s = seen[(uint64_t)(i - 1) * wstride + (base >> 5)];
-      s = (s >> (base & 31)) & 0xFFFFu;
-      fold = s & ~folded;
-      folded |= s;
+      const uint32_t bits = (s >> (base & 31)) & 0xFFFFu;
+      fold = bits & ~folded;  // only the slice's highest LBP1 is recorded
+      folded |= bits;
     }
     u32x4 nd;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      const uint32_t word = d[w];
-      uint32_t nword = 0;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int j = w * 4 + e;
-        const uint32_t v = (word >> (8 * e)) & 0xFFu;
-        uint32_t nv = v + (v < kSat ? 1u : 0u);  // SlideDR, saturating
-        if (FAST && ((fold >> j) & 1u)) nv = 0;  // SetDR of the slice's LBP1
-        const bool act = FAST ? (nv <= thr) : (v <= thr);
-        if (act && !((found >> j) & 1u)) {
-          regb[j] = (uint32_t)i;
-          found |= 1u << j;
-        }
-        nword |= nv << (8 * e);
-      }
-      nd[w] = nword;
+      const uint32_t x = d[w];
+      uint32_t y = swar_sat_inc(x);                               // SlideDR
+      if constexpr (FAST) y &= ~swar_nibble_to_bytes((fold >> (4 * w)) & 0xFu);  // SetDR
+      const uint32_t act = swar_le_mask(FAST ? y : x, gt_bias);  // IsActiveDR
+      R[w] |= act & ~M[w] & ((uint32_t)i * 0x01010101u);
+      M[w] |= act;
+      nd[w] = y;
     }
-    *pl = nd;
+    *reinterpret_cast<u32x4*>(dr + (uint64_t)(i - 1) * mstride + base) = nd;
   }
   if constexpr (FAST) {
     // The two threads sharing a bsLBP1 word are adjacent lanes of one wave
@@ -212,19 +219,19 @@ __global__ __launch_bounds__(kAdvBlock) void k_advance(uint8_t* __restrict__ dr,
     if ((base & 31) == 0)
       for (uint32_t i = 0; i < L; ++i) seen[(uint64_t)i * wstride + (base >> 5)] = 0;
   }
-  u32x4 rw;
+  *reinterpret_cast<u32x4*>(reg + base) = u32x4{R[0], R[1], R[2], R[3]};
+  uint64_t nib = 0;
 #pragma unroll
-  for (int w = 0; w < 4; ++w)
-    rw[w] = regb[4 * w] | (regb[4 * w + 1] << 8) | (regb[4 * w + 2] << 16) | (regb[4 * w + 3] << 24);
-  *reinterpret_cast<u32x4*>(reg + base) = rw;
+  for (int w = 0; w < 4; ++w) nib |= (uint64_t)swar_pack_nibbles(R[w]) << (16 * w);
+  *reinterpret_cast<uint64_t*>(reg4 + base / 2) = nib;
 #pragma unroll
   for (int j = 0; j < kAdvBpt; ++j)
-    if (base + j < m) atomicAdd(&lh[wave][regb[j]], 1u);
+    if (base + j < m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
   __syncthreads();
   if (threadIdx.x < kBins) {
-    uint32_t s = 0;
-    for (int w = 0; w < kAdvBlock / 64; ++w) s += lh[w][threadIdx.x];
-    if (s) atomicAdd(hist + threadIdx.x, (unsigned long long)s);
+    uint32_t c = 0;
+    for (int w = 0; w < kAdvBlock / 64; ++w) c += lh[w][threadIdx.x];
+    if (c) atomicAdd(hist + threadIdx.x, (unsigned long long)c);
   }
 }
 
@@ -321,6 +328,94 @@ __global__ __launch_bounds__(kEstBlock) void k_estimate(const uint32_t* __restri
   }
 }
 
+// ------------------------------------------- estimate, XCD-partitioned
+// The register array of a large pool does not fit one XCD's L2, so direct
+// gathers pull a whole line from the memory side per byte used.  Here the
+// pool is split into `parts` contiguous ranges by the top bits of the
+// getPhyIdx hash; workgroup b (dispatched to XCD b mod 8) hashes every
+// (host, i) but gathers only those landing in range b mod parts, from the
+// nibble copy of the registers, whose range share stays L2 resident.  The
+// per-range partial sums are combined by k_estimate_final.  The sums are
+// exact integers, so the result equals the direct kernel's bit for bit.
+
+template <bool STAGE>
+__global__ __launch_bounds__(kEstBlock) void k_estimate_part(const uint32_t* __restrict__ hosts, uint32_t nh,
+                                                             const uint32_t* __restrict__ s1g, uint32_t g, uint32_t m,
+                                                             const uint8_t* __restrict__ reg,
+                                                             const uint8_t* __restrict__ reg4, uint32_t parts,
+                                                             uint32_t part_shift,
+                                                             unsigned long long* __restrict__ part_u,
+                                                             uint32_t* __restrict__ part_v) {
+  extern __shared__ uint32_t s1_lds[];
+  const uint32_t* s1 = s1g;
+  if constexpr (STAGE) {
+    for (uint32_t i = threadIdx.x; i < g; i += kEstBlock) s1_lds[i] = s1g[i];
+    __syncthreads();
+    s1 = s1_lds;
+  }
+  const uint32_t x = blockIdx.x % parts;
+  const uint32_t tiles = gridDim.x / parts;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint32_t h = (blockIdx.x / parts) * kEstWaves + wave; h < nh; h += tiles * kEstWaves) {
+    const uint32_t kmix = mm3_key(hosts[h]);
+    uint64_t U = 0;
+    uint32_t V = 0;
+    for (uint32_t i0 = lane; i0 < g; i0 += 64 * kEstUnroll) {
+#pragma unroll
+      for (int u = 0; u < kEstUnroll; ++u) {
+        const uint32_t i = i0 + 64u * u;
+        if (i < g) {
+          const uint32_t hh = mm3_seeded(kmix, s1[i]);
+          if ((hh >> part_shift) == x) {
+            const uint32_t p = reduce_m(hh, m);
+            const uint32_t nib = (reg4[p >> 1] >> ((p & 1u) << 2)) & 15u;
+            const uint32_t r = nib < 15u ? nib : (uint32_t)reg[p];
+            U += 1ull << (32 - r);
+            V += r == 0;
+          }
+        }
+      }
+    }
+    U = wave_sum_u64(U);
+    V = (uint32_t)wave_sum_u64(V);
+    if (lane == 0) {
+      part_u[(uint64_t)x * kPartChunk + h] = U;
+      part_v[(uint64_t)x * kPartChunk + h] = V;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_estimate_final(uint32_t nh, uint32_t g, uint32_t m, uint32_t parts,
+                                                        const unsigned long long* __restrict__ hist,
+                                                        const unsigned long long* __restrict__ part_u,
+                                                        const uint32_t* __restrict__ part_v, float* __restrict__ out) {
+  __shared__ double em_sh;
+  if (threadIdx.x == 0) {
+    uint64_t U = 0;
+    for (int r = 0; r < kBins; ++r) U += (uint64_t)hist[r] << (32 - r);
+    em_sh = hll_estimate(U, hist[0], (double)m);
+  }
+  __syncthreads();
+  const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+  if (h >= nh) return;
+  uint64_t U = 0, V = 0;
+  for (uint32_t x = 0; x < parts; ++x) {
+    U += part_u[(uint64_t)x * kPartChunk + h];
+    V += part_v[(uint64_t)x * kPartChunk + h];
+  }
+  const double Es = hll_estimate(U, V, (double)g);
+  const double n = noise_removed(Es, em_sh, (double)m, (double)g);
+  out[h] = (float)(n > 0.0 ? n : 0.0);
+}
+
+// Nibble copy of the registers (after a state import).
+__global__ void k_pack_reg4(const uint8_t* __restrict__ reg, uint8_t* __restrict__ reg4, uint64_t nbytes4) {
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nbytes4; q += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t a = reg[2 * q], b = reg[2 * q + 1];
+    reg4[q] = (uint8_t)((a < 15u ? a : 15u) | ((b < 15u ? b : 15u) << 4));
+  }
+}
+
 // ------------------------------------------------------------- helpers
 
 int check_device(const vbdr_sketch* sk) {
@@ -351,6 +446,9 @@ int init_state(vbdr_sketch* sk, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, reinterpret_cast<uint32_t*>(sk->reg),
                      sk->mstride / 4, 0u);
   VBDR_LAUNCHED("k_fill_u32(reg)");
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, reinterpret_cast<uint32_t*>(sk->reg4),
+                     sk->mstride / 8, 0u);
+  VBDR_LAUNCHED("k_fill_u32(reg4)");
   if (sk->seen) {
     hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, sk->seen, (uint64_t)sk->L * sk->wstride, 0u);
     VBDR_LAUNCHED("k_fill_u32(seen)");
@@ -395,16 +493,24 @@ int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_
     sk->wstride = sk->mstride / 32;
     const uint64_t dr_bytes = (uint64_t)sk->L * sk->mstride;
     const uint64_t seen_bytes = layout == VBDR_LAYOUT_FAST ? (uint64_t)sk->L * sk->wstride * 4 : 0;
+    // The partitioned estimate pays off once the registers outgrow one XCD's L2.
+    const int xcds = sk->n_cu / (int)kCusPerXcd;
+    sk->parts = (m >= kPartMinM && xcds >= 8) ? 8 : (m >= kPartMinM && xcds >= 4) ? 4 : 1;
+    const uint64_t part_bytes = sk->parts > 1 ? (uint64_t)sk->parts * kPartChunk * (8 + 4) : 0;
     if (hipMalloc(&sk->dr, dr_bytes) != hipSuccess || hipMalloc(&sk->reg, sk->mstride) != hipSuccess ||
+        hipMalloc(&sk->reg4, sk->mstride / 2) != hipSuccess ||
         hipMalloc(&sk->hist, 64 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&sk->s1, (uint64_t)g * 4) != hipSuccess ||
-        (seen_bytes && hipMalloc(&sk->seen, seen_bytes) != hipSuccess)) {
+        (seen_bytes && hipMalloc(&sk->seen, seen_bytes) != hipSuccess) ||
+        (part_bytes && hipMalloc(&sk->part_u, (uint64_t)sk->parts * kPartChunk * 8) != hipSuccess) ||
+        (part_bytes && hipMalloc(&sk->part_v, (uint64_t)sk->parts * kPartChunk * 4) != hipSuccess)) {
       (void)hipGetLastError();
       rc = fail(VBDR_ENOMEM, "device allocation of %llu bytes failed",
-                (unsigned long long)(dr_bytes + seen_bytes + sk->mstride));
+                (unsigned long long)(dr_bytes + seen_bytes + sk->mstride * 3 / 2 + part_bytes));
       break;
     }
-    sk->bytes = dr_bytes + seen_bytes + sk->mstride + 64 * sizeof(unsigned long long) + (uint64_t)g * 4;
+    sk->bytes = dr_bytes + seen_bytes + sk->mstride * 3 / 2 + 64 * sizeof(unsigned long long) + (uint64_t)g * 4 +
+                part_bytes;
     hipStream_t st = nullptr;
     if ((rc = init_state(sk, st)) != VBDR_OK) break;
     hipLaunchKernelGGL(k_seeds, dim3((g + 255) / 256), dim3(256), 0, st, sk->s1, g, sk->A0);
@@ -436,6 +542,9 @@ void vbdr_sketch_destroy(vbdr_sketch* sk) {
   if (sk->reg) (void)hipFree(sk->reg);
   if (sk->hist) (void)hipFree(sk->hist);
   if (sk->s1) (void)hipFree(sk->s1);
+  if (sk->reg4) (void)hipFree(sk->reg4);
+  if (sk->part_u) (void)hipFree(sk->part_u);
+  if (sk->part_v) (void)hipFree(sk->part_v);
   if (prev >= 0 && prev != sk->device) (void)hipSetDevice(prev);
   delete sk;
 }
@@ -503,7 +612,7 @@ int vbdr_advance_slice(vbdr_sketch* sk, void* stream) {
   const uint32_t grid = (uint32_t)(sk->mstride / (kAdvBlock * kAdvBpt));
   auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_advance<true> : k_advance<false>;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kAdvBlock), 0, st, sk->dr, sk->mstride, sk->seen, sk->wstride, sk->reg,
-                     sk->m, sk->L, sk->k - 1, sk->hist);
+                     sk->reg4, sk->m, sk->L, sk->k - 1, sk->hist);
   VBDR_LAUNCHED("k_advance");
   sk->t++;
   return VBDR_OK;
@@ -520,6 +629,23 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
   const bool stage = sk->g <= kStageMaxG;
   const bool extra = raw_es_dev || hist_dev;
   const size_t lds = stage ? (size_t)sk->g * 4 : 0;
+  if (sk->parts > 1 && !extra) {
+    const uint32_t parts = (uint32_t)sk->parts, shift = parts == 8 ? 29u : 30u;
+    auto kern = stage ? k_estimate_part<true> : k_estimate_part<false>;
+    for (uint64_t c = 0; c < n_hosts; c += kPartChunk) {
+      const uint32_t nh = (uint32_t)(n_hosts - c < kPartChunk ? n_hosts - c : kPartChunk);
+      const uint64_t want = (nh + kEstWaves - 1) / kEstWaves;
+      const uint64_t cap = (uint64_t)sk->n_cu * sk->tune.est_blocks_per_cu / parts;
+      const uint32_t tiles = (uint32_t)(want < cap ? want : (cap ? cap : 1));
+      hipLaunchKernelGGL(kern, dim3(tiles * parts), dim3(kEstBlock), lds, st, hosts_dev + c, nh, sk->s1, sk->g,
+                         (uint32_t)sk->m, sk->reg, sk->reg4, parts, shift, sk->part_u, sk->part_v);
+      VBDR_LAUNCHED("k_estimate_part");
+      hipLaunchKernelGGL(k_estimate_final, dim3((nh + 255) / 256), dim3(256), 0, st, nh, sk->g, (uint32_t)sk->m,
+                         parts, sk->hist, sk->part_u, sk->part_v, out_dev + c);
+      VBDR_LAUNCHED("k_estimate_final");
+    }
+    return VBDR_OK;
+  }
   const uint32_t grid = grid_cap(sk, (n_hosts + kEstWaves - 1) / kEstWaves, sk->tune.est_blocks_per_cu);
   auto kern = stage ? (extra ? k_estimate<true, true> : k_estimate<true, false>)
                     : (extra ? k_estimate<false, true> : k_estimate<false, false>);
@@ -604,6 +730,10 @@ int vbdr_import_state(vbdr_sketch* sk, const uint8_t* dr_host, const uint32_t* b
     VBDR_HIP(hipMemcpy(sk->reg, r.data(), sk->mstride, hipMemcpyHostToDevice));
   }
   VBDR_HIP(hipMemcpy(sk->hist, hist_host, kBins * sizeof(uint64_t), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_pack_reg4, dim3(grid_cap(sk, (sk->mstride / 2 + 255) / 256, 8)), dim3(256), 0, nullptr, sk->reg,
+                     sk->reg4, sk->mstride / 2);
+  VBDR_LAUNCHED("k_pack_reg4");
+  VBDR_HIP(hipStreamSynchronize(nullptr));
   sk->t = t;
   return VBDR_OK;
 }

@@ -62,6 +62,39 @@ __device__ __forceinline__ void bip_map(uint32_t bip, uint32_t A1, uint32_t b, u
   rho = __clz((h << b) | (1u << (b - 1))) + 1;
 }
 
+// ---- byte-wise (SWAR) operations on four one-byte DRs held in a uint32 ----
+
+// Saturating increment of every byte (SlideDR): bytes below 255 gain 1.
+__host__ __device__ __forceinline__ uint32_t swar_sat_inc(uint32_t x) {
+  const uint32_t t = ~x;  // a byte of t is zero exactly where x holds 255
+  const uint32_t not_sat = (((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
+  return x + (not_sat >> 7);
+}
+
+// 0xFF in byte j for each set bit j of a 4-bit mask.
+__host__ __device__ __forceinline__ uint32_t swar_nibble_to_bytes(uint32_t f4) {
+  return ((f4 * 0x00204081u) & 0x01010101u) * 0xFFu;
+}
+
+// Bias for swar_le_mask: each byte value v sits in its own 16-bit lane, where
+// v + (255 - thr) carries into bit 8 exactly when v > thr.
+__host__ __device__ __forceinline__ uint32_t swar_gt_bias(uint32_t thr) { return (0xFFu - thr) * 0x00010001u; }
+
+// 0xFF in every byte whose value is <= thr (thr < 255).
+__host__ __device__ __forceinline__ uint32_t swar_le_mask(uint32_t v, uint32_t bias) {
+  const uint32_t even = ((((v & 0x00FF00FFu) + bias) >> 8) & 0x00010001u);
+  const uint32_t odd = ((((v >> 8) & 0x00FF00FFu) + bias) & 0x01000100u);
+  return ((even | odd) ^ 0x01010101u) * 0xFFu;
+}
+
+// Four register bytes (<= 32) -> four nibbles min(r, 15), byte j -> bits 4j..4j+3.
+__host__ __device__ __forceinline__ uint32_t swar_pack_nibbles(uint32_t r) {
+  const uint32_t ge15 = ((r + 0x71717171u) & 0x80808080u) >> 7;  // 1 where r >= 15
+  const uint32_t c = (r & ~(ge15 * 0xFFu)) | (ge15 * 0x0Fu);
+  const uint32_t t = (c | (c >> 4)) & 0x00FF00FFu;
+  return (t & 0xFFu) | ((t >> 8) & 0xFF00u);
+}
+
 // HyperLogLog alpha_q (Flajolet et al. 2007).
 __device__ __forceinline__ double hll_alpha(double q) {
   if (q == 16.0) return 0.673;

@@ -166,6 +166,37 @@ def test_parity_tiny_workload(V, O, layout):
         assert_estimates_close(V, O, sk, osk, hosts)
 
 
+@pytest.mark.parametrize("layout", ["fast", "small"])
+def test_parity_large_pool_partitioned_estimate(V, O, layout):
+    """Pools of 2^22 BDRs and more take the XCD-partitioned estimate; more
+    hosts than one partition pass holds (2^17) exercise the chunking.  The
+    plain estimate (partitioned) is checked against the oracle and against
+    estimate_ex (direct gathers); both must agree bit for bit."""
+    m, g, k, seed = (1 << 22) + 77, 256, 3, 13
+    rng = np.random.default_rng(seed)
+    aips = rng.integers(0, 2**32, 5000, dtype=np.uint64).astype(np.uint32)
+    sk = V.Sketch(m, g, k, seed, layout)
+    osk = O.Sketch(m, g, k, seed, LAYOUT_CODE[layout])
+    for t in range(3):
+        n = 1 << 19
+        pairs = np.stack([aips[rng.integers(0, len(aips), n)],
+                          rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
+        sk.scan_slice(_dev(V, pairs.reshape(-1)))
+        osk.scan(pairs)
+        sk.advance_slice()
+        osk.advance()
+    assert_state_equal(sk.state(), osk.state(), layout, "large pool")
+    hosts = np.concatenate([aips, rng.integers(0, 2**32, (1 << 17) + 3000 - len(aips), dtype=np.uint64)
+                            .astype(np.uint32)])
+    ref = assert_estimates_close(V, O, sk, osk, hosts)
+    assert (ref[: len(aips)] > 0).all()
+    # resume: the imported registers must feed the partitioned path too
+    b = V.Sketch(m, g, k, seed, layout)
+    b.load_state(sk.state())
+    hd = _dev(V, hosts)
+    assert torch.equal(b.estimate(hd), sk.estimate(hd))
+
+
 def test_resume_from_exported_state(V, O):
     """Export after 5 slices, import into a fresh sketch, continue: identical
     to an uninterrupted run."""
