@@ -94,13 +94,72 @@ def cpu_baseline(w, layout, slice0, hosts_sample, n_active):
                         "estimate": round(t_est, 3)}}
 
 
+def learned_accuracy():
+    """Plain vs learned RMS relative error on one evaluation stream of the tiny
+    workload (the shape the network is trained on), and both estimators'
+    hosts/s there; None when no trained weights are present."""
+    import torch
+    from paper_1810_13132_amd import learn, vbdr
+    if not os.path.exists(learn.DEFAULT_WEIGHTS):
+        return None
+    params, lo, hi, meta = learn.load()
+    res = learn.evaluate(params, lo, hi, eval_seeds=range(100, 101))
+    res["workload"] = "tiny (2^12 hosts, 2^20 pairs/slice, m=2^18, g=256, k=4), eval seed 100"
+    res["trained_on"] = meta.get("train_seeds")
+    return res
+
+
+def run_batched(args):
+    """32 independent edge-router streams stepped together: persistent kernels,
+    graph replay, launch shape picked by the autotuner on a scratch batch."""
+    import numpy as np
+    import torch
+    from paper_1810_13132_amd import autotune, synth, vbdr
+    torch.cuda.set_device(0)
+    ws = synth.batched_workloads()
+    K, W = args.steps, args.warmup
+    params = [dict(m=w.m, g=w.g, k=w.k, hash_seed=w.seed, layout=args.layout) for w in ws]
+    streams = [synth.Stream(w) for w in ws]
+    pairs = [[vbdr.to_device_u32(st.slice(t).reshape(-1)) for st in streams] for t in range(W + K)]
+    log(f"batched: {len(ws)} streams, {sum(w.pairs_per_slice for w in ws)} pairs per step generated")
+    hosts = [vbdr.to_device_u32(st.aip) for st in streams]
+    outs = [torch.empty(h.numel(), dtype=torch.float32, device="cuda") for h in hosts]
+    scratch = vbdr.Batch(params)
+    best, timings = autotune.tune(scratch, pairs[0], hosts, outs, reps=2)
+    scratch.close()
+    log(f"autotuned: {best}")
+    bt = vbdr.Batch(params)
+    bt.set_tuning(best["scan_tile"], best["est_tile"], best["blocks_per_cu"], True)
+    for t in range(W):
+        bt.step(pairs[t], hosts, outs)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for t in range(W, W + K):
+        bt.step(pairs[t], hosts, outs)
+    ev[1].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_pairs = sum(w.pairs_per_slice for w in ws)
+    n_hosts = sum(h.numel() for h in hosts)
+    res = {"metric": METRIC, "value": n_pairs * K / elapsed, "unit": "pairs/s", "n_gpus": 1, "steps": K,
+           "warmup": W, "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "batched", "sketches": len(ws), "pairs_per_step": n_pairs,
+                      "hosts_per_step": n_hosts, "layout": args.layout, "tuning": best},
+           "hosts_per_s": n_hosts * K / elapsed, "graph_ms_per_step": ev[0].elapsed_time(ev[1]) / K,
+           "autotune_ms_per_step": timings}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--layout", default="small", choices=["small", "fast"])
-    ap.add_argument("--workload", default="line_rate", choices=["line_rate", "tiny"])
+    ap.add_argument("--workload", default="line_rate", choices=["line_rate", "tiny", "batched"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -113,6 +172,8 @@ def main():
     import torch
     from paper_1810_13132_amd import synth, vbdr
 
+    if args.workload == "batched":
+        return run_batched(args)
     w = synth.LINE_RATE if args.workload == "line_rate" else synth.TINY
     K, W = args.steps, args.warmup
     n_slices = W + K
@@ -204,6 +265,9 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
         "roofline": roofline,
     }
+    acc = learned_accuracy()
+    if acc:
+        res["accuracy"] = acc
     if not args.no_cpu_baseline:
         rng = np.random.default_rng(0)
         act_last = hosts_all[np.nonzero(np.logical_or.reduce(window))[0]]

@@ -139,12 +139,17 @@ int vbdr_sketch_info(const vbdr_sketch *sk, vbdr_info *out);
  *                      update when it is already made; 2: always update
  *                      (default: the variant measured faster for the layout);
  *   scan_blocks_per_cu workgroups per compute unit of the scan (1..64);
- *   est_blocks_per_cu  workgroups per compute unit of the estimate (1..64).
+ *   est_blocks_per_cu  workgroups per compute unit of the estimate (1..64);
+ *   scan_binned        1: pools of 2^22..2^27 BDRs scan in two passes, the
+ *                      pairs first binned by pool range so that each XCD
+ *                      updates only its own range; 2: always scan directly
+ *                      (default: 1).
  */
 typedef struct vbdr_tuning {
     int32_t scan_test_first;
     uint32_t scan_blocks_per_cu;
     uint32_t est_blocks_per_cu;
+    int32_t scan_binned;
 } vbdr_tuning;
 int vbdr_sketch_set_tuning(vbdr_sketch *sk, const vbdr_tuning *tuning);
 int vbdr_sketch_get_tuning(const vbdr_sketch *sk, vbdr_tuning *tuning);
@@ -172,6 +177,115 @@ int vbdr_import_state(vbdr_sketch *sk, const uint8_t *dr_host, const uint32_t *b
 
 /* Message of the calling thread's last error ("" if none).  Valid until the next call. */
 const char *vbdr_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Learned estimator (an addition beside the paper's estimate, not from it).
+ *
+ * Features of a host (VBDR_MLP_IN = 67, float):
+ *   [0..32]  hist[r] / g, the host's register histogram (the per-register
+ *            values Alg. 5 sums, taken as a histogram);
+ *   [33..65] pool_hist[r] / m, the pool's register histogram;
+ *   [66]     ln(g / m).
+ * Network: 67 -> 64 -> 64 -> 1 with GELU (exact erf form), output y
+ * estimating ln(1 + n), so n_hat = exp(y) - 1 clamped at 0.
+ * Parameters (VBDR_MLP_PARAMS = 8577 float, in this order):
+ *   W1 [64][67] row-major, b1 [64], W2 [64][64], b2 [64], w3 [64], b3 [1].
+ * Inference rounds the inputs, W1, W2, w3 and the first hidden layer to
+ * bfloat16 (round to nearest even) and accumulates in float32 on the matrix
+ * cores; the learned estimate is replaced by the plain vbdr_estimate value
+ * for hosts whose features leave the envelope [env_lo, env_hi] or whose
+ * output is not finite.
+ * ---------------------------------------------------------------------- */
+#define VBDR_MLP_IN 67
+#define VBDR_MLP_PARAMS 8577
+
+typedef struct vbdr_mlp vbdr_mlp;
+typedef struct vbdr_trainer vbdr_trainer;
+
+/* Upload a network (params_host: VBDR_MLP_PARAMS floats, host memory, copied).
+ * env_lo / env_hi: VBDR_MLP_IN floats each, or both NULL for no envelope.
+ * The network lives on the current device.  Synchronous. */
+int vbdr_mlp_create(const float *params_host, const float *env_lo, const float *env_hi, vbdr_mlp **out);
+void vbdr_mlp_destroy(vbdr_mlp *mlp); /* NULL-safe; synchronises the device */
+
+/* Features (n_hosts x 67 float, row-major, device) of the given hosts for the
+ * last closed window, from the same register gathers as vbdr_estimate. */
+int vbdr_features(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_hosts, float *feats_dev, void *stream);
+
+/* Learned estimate of n_hosts hosts into out_dev (float); used_fallback_dev
+ * (n_hosts bytes, nullable) receives 1 where the plain estimate was used. */
+int vbdr_estimate_learned(vbdr_sketch *sk, const vbdr_mlp *mlp, const uint32_t *hosts_dev, uint64_t n_hosts,
+                          float *out_dev, uint8_t *used_fallback_dev, void *stream);
+
+/* Float32 training state (parameters, Adam moments, gradient buffer) on the
+ * current device, initialised from params_host; Adam with beta1 0.9, beta2
+ * 0.999, eps 1e-8 and learning rate lr. */
+int vbdr_trainer_create(const float *params_host, float lr, vbdr_trainer **out);
+void vbdr_trainer_destroy(vbdr_trainer *tr); /* NULL-safe; synchronises the device */
+int vbdr_trainer_set_lr(vbdr_trainer *tr, float lr);
+
+/* One Adam step on the mean squared error of y against targets over a batch:
+ * feats_dev (n x 67 float), targets_dev (n float, ln(1 + n) of each sample).
+ * loss_dev (nullable, 1 float) has the batch loss ADDED to it. */
+int vbdr_trainer_step(vbdr_trainer *tr, const float *feats_dev, const float *targets_dev, uint64_t n, float *loss_dev,
+                      void *stream);
+
+/* The batch-mean-loss gradient at the current parameters, ADDED into
+ * grads_out_dev (VBDR_MLP_PARAMS float, device); no update. */
+int vbdr_trainer_grad(vbdr_trainer *tr, const float *feats_dev, const float *targets_dev, uint64_t n,
+                      float *grads_out_dev, float *loss_dev, void *stream);
+
+/* Copy the float32 parameters to host memory (synchronous on stream). */
+int vbdr_trainer_params(vbdr_trainer *tr, float *params_host, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent sketches (e.g. one per edge router), each with
+ * its own pool size, g, k, seed and layout, stepped together.  One step =
+ * for every sketch, scan its slice, close it, estimate its host list --
+ * vbdr_scan_slice + vbdr_advance_slice + vbdr_estimate semantics per sketch,
+ * run as three persistent work-queue kernels over all sketches, captured once
+ * into a HIP graph and replayed.  At most 256 sketches per batch.
+ * ---------------------------------------------------------------------- */
+typedef struct vbdr_batch vbdr_batch;
+
+typedef struct vbdr_batch_params {
+    uint64_t m;
+    uint32_t g, k;
+    uint64_t hash_seed;
+    int32_t layout;
+} vbdr_batch_params;
+
+/* Launch shape of a batch step (no effect on results):
+ *   scan_tile      pairs per scan work item (256 .. 2^22);
+ *   est_tile       hosts per estimate work item (4 .. 2^16);
+ *   blocks_per_cu  workgroups per compute unit of each persistent kernel (1..32);
+ *   use_graph      1 = capture the kernel sequence once and replay it. */
+typedef struct vbdr_batch_tuning {
+    uint32_t scan_tile;
+    uint32_t est_tile;
+    uint32_t blocks_per_cu;
+    int32_t use_graph;
+} vbdr_batch_tuning;
+
+/* Create n_sketches (1..256) sketches described by params[n_sketches] on the
+ * current device.  Synchronous. */
+int vbdr_batch_create(uint32_t n_sketches, const vbdr_batch_params *params, vbdr_batch **out);
+void vbdr_batch_destroy(vbdr_batch *bt); /* NULL-safe; also frees its sketches */
+
+/* Borrowed handle of sketch i (for export, estimate_ex, learned estimates);
+ * owned by the batch.  NULL (and vbdr_last_error set) if i is out of range. */
+vbdr_sketch *vbdr_batch_sketch(vbdr_batch *bt, uint32_t i);
+
+int vbdr_batch_set_tuning(vbdr_batch *bt, const vbdr_batch_tuning *tuning);
+int vbdr_batch_get_tuning(const vbdr_batch *bt, vbdr_batch_tuning *tuning);
+
+/* One step.  Host arrays of n_sketches entries: pairs_dev[i] (2*n_pairs[i]
+ * uint32, device, 8-byte aligned), hosts_dev[i] (n_hosts[i] uint32, device)
+ * and out_dev[i] (n_hosts[i] float, device).  Work is ordered after earlier
+ * work on `stream`, and later work on `stream` is ordered after it; it runs
+ * on a stream the batch owns.  The host arrays may be reused on return. */
+int vbdr_batch_step(vbdr_batch *bt, const uint32_t *const *pairs_dev, const uint64_t *n_pairs,
+                    const uint32_t *const *hosts_dev, const uint64_t *n_hosts, float *const *out_dev, void *stream);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,7 @@ def hip_flags():
 
 
 def build_hip(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, "vbdr.hip")]
+    srcs = [os.path.join(CSRC, n) for n in ("vbdr.hip", "vbdr_learn.hip", "vbdr_batch.hip")]
     cmd = [hipcc()] + hip_flags() + ["-shared", "-o", LIB + ".tmp"] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)

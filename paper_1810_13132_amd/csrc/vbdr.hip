@@ -22,46 +22,24 @@
 #include <string>
 #include <vector>
 
-#include "vbdr.h"
-#include "vbdr_device.h"
+#include "vbdr_internal.h"
 
 using namespace vbdr;
-
-struct vbdr_sketch {
-  int device;
-  int n_cu;
-  uint64_t m;
-  uint32_t g, b, L, k;
-  int layout;
-  uint32_t A0, A1;
-  uint64_t t;
-  uint64_t mstride, wstride;
-  uint8_t* dr;
-  uint32_t* seen;
-  uint8_t* reg;
-  unsigned long long* hist;
-  uint32_t* s1;
-  uint8_t* reg4;                 // registers as nibbles, min(reg, 15); 15 = read reg
-  int parts;                     // XCD partitions of the estimate (1 = direct gather)
-  unsigned long long* part_u;    // [parts][kPartChunk] partial harmonic sums
-  uint32_t* part_v;              // [parts][kPartChunk] partial zero counts
-  uint64_t bytes;
-  vbdr_tuning tune;
-};
 
 static vbdr_tuning default_tuning(int layout) {
   vbdr_tuning t;
   t.scan_test_first = layout == VBDR_LAYOUT_FAST ? 1 : 2;
   t.scan_blocks_per_cu = 16;
   t.est_blocks_per_cu = 32;
+  t.scan_binned = 1;
   return t;
 }
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const char* fmt, ...) {
+int vbdr_fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -71,23 +49,7 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define VBDR_HIP(call)                                                                    \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess) return fail(VBDR_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
-
-#define VBDR_LAUNCHED(name)                                                                    \
-  do {                                                                                         \
-    hipError_t e_ = hipGetLastError();                                                         \
-    if (e_ != hipSuccess) return fail(VBDR_EHIP, "launch of %s: %s", name, hipGetErrorString(e_)); \
-  } while (0)
-
-constexpr uint64_t kPad = 4096;          // BDR padding granule of a plane
-constexpr uint32_t kStageMaxG = 8192;    // s1 staged in LDS up to 32 KiB
-constexpr uint32_t kCusPerXcd = 32;      // gfx950: 8 XCDs x 32 CUs
-constexpr uint64_t kPartMinM = 1ull << 22;  // pools whose registers outgrow one XCD's L2
-constexpr uint32_t kPartChunk = 1u << 17;   // hosts per partitioned-estimate pass
+namespace {
 
 // ----------------------------------------------------------------- init
 
@@ -138,18 +100,130 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const u32x2* __restrict__ p
 #pragma unroll
     for (int u = 0; u < kScanUnroll; ++u) {
       const uint64_t i = base + (uint64_t)u * kScanBlock;
+      if (i < n) scan_pair<FAST, TEST>(p[u].x, p[u].y, s1, b, A1, m, dr, mstride, seen, wstride);
+    }
+  }
+}
+
+// ---------------------------------------------------- scan, XCD-binned
+// For large pools the direct scan is bound by random accesses that miss
+// every L2.  Pass 1 streams the pairs, hashes each once and writes a 4-byte
+// record (pidx << 5 | LBP1-1) into one of 8 bins by pool range (the top
+// bits of the getPhyIdx hash, as in the partitioned estimate); a block stages
+// its records in LDS sorted by bin so that each bin receives one contiguous
+// run.  Pass 2 runs bin x on the workgroups dispatched to XCD x (b mod 8), so
+// the test-and-set traffic of a pool range stays in one L2.  A record that
+// finds its bin full is applied directly in pass 1, so any skew is correct.
+
+constexpr int kBinBlock = 256;
+constexpr int kBinPerThread = 16;
+constexpr int kBinTile = kBinBlock * kBinPerThread;
+
+__global__ void k_bin_reset(uint32_t* __restrict__ fill) {
+  if (threadIdx.x < 8) fill[threadIdx.x] = 0;
+}
+
+template <bool FAST, bool STAGE, bool TEST>
+__global__ __launch_bounds__(kBinBlock) void k_scan_bin(const u32x2* __restrict__ pairs, uint64_t n,
+                                                        const uint32_t* __restrict__ s1g, uint32_t g, uint32_t b,
+                                                        uint32_t A1, uint32_t m, uint32_t* __restrict__ bins,
+                                                        uint32_t* __restrict__ fill, uint8_t* __restrict__ dr,
+                                                        uint64_t mstride, uint32_t* __restrict__ seen,
+                                                        uint64_t wstride) {
+  extern __shared__ uint32_t s1_lds[];
+  __shared__ uint32_t rec_lds[kBinTile];
+  __shared__ uint32_t cnt[8], start[9], base[8];
+  const uint32_t* s1 = s1g;
+  if constexpr (STAGE) {
+    for (uint32_t i = threadIdx.x; i < g; i += kBinBlock) s1_lds[i] = s1g[i];
+    s1 = s1_lds;
+  }
+  for (uint64_t tile = (uint64_t)blockIdx.x * kBinTile; tile < n; tile += (uint64_t)gridDim.x * kBinTile) {
+    if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t rec[kBinPerThread], slot[kBinPerThread];
+    u32x2 p[kBinPerThread];
+#pragma unroll
+    for (int u = 0; u < kBinPerThread; ++u) {
+      const uint64_t i = tile + (uint64_t)u * kBinBlock + threadIdx.x;
+      p[u] = i < n ? __builtin_nontemporal_load(pairs + i) : u32x2{0u, 0u};
+    }
+#pragma unroll
+    for (int u = 0; u < kBinPerThread; ++u) {
+      const uint64_t i = tile + (uint64_t)u * kBinBlock + threadIdx.x;
+      slot[u] = 0xFFFFFFFFu;
       if (i < n) {
         uint32_t vidx, rho;
         bip_map(p[u].y, A1, b, vidx, rho);
-        const uint32_t pidx = reduce_m(mm3(p[u].x, s1[vidx]), m);  // getPhyIdx (Alg. 3)
+        const uint32_t hh = mm3(p[u].x, s1[vidx]);
+        rec[u] = (reduce_m(hh, m) << 5) | (rho - 1);
+        const uint32_t x = hh >> 29;
+        slot[u] = (x << 24) | atomicAdd(&cnt[x], 1u);  // rank within the bin (< 2^13)
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      start[0] = 0;
+      for (int x = 0; x < 8; ++x) start[x + 1] = start[x] + cnt[x];
+    }
+    if (threadIdx.x < 8) base[threadIdx.x] = atomicAdd(&fill[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kBinPerThread; ++u)
+      if (slot[u] != 0xFFFFFFFFu) rec_lds[start[slot[u] >> 24] + (slot[u] & 0xFFFFFFu)] = rec[u];
+    __syncthreads();
+    const uint32_t total = start[8];
+    for (uint32_t j = threadIdx.x; j < total; j += kBinBlock) {
+      uint32_t x = 0;
+      while (j >= start[x + 1]) ++x;
+      const uint32_t r = rec_lds[j];
+      const uint32_t pos = base[x] + (j - start[x]);
+      if (pos < kBinCap) {
+        bins[(uint64_t)x * kBinCap + pos] = r;
+      } else {  // bin full: apply the update here
+        const uint32_t pidx = r >> 5, plane = r & 31u;
         if constexpr (FAST) {
-          uint32_t* w = seen + (uint64_t)(rho - 1) * wstride + (pidx >> 5);
+          uint32_t* w = seen + (uint64_t)plane * wstride + (pidx >> 5);
           const uint32_t bit = 1u << (pidx & 31);
           if (!TEST || !(*w & bit)) atomicOr(w, bit);
         } else {
-          uint8_t* d = dr + (uint64_t)(rho - 1) * mstride + pidx;
+          uint8_t* d = dr + (uint64_t)plane * mstride + pidx;
           if (!TEST || *d != 0) *d = 0;
         }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool FAST, bool TEST>
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint32_t* __restrict__ bins,
+                                                           const uint32_t* __restrict__ fill, uint8_t* __restrict__ dr,
+                                                           uint64_t mstride, uint32_t* __restrict__ seen,
+                                                           uint64_t wstride) {
+  const uint32_t x = blockIdx.x & 7u;  // workgroups are dispatched round-robin over the 8 XCDs
+  const uint32_t per = gridDim.x >> 3;
+  const uint32_t count = fill[x] < kBinCap ? fill[x] : kBinCap;
+  const uint32_t* rx = bins + (uint64_t)x * kBinCap;
+  for (uint32_t j0 = (blockIdx.x >> 3) * kScanBlock * kScanUnroll + threadIdx.x; j0 < count;
+       j0 += per * kScanBlock * kScanUnroll) {
+    uint32_t r[kScanUnroll];
+#pragma unroll
+    for (int u = 0; u < kScanUnroll; ++u) {
+      const uint32_t j = j0 + u * kScanBlock;
+      r[u] = j < count ? __builtin_nontemporal_load(rx + j) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kScanUnroll; ++u) {
+      if (j0 + u * kScanBlock >= count) continue;  // every 32-bit value is a valid record
+      const uint32_t pidx = r[u] >> 5, plane = r[u] & 31u;
+      if constexpr (FAST) {
+        uint32_t* w = seen + (uint64_t)plane * wstride + (pidx >> 5);
+        const uint32_t bit = 1u << (pidx & 31);
+        if (!TEST || !(*w & bit)) atomicOr(w, bit);
+      } else {
+        uint8_t* d = dr + (uint64_t)plane * mstride + pidx;
+        if (!TEST || *d != 0) *d = 0;
       }
     }
   }
@@ -178,52 +252,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_advance(uint8_t* __restrict__ dr,
   if (lane < kBins) lh[wave][lane] = 0;
   __syncthreads();
   const uint64_t base = ((uint64_t)blockIdx.x * kAdvBlock + threadIdx.x) * kAdvBpt;
-  const uint32_t gt_bias = swar_gt_bias(thr);
-  // Four DR bytes per 32-bit word: R = registers found so far, M = 0xFF for
-  // BDRs whose register is already known (planes are visited downwards).
-  uint32_t R[4] = {0, 0, 0, 0}, M[4] = {0, 0, 0, 0};
-  uint32_t folded = 0;
-  const uint8_t* top = dr + (uint64_t)(L - 1) * mstride + base;
-  u32x4 dn = *reinterpret_cast<const u32x4*>(top);
-  uint32_t sn = 0;
-  if constexpr (FAST) sn = seen[(uint64_t)(L - 1) * wstride + (base >> 5)];
-  for (int i = (int)L; i >= 1; --i) {
-    const u32x4 d = dn;
-    const uint32_t s = sn;
-    if (i > 1) {  // prefetch the next plane down
-      dn = *reinterpret_cast<const u32x4*>(dr + (uint64_t)(i - 2) * mstride + base);
-      if constexpr (FAST) sn = seen[(uint64_t)(i - 2) * wstride + (base >> 5)];
-    }
-    uint32_t fold = 0;
-    if constexpr (FAST) {
-      const uint32_t bits = (s >> (base & 31)) & 0xFFFFu;
-      fold = bits & ~folded;  // only the slice's highest LBP1 is recorded
-      folded |= bits;
-    }
-    u32x4 nd;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const uint32_t x = d[w];
-      uint32_t y = swar_sat_inc(x);                               // SlideDR
-      if constexpr (FAST) y &= ~swar_nibble_to_bytes((fold >> (4 * w)) & 0xFu);  // SetDR
-      const uint32_t act = swar_le_mask(FAST ? y : x, gt_bias);  // IsActiveDR
-      R[w] |= act & ~M[w] & ((uint32_t)i * 0x01010101u);
-      M[w] |= act;
-      nd[w] = y;
-    }
-    *reinterpret_cast<u32x4*>(dr + (uint64_t)(i - 1) * mstride + base) = nd;
-  }
-  if constexpr (FAST) {
-    // The two threads sharing a bsLBP1 word are adjacent lanes of one wave
-    // and have both consumed it above; the even one clears it.
-    if ((base & 31) == 0)
-      for (uint32_t i = 0; i < L; ++i) seen[(uint64_t)i * wstride + (base >> 5)] = 0;
-  }
-  *reinterpret_cast<u32x4*>(reg + base) = u32x4{R[0], R[1], R[2], R[3]};
-  uint64_t nib = 0;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) nib |= (uint64_t)swar_pack_nibbles(R[w]) << (16 * w);
-  *reinterpret_cast<uint64_t*>(reg4 + base / 2) = nib;
+  uint32_t R[4];
+  advance_group<FAST>(dr, mstride, seen, wstride, reg, reg4, base, L, swar_gt_bias(thr), R);
 #pragma unroll
   for (int j = 0; j < kAdvBpt; ++j)
     if (base + j < m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
@@ -244,22 +274,6 @@ __global__ __launch_bounds__(kAdvBlock) void k_advance(uint8_t* __restrict__ dr,
 
 constexpr int kEstBlock = 256;
 constexpr int kEstWaves = kEstBlock / 64;
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint32_t olo = __shfl_xor(lo, off), ohi = __shfl_xor(hi, off);
-    const uint64_t s = ((uint64_t)hi << 32 | lo) + ((uint64_t)ohi << 32 | olo);
-    lo = (uint32_t)s, hi = (uint32_t)(s >> 32);
-  }
-  return (uint64_t)hi << 32 | lo;
-}
-
-__device__ __forceinline__ double noise_removed(double Es, double Em, double m, double g) {
-#pragma clang fp contract(off)
-  return (m * Es - g * Em) / (m - g);
-}
 
 constexpr int kEstUnroll = 8;  // gathers in flight per lane
 
@@ -338,15 +352,17 @@ __global__ __launch_bounds__(kEstBlock) void k_estimate(const uint32_t* __restri
 // per-range partial sums are combined by k_estimate_final.  The sums are
 // exact integers, so the result equals the direct kernel's bit for bit.
 
-template <bool STAGE>
+template <bool STAGE, bool HIST>
 __global__ __launch_bounds__(kEstBlock) void k_estimate_part(const uint32_t* __restrict__ hosts, uint32_t nh,
                                                              const uint32_t* __restrict__ s1g, uint32_t g, uint32_t m,
                                                              const uint8_t* __restrict__ reg,
                                                              const uint8_t* __restrict__ reg4, uint32_t parts,
                                                              uint32_t part_shift,
                                                              unsigned long long* __restrict__ part_u,
-                                                             uint32_t* __restrict__ part_v) {
+                                                             uint32_t* __restrict__ part_v,
+                                                             uint32_t* __restrict__ hout) {
   extern __shared__ uint32_t s1_lds[];
+  __shared__ uint32_t lh[kEstWaves][kBins];
   const uint32_t* s1 = s1g;
   if constexpr (STAGE) {
     for (uint32_t i = threadIdx.x; i < g; i += kEstBlock) s1_lds[i] = s1g[i];
@@ -358,6 +374,11 @@ __global__ __launch_bounds__(kEstBlock) void k_estimate_part(const uint32_t* __r
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (uint32_t h = (blockIdx.x / parts) * kEstWaves + wave; h < nh; h += tiles * kEstWaves) {
     const uint32_t kmix = mm3_key(hosts[h]);
+    if constexpr (HIST) {
+      if (lane < kBins) lh[wave][lane] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
     uint64_t U = 0;
     uint32_t V = 0;
     for (uint32_t i0 = lane; i0 < g; i0 += 64 * kEstUnroll) {
@@ -372,15 +393,23 @@ __global__ __launch_bounds__(kEstBlock) void k_estimate_part(const uint32_t* __r
             const uint32_t r = nib < 15u ? nib : (uint32_t)reg[p];
             U += 1ull << (32 - r);
             V += r == 0;
+            if constexpr (HIST) atomicAdd(&lh[wave][r], 1u);
           }
         }
       }
     }
-    U = wave_sum_u64(U);
-    V = (uint32_t)wave_sum_u64(V);
-    if (lane == 0) {
-      part_u[(uint64_t)x * kPartChunk + h] = U;
-      part_v[(uint64_t)x * kPartChunk + h] = V;
+    if constexpr (HIST) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (lane < kBins) hout[((uint64_t)x * kLearnChunk + h) * kBins + lane] = lh[wave][lane];
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      U = wave_sum_u64(U);
+      V = (uint32_t)wave_sum_u64(V);
+      if (lane == 0) {
+        part_u[(uint64_t)x * kPartChunk + h] = U;
+        part_v[(uint64_t)x * kPartChunk + h] = V;
+      }
     }
   }
 }
@@ -418,12 +447,6 @@ __global__ void k_pack_reg4(const uint8_t* __restrict__ reg, uint8_t* __restrict
 
 // ------------------------------------------------------------- helpers
 
-int check_device(const vbdr_sketch* sk) {
-  int cur = -1;
-  VBDR_HIP(hipGetDevice(&cur));
-  if (cur != sk->device) return fail(VBDR_EINVAL, "sketch lives on device %d but device %d is current", sk->device, cur);
-  return VBDR_OK;
-}
 
 uint32_t grid_cap(const vbdr_sketch* sk, uint64_t want, uint32_t per_cu) {
   const uint64_t cap = (uint64_t)sk->n_cu * per_cu;
@@ -460,6 +483,38 @@ int init_state(vbdr_sketch* sk, hipStream_t st) {
 
 }  // namespace
 
+int vbdr_check_device(const vbdr_sketch* sk) {
+  int cur = -1;
+  VBDR_HIP(hipGetDevice(&cur));
+  if (cur != sk->device)
+    return vbdr_fail(VBDR_EINVAL, "sketch lives on device %d but device %d is current", sk->device, cur);
+  return VBDR_OK;
+}
+
+int vbdr_hist_pass(vbdr_sketch* sk, const uint32_t* hosts_dev, uint32_t nh, hipStream_t st) {
+  if (nh == 0) return VBDR_OK;
+  if (nh > kLearnChunk) return vbdr_fail(VBDR_EINVAL, "histogram pass of %u hosts exceeds %u", nh, kLearnChunk);
+  const bool stage = sk->g <= kStageMaxG;
+  const size_t lds = stage ? (size_t)sk->g * 4 : 0;
+  if (sk->parts > 1) {
+    const uint32_t parts = (uint32_t)sk->parts, shift = parts == 8 ? 29u : 30u;
+    const uint64_t want = (nh + kEstWaves - 1) / kEstWaves;
+    const uint64_t cap = (uint64_t)sk->n_cu * sk->tune.est_blocks_per_cu / parts;
+    const uint32_t tiles = (uint32_t)(want < cap ? want : (cap ? cap : 1));
+    auto kern = stage ? k_estimate_part<true, true> : k_estimate_part<false, true>;
+    hipLaunchKernelGGL(kern, dim3(tiles * parts), dim3(kEstBlock), lds, st, hosts_dev, nh, sk->s1, sk->g,
+                       (uint32_t)sk->m, sk->reg, sk->reg4, parts, shift, sk->part_u, sk->part_v, sk->hist_ws);
+    VBDR_LAUNCHED("k_estimate_part(hist)");
+  } else {
+    const uint32_t grid = grid_cap(sk, (nh + kEstWaves - 1) / kEstWaves, sk->tune.est_blocks_per_cu);
+    auto kern = stage ? k_estimate<true, true> : k_estimate<false, true>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kEstBlock), lds, st, hosts_dev, (uint64_t)nh, sk->s1, sk->g,
+                       (uint32_t)sk->m, sk->reg, sk->hist, sk->est_ws, nullptr, sk->hist_ws);
+    VBDR_LAUNCHED("k_estimate(hist)");
+  }
+  return VBDR_OK;
+}
+
 // ================================================================= C ABI
 
 extern "C" {
@@ -467,20 +522,20 @@ extern "C" {
 const char* vbdr_last_error(void) { return g_err.c_str(); }
 
 int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out) {
-  if (!out) return fail(VBDR_EINVAL, "out is NULL");
+  if (!out) return vbdr_fail(VBDR_EINVAL, "out is NULL");
   *out = nullptr;
-  if (g < 2 || g > 65536u || (g & (g - 1))) return fail(VBDR_EINVAL, "g=%u must be a power of two in [2, 65536]", g);
-  if (m <= g || m >= (1ull << 32)) return fail(VBDR_EINVAL, "m=%llu must satisfy g < m < 2^32", (unsigned long long)m);
-  if (k < 1 || k > 254) return fail(VBDR_EINVAL, "k=%u must be in [1, 254]", k);
-  if (layout != VBDR_LAYOUT_FAST && layout != VBDR_LAYOUT_SMALL) return fail(VBDR_EINVAL, "unknown layout %d", layout);
+  if (g < 2 || g > 65536u || (g & (g - 1))) return vbdr_fail(VBDR_EINVAL, "g=%u must be a power of two in [2, 65536]", g);
+  if (m <= g || m >= (1ull << 32)) return vbdr_fail(VBDR_EINVAL, "m=%llu must satisfy g < m < 2^32", (unsigned long long)m);
+  if (k < 1 || k > 254) return vbdr_fail(VBDR_EINVAL, "k=%u must be in [1, 254]", k);
+  if (layout != VBDR_LAYOUT_FAST && layout != VBDR_LAYOUT_SMALL) return vbdr_fail(VBDR_EINVAL, "unknown layout %d", layout);
   vbdr_sketch* sk = new (std::nothrow) vbdr_sketch();
-  if (!sk) return fail(VBDR_ENOMEM, "host allocation failed");
+  if (!sk) return vbdr_fail(VBDR_ENOMEM, "host allocation failed");
   std::memset(sk, 0, sizeof(*sk));
   int rc = VBDR_OK;
   do {
-    if (hipGetDevice(&sk->device) != hipSuccess) { rc = fail(VBDR_EHIP, "hipGetDevice failed"); break; }
+    if (hipGetDevice(&sk->device) != hipSuccess) { rc = vbdr_fail(VBDR_EHIP, "hipGetDevice failed"); break; }
     if (hipDeviceGetAttribute(&sk->n_cu, hipDeviceAttributeMultiprocessorCount, sk->device) != hipSuccess) {
-      rc = fail(VBDR_EHIP, "hipDeviceGetAttribute failed");
+      rc = vbdr_fail(VBDR_EHIP, "hipDeviceGetAttribute failed");
       break;
     }
     sk->m = m, sk->g = g, sk->k = k, sk->layout = layout;
@@ -497,25 +552,31 @@ int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_
     const int xcds = sk->n_cu / (int)kCusPerXcd;
     sk->parts = (m >= kPartMinM && xcds >= 8) ? 8 : (m >= kPartMinM && xcds >= 4) ? 4 : 1;
     const uint64_t part_bytes = sk->parts > 1 ? (uint64_t)sk->parts * kPartChunk * (8 + 4) : 0;
+    // the binned scan needs 8 XCDs and pidx < 2^27 to pack its records
+    const uint64_t bin_bytes = (sk->parts == 8 && m <= kBinMaxM) ? 8ull * kBinCap * 4 : 0;
     if (hipMalloc(&sk->dr, dr_bytes) != hipSuccess || hipMalloc(&sk->reg, sk->mstride) != hipSuccess ||
         hipMalloc(&sk->reg4, sk->mstride / 2) != hipSuccess ||
         hipMalloc(&sk->hist, 64 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&sk->s1, (uint64_t)g * 4) != hipSuccess ||
         (seen_bytes && hipMalloc(&sk->seen, seen_bytes) != hipSuccess) ||
         (part_bytes && hipMalloc(&sk->part_u, (uint64_t)sk->parts * kPartChunk * 8) != hipSuccess) ||
-        (part_bytes && hipMalloc(&sk->part_v, (uint64_t)sk->parts * kPartChunk * 4) != hipSuccess)) {
+        (part_bytes && hipMalloc(&sk->part_v, (uint64_t)sk->parts * kPartChunk * 4) != hipSuccess) ||
+        hipMalloc(&sk->hist_ws, (uint64_t)sk->parts * kLearnChunk * kBins * 4) != hipSuccess ||
+        hipMalloc(&sk->est_ws, (uint64_t)kLearnChunk * 4) != hipSuccess ||
+        (bin_bytes && hipMalloc(&sk->bins, bin_bytes) != hipSuccess) ||
+        (bin_bytes && hipMalloc(&sk->bin_fill, 64) != hipSuccess)) {
       (void)hipGetLastError();
-      rc = fail(VBDR_ENOMEM, "device allocation of %llu bytes failed",
+      rc = vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed",
                 (unsigned long long)(dr_bytes + seen_bytes + sk->mstride * 3 / 2 + part_bytes));
       break;
     }
     sk->bytes = dr_bytes + seen_bytes + sk->mstride * 3 / 2 + 64 * sizeof(unsigned long long) + (uint64_t)g * 4 +
-                part_bytes;
+                part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + bin_bytes;
     hipStream_t st = nullptr;
     if ((rc = init_state(sk, st)) != VBDR_OK) break;
     hipLaunchKernelGGL(k_seeds, dim3((g + 255) / 256), dim3(256), 0, st, sk->s1, g, sk->A0);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
-      rc = fail(VBDR_EHIP, "sketch initialisation failed");
+      rc = vbdr_fail(VBDR_EHIP, "sketch initialisation failed");
       break;
     }
   } while (0);
@@ -545,30 +606,36 @@ void vbdr_sketch_destroy(vbdr_sketch* sk) {
   if (sk->reg4) (void)hipFree(sk->reg4);
   if (sk->part_u) (void)hipFree(sk->part_u);
   if (sk->part_v) (void)hipFree(sk->part_v);
+  if (sk->hist_ws) (void)hipFree(sk->hist_ws);
+  if (sk->est_ws) (void)hipFree(sk->est_ws);
+  if (sk->bins) (void)hipFree(sk->bins);
+  if (sk->bin_fill) (void)hipFree(sk->bin_fill);
   if (prev >= 0 && prev != sk->device) (void)hipSetDevice(prev);
   delete sk;
 }
 
 int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
-  if (!sk || !tuning) return fail(VBDR_EINVAL, "NULL argument");
-  if (tuning->scan_test_first < 0 || tuning->scan_test_first > 2) return fail(VBDR_EINVAL, "scan_test_first must be 0, 1 or 2");
+  if (!sk || !tuning) return vbdr_fail(VBDR_EINVAL, "NULL argument");
+  if (tuning->scan_test_first < 0 || tuning->scan_test_first > 2) return vbdr_fail(VBDR_EINVAL, "scan_test_first must be 0, 1 or 2");
+  if (tuning->scan_binned < 0 || tuning->scan_binned > 2) return vbdr_fail(VBDR_EINVAL, "scan_binned must be 0, 1 or 2");
   if (tuning->scan_blocks_per_cu > 64 || tuning->est_blocks_per_cu > 64)
-    return fail(VBDR_EINVAL, "blocks per CU must be at most 64");
+    return vbdr_fail(VBDR_EINVAL, "blocks per CU must be at most 64");
   sk->tune = default_tuning(sk->layout);
   if (tuning->scan_test_first) sk->tune.scan_test_first = tuning->scan_test_first;
   if (tuning->scan_blocks_per_cu) sk->tune.scan_blocks_per_cu = tuning->scan_blocks_per_cu;
   if (tuning->est_blocks_per_cu) sk->tune.est_blocks_per_cu = tuning->est_blocks_per_cu;
+  if (tuning->scan_binned) sk->tune.scan_binned = tuning->scan_binned;
   return VBDR_OK;
 }
 
 int vbdr_sketch_get_tuning(const vbdr_sketch* sk, vbdr_tuning* tuning) {
-  if (!sk || !tuning) return fail(VBDR_EINVAL, "NULL argument");
+  if (!sk || !tuning) return vbdr_fail(VBDR_EINVAL, "NULL argument");
   *tuning = sk->tune;
   return VBDR_OK;
 }
 
 int vbdr_sketch_info(const vbdr_sketch* sk, vbdr_info* out) {
-  if (!sk || !out) return fail(VBDR_EINVAL, "NULL argument");
+  if (!sk || !out) return vbdr_fail(VBDR_EINVAL, "NULL argument");
   out->m = sk->m, out->g = sk->g, out->b = sk->b, out->L = sk->L, out->k = sk->k;
   out->layout = sk->layout, out->A0 = sk->A0, out->A1 = sk->A1, out->t = sk->t;
   out->state_bytes = sk->bytes;
@@ -576,12 +643,12 @@ int vbdr_sketch_info(const vbdr_sketch* sk, vbdr_info* out) {
 }
 
 int vbdr_scan_slice(vbdr_sketch* sk, const uint32_t* pairs_dev, uint64_t n, void* stream) {
-  if (!sk) return fail(VBDR_EINVAL, "sketch is NULL");
+  if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
   if (n == 0) return VBDR_OK;
-  if (!pairs_dev) return fail(VBDR_EINVAL, "pairs_dev is NULL");
-  if (reinterpret_cast<uintptr_t>(pairs_dev) & 7u) return fail(VBDR_EINVAL, "pairs_dev must be 8-byte aligned");
-  if (n >= (1ull << 40)) return fail(VBDR_EINVAL, "n=%llu too large", (unsigned long long)n);
-  if (int rc = check_device(sk)) return rc;
+  if (!pairs_dev) return vbdr_fail(VBDR_EINVAL, "pairs_dev is NULL");
+  if (reinterpret_cast<uintptr_t>(pairs_dev) & 7u) return vbdr_fail(VBDR_EINVAL, "pairs_dev must be 8-byte aligned");
+  if (n >= (1ull << 40)) return vbdr_fail(VBDR_EINVAL, "n=%llu too large", (unsigned long long)n);
+  if (int rc = vbdr_check_device(sk)) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool stage = sk->g <= kStageMaxG;
   const size_t lds = stage ? (size_t)sk->g * 4 : 0;
@@ -590,6 +657,33 @@ int vbdr_scan_slice(vbdr_sketch* sk, const uint32_t* pairs_dev, uint64_t n, void
   const u32x2* p = reinterpret_cast<const u32x2*>(pairs_dev);
   const uint32_t m32 = (uint32_t)sk->m;
   const bool test = sk->tune.scan_test_first == 1;
+  if (sk->bins && sk->tune.scan_binned == 1) {
+    decltype(&k_scan_bin<true, true, true>) bin;
+    decltype(&k_scan_apply<true, true>) apply;
+    if (sk->layout == VBDR_LAYOUT_FAST) {
+      bin = stage ? (test ? k_scan_bin<true, true, true> : k_scan_bin<true, true, false>)
+                  : (test ? k_scan_bin<true, false, true> : k_scan_bin<true, false, false>);
+      apply = test ? k_scan_apply<true, true> : k_scan_apply<true, false>;
+    } else {
+      bin = stage ? (test ? k_scan_bin<false, true, true> : k_scan_bin<false, true, false>)
+                  : (test ? k_scan_bin<false, false, true> : k_scan_bin<false, false, false>);
+      apply = test ? k_scan_apply<false, true> : k_scan_apply<false, false>;
+    }
+    const uint32_t apply_grid = 8u * (uint32_t)(sk->n_cu / 8) * sk->tune.scan_blocks_per_cu;
+    for (uint64_t c = 0; c < n; c += kBinChunk) {
+      const uint64_t nc = n - c < kBinChunk ? n - c : kBinChunk;
+      hipLaunchKernelGGL(k_bin_reset, dim3(1), dim3(64), 0, st, sk->bin_fill);
+      VBDR_LAUNCHED("k_bin_reset");
+      const uint32_t grid = grid_cap(sk, (nc + kBinTile - 1) / kBinTile, 4);
+      hipLaunchKernelGGL(bin, dim3(grid), dim3(kBinBlock), lds, st, p + c, nc, sk->s1, sk->g, sk->b, sk->A1, m32,
+                         sk->bins, sk->bin_fill, sk->dr, sk->mstride, sk->seen, sk->wstride);
+      VBDR_LAUNCHED("k_scan_bin");
+      hipLaunchKernelGGL(apply, dim3(apply_grid), dim3(kScanBlock), 0, st, sk->bins, sk->bin_fill, sk->dr, sk->mstride,
+                         sk->seen, sk->wstride);
+      VBDR_LAUNCHED("k_scan_apply");
+    }
+    return VBDR_OK;
+  }
   decltype(&k_scan<true, true, true>) kern;
   if (sk->layout == VBDR_LAYOUT_FAST)
     kern = stage ? (test ? k_scan<true, true, true> : k_scan<true, true, false>)
@@ -604,8 +698,8 @@ int vbdr_scan_slice(vbdr_sketch* sk, const uint32_t* pairs_dev, uint64_t n, void
 }
 
 int vbdr_advance_slice(vbdr_sketch* sk, void* stream) {
-  if (!sk) return fail(VBDR_EINVAL, "sketch is NULL");
-  if (int rc = check_device(sk)) return rc;
+  if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
+  if (int rc = vbdr_check_device(sk)) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(64), 0, st, sk->hist, 0ull);
   VBDR_LAUNCHED("k_hist_reset");
@@ -620,25 +714,25 @@ int vbdr_advance_slice(vbdr_sketch* sk, void* stream) {
 
 int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, float* out_dev, double* raw_es_dev,
                      uint32_t* hist_dev, void* stream) {
-  if (!sk) return fail(VBDR_EINVAL, "sketch is NULL");
+  if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
   if (n_hosts == 0) return VBDR_OK;
-  if (!hosts_dev || !out_dev) return fail(VBDR_EINVAL, "hosts_dev and out_dev must not be NULL");
-  if (n_hosts >= (1ull << 40)) return fail(VBDR_EINVAL, "n_hosts too large");
-  if (int rc = check_device(sk)) return rc;
+  if (!hosts_dev || !out_dev) return vbdr_fail(VBDR_EINVAL, "hosts_dev and out_dev must not be NULL");
+  if (n_hosts >= (1ull << 40)) return vbdr_fail(VBDR_EINVAL, "n_hosts too large");
+  if (int rc = vbdr_check_device(sk)) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool stage = sk->g <= kStageMaxG;
   const bool extra = raw_es_dev || hist_dev;
   const size_t lds = stage ? (size_t)sk->g * 4 : 0;
   if (sk->parts > 1 && !extra) {
     const uint32_t parts = (uint32_t)sk->parts, shift = parts == 8 ? 29u : 30u;
-    auto kern = stage ? k_estimate_part<true> : k_estimate_part<false>;
+    auto kern = stage ? k_estimate_part<true, false> : k_estimate_part<false, false>;
     for (uint64_t c = 0; c < n_hosts; c += kPartChunk) {
       const uint32_t nh = (uint32_t)(n_hosts - c < kPartChunk ? n_hosts - c : kPartChunk);
       const uint64_t want = (nh + kEstWaves - 1) / kEstWaves;
       const uint64_t cap = (uint64_t)sk->n_cu * sk->tune.est_blocks_per_cu / parts;
       const uint32_t tiles = (uint32_t)(want < cap ? want : (cap ? cap : 1));
       hipLaunchKernelGGL(kern, dim3(tiles * parts), dim3(kEstBlock), lds, st, hosts_dev + c, nh, sk->s1, sk->g,
-                         (uint32_t)sk->m, sk->reg, sk->reg4, parts, shift, sk->part_u, sk->part_v);
+                         (uint32_t)sk->m, sk->reg, sk->reg4, parts, shift, sk->part_u, sk->part_v, nullptr);
       VBDR_LAUNCHED("k_estimate_part");
       hipLaunchKernelGGL(k_estimate_final, dim3((nh + 255) / 256), dim3(256), 0, st, nh, sk->g, (uint32_t)sk->m,
                          parts, sk->hist, sk->part_u, sk->part_v, out_dev + c);
@@ -661,8 +755,8 @@ int vbdr_estimate(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, 
 
 int vbdr_export_state(vbdr_sketch* sk, uint8_t* dr_host, uint32_t* bs_host, uint8_t* reg_host, uint64_t* hist_host,
                       void* stream) {
-  if (!sk) return fail(VBDR_EINVAL, "sketch is NULL");
-  if (int rc = check_device(sk)) return rc;
+  if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
+  if (int rc = vbdr_check_device(sk)) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   VBDR_HIP(hipStreamSynchronize(st));
   const uint64_t m = sk->m, L = sk->L;
@@ -690,22 +784,22 @@ int vbdr_export_state(vbdr_sketch* sk, uint8_t* dr_host, uint32_t* bs_host, uint
 
 int vbdr_import_state(vbdr_sketch* sk, const uint8_t* dr_host, const uint32_t* bs_host, const uint8_t* reg_host,
                       const uint64_t* hist_host, uint64_t t, void* stream) {
-  if (!sk) return fail(VBDR_EINVAL, "sketch is NULL");
-  if (!dr_host || !reg_host || !hist_host) return fail(VBDR_EINVAL, "dr_host, reg_host and hist_host are required");
+  if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
+  if (!dr_host || !reg_host || !hist_host) return vbdr_fail(VBDR_EINVAL, "dr_host, reg_host and hist_host are required");
   if (bs_host && !sk->seen) {
     for (uint64_t p = 0; p < sk->m; ++p)
-      if (bs_host[p]) return fail(VBDR_EINVAL, "small-layout sketch cannot hold bsLBP1 bits");
+      if (bs_host[p]) return vbdr_fail(VBDR_EINVAL, "small-layout sketch cannot hold bsLBP1 bits");
   }
   uint64_t total = 0;
   for (int r = 0; r < kBins; ++r) total += hist_host[r];
-  if (total != sk->m) return fail(VBDR_EINVAL, "histogram does not sum to m");
+  if (total != sk->m) return vbdr_fail(VBDR_EINVAL, "histogram does not sum to m");
   const uint64_t m = sk->m, L = sk->L;
   for (uint64_t p = 0; p < m; ++p)
-    if (reg_host[p] > L) return fail(VBDR_EINVAL, "register %u of BDR %llu exceeds L", reg_host[p], (unsigned long long)p);
+    if (reg_host[p] > L) return vbdr_fail(VBDR_EINVAL, "register %u of BDR %llu exceeds L", reg_host[p], (unsigned long long)p);
   if (bs_host)
     for (uint64_t p = 0; p < m; ++p)
-      if (L < 32 && (bs_host[p] >> L)) return fail(VBDR_EINVAL, "bsLBP1 of BDR %llu has bits above L", (unsigned long long)p);
-  if (int rc = check_device(sk)) return rc;
+      if (L < 32 && (bs_host[p] >> L)) return vbdr_fail(VBDR_EINVAL, "bsLBP1 of BDR %llu has bits above L", (unsigned long long)p);
+  if (int rc = vbdr_check_device(sk)) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   VBDR_HIP(hipStreamSynchronize(st));
   {

@@ -115,4 +115,133 @@ __device__ __forceinline__ double hll_estimate(uint64_t U, uint64_t V, double q)
   return E;
 }
 
+// ---- per-item bodies shared by the single-sketch and the batched kernels ----
+
+// Scan one pair (Alg. 7 / Alg. 9 with the hashing of Alg. 4 and getPhyIdx of
+// Alg. 3).  Fast layout: set bit pidx of bsLBP1 bit-plane LBP1-1 with a
+// device-scope atomic OR; small layout: store 0 into DR[LBP1] of BDR pidx.
+// TEST: read first and skip an update that is already made.
+template <bool FAST, bool TEST>
+__device__ __forceinline__ void scan_pair(uint32_t aip, uint32_t bip, const uint32_t* s1, uint32_t b, uint32_t A1,
+                                          uint32_t m, uint8_t* dr, uint64_t mstride, uint32_t* seen,
+                                          uint64_t wstride) {
+  uint32_t vidx, rho;
+  bip_map(bip, A1, b, vidx, rho);
+  const uint32_t pidx = reduce_m(mm3(aip, s1[vidx]), m);
+  if constexpr (FAST) {
+    uint32_t* w = seen + (uint64_t)(rho - 1) * wstride + (pidx >> 5);
+    const uint32_t bit = 1u << (pidx & 31);
+    if (!TEST || !(*w & bit)) atomicOr(w, bit);
+  } else {
+    uint8_t* d = dr + (uint64_t)(rho - 1) * mstride + pidx;
+    if (!TEST || *d != 0) *d = 0;
+  }
+}
+
+// Advance 16 consecutive BDRs starting at `base` (a multiple of 16), planes
+// visited from LBP1 = L down to 1 with a one-plane prefetch.  Fast layout
+// (Alg. 6): slide every DR, zero the DR of the slice's highest LBP1, clear
+// bsLBP1.  Small layout (Alg. 8): slide every DR, the window's register read
+// before the slide.  Register (Alg. 2): the largest LBP1 whose DR is active,
+// DR <= k-1 at the moment the window is read.  R receives the 16 registers
+// (byte j of R[w] = BDR base + 4w + j); they are also stored to reg and reg4.
+// With 16 BDRs per thread, the two threads sharing a bsLBP1 word are
+// adjacent lanes of one wave and both consume it before the even one clears it.
+template <bool FAST>
+__device__ __forceinline__ void advance_group(uint8_t* dr, uint64_t mstride, uint32_t* seen, uint64_t wstride,
+                                              uint8_t* reg, uint8_t* reg4, uint64_t base, uint32_t L,
+                                              uint32_t gt_bias, uint32_t R[4]) {
+  uint32_t M[4] = {0, 0, 0, 0};
+  R[0] = R[1] = R[2] = R[3] = 0;
+  uint32_t folded = 0;
+  u32x4 dn = *reinterpret_cast<const u32x4*>(dr + (uint64_t)(L - 1) * mstride + base);
+  uint32_t sn = 0;
+  if constexpr (FAST) sn = seen[(uint64_t)(L - 1) * wstride + (base >> 5)];
+  for (int i = (int)L; i >= 1; --i) {
+    const u32x4 d = dn;
+    const uint32_t s = sn;
+    if (i > 1) {
+      dn = *reinterpret_cast<const u32x4*>(dr + (uint64_t)(i - 2) * mstride + base);
+      if constexpr (FAST) sn = seen[(uint64_t)(i - 2) * wstride + (base >> 5)];
+    }
+    uint32_t fold = 0;
+    if constexpr (FAST) {
+      const uint32_t bits = (s >> (base & 31)) & 0xFFFFu;
+      fold = bits & ~folded;  // only the slice's highest LBP1 is recorded
+      folded |= bits;
+    }
+    u32x4 nd;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t x = d[w];
+      uint32_t y = swar_sat_inc(x);                                                // SlideDR
+      if constexpr (FAST) y &= ~swar_nibble_to_bytes((fold >> (4 * w)) & 0xFu);  // SetDR
+      const uint32_t act = swar_le_mask(FAST ? y : x, gt_bias);                   // IsActiveDR
+      R[w] |= act & ~M[w] & ((uint32_t)i * 0x01010101u);
+      M[w] |= act;
+      nd[w] = y;
+    }
+    *reinterpret_cast<u32x4*>(dr + (uint64_t)(i - 1) * mstride + base) = nd;
+  }
+  if constexpr (FAST) {
+    if ((base & 31) == 0)
+      for (uint32_t i = 0; i < L; ++i) seen[(uint64_t)i * wstride + (base >> 5)] = 0;
+  }
+  *reinterpret_cast<u32x4*>(reg + base) = u32x4{R[0], R[1], R[2], R[3]};
+  uint64_t nib = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) nib |= (uint64_t)swar_pack_nibbles(R[w]) << (16 * w);
+  *reinterpret_cast<uint64_t*>(reg4 + base / 2) = nib;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t olo = __shfl_xor(lo, off), ohi = __shfl_xor(hi, off);
+    const uint64_t s = ((uint64_t)hi << 32 | lo) + ((uint64_t)ohi << 32 | olo);
+    lo = (uint32_t)s, hi = (uint32_t)(s >> 32);
+  }
+  return (uint64_t)hi << 32 | lo;
+}
+
+// Noise-removed estimate (m E_s - g E_m) / (m - g), each operation rounded once.
+__device__ __forceinline__ double noise_removed(double Es, double Em, double m, double g) {
+#pragma clang fp contract(off)
+  return (m * Es - g * Em) / (m - g);
+}
+
+// E_m: the HyperLogLog estimate over all m registers from their histogram.
+__device__ __forceinline__ double pool_estimate(const unsigned long long* hist, double m) {
+  uint64_t U = 0;
+  for (int r = 0; r < kBins; ++r) U += (uint64_t)hist[r] << (32 - r);
+  return hll_estimate(U, hist[0], m);
+}
+
+// Exact harmonic sum U = sum 2^(32-R) and zero count V of one host's g
+// registers (getPhyIdx of Alg. 3, register gathers of Alg. 5), summed over
+// the wave; kmix = mm3_key(aip).  Every lane returns the totals.
+template <int UNROLL>
+__device__ __forceinline__ void host_harmonic(uint32_t kmix, const uint32_t* s1, uint32_t g, uint32_t m,
+                                              const uint8_t* reg, int lane, uint64_t& U, uint32_t& V) {
+  U = 0;
+  V = 0;
+  for (uint32_t i0 = lane; i0 < g; i0 += 64 * UNROLL) {
+    uint32_t r[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const uint32_t i = i0 + 64u * u;
+      r[u] = i < g ? (uint32_t)reg[reduce_m(mm3_seeded(kmix, s1[i]), m)] : 255u;
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u)
+      if (r[u] != 255u) {
+        U += 1ull << (32 - r[u]);
+        V += r[u] == 0;
+      }
+  }
+  U = wave_sum_u64(U);
+  V = (uint32_t)wave_sum_u64(V);
+}
+
 }  // namespace vbdr

@@ -1,0 +1,67 @@
+// Host-side internals shared by the translation units of libvbdr.so.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "vbdr.h"
+#include "vbdr_device.h"
+
+constexpr uint64_t kPad = 4096;             // BDR padding granule of a plane
+constexpr uint32_t kStageMaxG = 8192;       // s1 staged in LDS up to 32 KiB
+constexpr uint32_t kCusPerXcd = 32;         // gfx950: 8 XCDs x 32 CUs
+constexpr uint64_t kPartMinM = 1ull << 22;  // pools whose registers outgrow one XCD's L2
+constexpr uint32_t kPartChunk = 1u << 17;   // hosts per partitioned-estimate pass
+constexpr uint32_t kLearnChunk = 1u << 15;  // hosts per histogram pass of the learned estimate
+constexpr uint64_t kBinMaxM = 1ull << 27;   // binned scan records pack (pidx << 5) | (LBP1 - 1)
+constexpr uint32_t kBinChunk = 1u << 24;    // pairs per binned-scan pass
+constexpr uint32_t kBinCap = kBinChunk / 8 + kBinChunk / 32 + 65536;  // records per bin per pass
+
+struct vbdr_sketch {
+  int device;
+  int n_cu;
+  uint64_t m;
+  uint32_t g, b, L, k;
+  int layout;
+  uint32_t A0, A1;
+  uint64_t t;
+  uint64_t mstride, wstride;
+  uint8_t* dr;
+  uint32_t* seen;
+  uint8_t* reg;
+  unsigned long long* hist;
+  uint32_t* s1;
+  uint8_t* reg4;               // registers as nibbles, min(reg, 15); 15 = read reg
+  int parts;                   // XCD partitions of the estimate (1 = direct gather)
+  unsigned long long* part_u;  // [parts][kPartChunk] partial harmonic sums
+  uint32_t* part_v;            // [parts][kPartChunk] partial zero counts
+  uint32_t* hist_ws;           // [parts][kLearnChunk][33] per-host (partial) histograms
+  float* est_ws;               // [kLearnChunk] plain estimates of a histogram pass
+  uint32_t* bins;              // [parts][kBinCap] binned scan records (large pools)
+  uint32_t* bin_fill;          // [parts] records written per bin
+  uint64_t bytes;
+  vbdr_tuning tune;
+};
+
+// Records the calling thread's error message and returns code.
+int vbdr_fail(int code, const char* fmt, ...);
+
+#define VBDR_HIP(call)                                                                         \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return vbdr_fail(VBDR_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define VBDR_LAUNCHED(name)                                                                         \
+  do {                                                                                              \
+    hipError_t e_ = hipGetLastError();                                                              \
+    if (e_ != hipSuccess) return vbdr_fail(VBDR_EHIP, "launch of %s: %s", name, hipGetErrorString(e_)); \
+  } while (0)
+
+// VBDR_EINVAL unless the sketch's device is current.
+int vbdr_check_device(const vbdr_sketch* sk);
+
+// Register histograms of nh <= kLearnChunk hosts into sk->hist_ws: with
+// sk->parts == 1 one full histogram per host ([h][33]); otherwise one partial
+// histogram per XCD range ([x][h][33]), to be summed over x.
+int vbdr_hist_pass(vbdr_sketch* sk, const uint32_t* hosts_dev, uint32_t nh, hipStream_t st);

@@ -1,0 +1,476 @@
+// Learned cardinality estimator beside the HyperLogLog estimate of Alg. 5:
+// a 67 -> 64 -> 64 -> 1 GELU MLP over a host's register histogram, the pool's
+// register histogram and ln(g/m), predicting ln(1 + n).
+//   - inference: bf16 weights and inputs on the matrix cores
+//     (v_mfma_f32_16x16x32_bf16, fp32 accumulation), 16 hosts per wave, with
+//     the plain estimate as fallback outside the training envelope;
+//   - training: fp32 per-sample backpropagation with the weights in LDS,
+//     gradients reduced with atomics, then an Adam update.
+// Parameter vector (fp32, 8577): W1 (64 x 67), b1, W2 (64 x 64), b2, w3, b3.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "vbdr_internal.h"
+
+using namespace vbdr;
+
+namespace {
+
+constexpr int kIn = 67, kHid = 64, kInPad = 96;
+constexpr int kOffW1 = 0, kOffB1 = kHid * kIn, kOffW2 = kOffB1 + kHid, kOffB2 = kOffW2 + kHid * kHid;
+constexpr int kOffW3 = kOffB2 + kHid, kOffB3 = kOffW3 + kHid, kParams = kOffB3 + 1;
+static_assert(kParams == 8577, "parameter layout");
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct MlpDev {
+  uint16_t w1[kHid * kInPad];  // bf16, K zero-padded to 96
+  uint16_t w2[kHid * kHid];    // bf16
+  float b1[kHid], b2[kHid], w3[kHid], b3;  // w3 holds bf16-rounded values
+  float env_lo[kIn], env_hi[kIn];
+  int has_env;
+};
+
+// float -> bf16 bits, round to nearest even (host and device).
+__host__ __device__ inline uint16_t f2bf(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return 0x7FC0;  // NaN
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// ------------------------------------------------------------ features
+// fp32 features of nh hosts from the histogram pass: [h][67].
+__global__ __launch_bounds__(256) void k_features(uint32_t nh, uint32_t parts, const uint32_t* __restrict__ hws,
+                                                  const unsigned long long* __restrict__ hist, uint32_t g, uint32_t m,
+                                                  float* __restrict__ feats) {
+  const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+  if (h >= nh) return;
+  float* f = feats + (uint64_t)h * kIn;
+  for (int r = 0; r < kBins; ++r) {
+    uint32_t c = 0;
+    for (uint32_t x = 0; x < parts; ++x) c += hws[((uint64_t)x * kLearnChunk + h) * kBins + r];
+    f[r] = (float)((double)c / (double)g);
+    f[kBins + r] = (float)((double)hist[r] / (double)m);
+  }
+  f[2 * kBins] = (float)log((double)g / (double)m);
+}
+
+// ----------------------------------------------------------- inference
+constexpr int kInfBlock = 256;
+constexpr int kInfWaves = kInfBlock / 64;
+
+__global__ __launch_bounds__(kInfBlock) void k_learned(uint32_t nh, uint32_t parts, const uint32_t* __restrict__ hws,
+                                                       const unsigned long long* __restrict__ hist, uint32_t g,
+                                                       uint32_t m, const MlpDev* __restrict__ mlp,
+                                                       float* __restrict__ out, uint8_t* __restrict__ used_fallback) {
+  __shared__ __attribute__((aligned(16))) uint16_t sw1[kHid * kInPad];
+  __shared__ __attribute__((aligned(16))) uint16_t sw2[kHid * kHid];
+  __shared__ __attribute__((aligned(16))) uint16_t sx[kInfWaves][16 * kInPad];
+  __shared__ __attribute__((aligned(16))) uint16_t sh1[kInfWaves][16 * kHid];
+  __shared__ float spool[kInPad];  // fp32 pool features, columns 33..95
+  __shared__ uint16_t spool_bf[kInPad];
+  __shared__ int spool_bad;
+  __shared__ float splain[kInfWaves][16];
+  __shared__ int sflag[kInfWaves][16];
+  __shared__ double sem;
+  for (int i = threadIdx.x; i < kHid * kInPad / 8; i += kInfBlock)
+    reinterpret_cast<uint4*>(sw1)[i] = reinterpret_cast<const uint4*>(mlp->w1)[i];
+  for (int i = threadIdx.x; i < kHid * kHid / 8; i += kInfBlock)
+    reinterpret_cast<uint4*>(sw2)[i] = reinterpret_cast<const uint4*>(mlp->w2)[i];
+  if (threadIdx.x == 0) {
+    sem = pool_estimate(hist, (double)m);
+    spool_bad = 0;
+  }
+  if (threadIdx.x < kInPad) {
+    const int c = threadIdx.x;
+    float v = 0.0f;
+    if (c >= kBins && c < 2 * kBins) v = (float)((double)hist[c - kBins] / (double)m);
+    if (c == 2 * kBins) v = (float)log((double)g / (double)m);
+    spool[c] = v;
+    spool_bf[c] = f2bf(v);
+  }
+  __syncthreads();
+  if (threadIdx.x >= kBins && threadIdx.x < kIn && mlp->has_env) {
+    const float v = spool[threadIdx.x];
+    if (!(v >= mlp->env_lo[threadIdx.x] && v <= mlp->env_hi[threadIdx.x])) atomicOr(&spool_bad, 1);
+  }
+  __syncthreads();
+  const double Em = sem;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint16_t* X = sx[wave];
+  uint16_t* H1 = sh1[wave];
+  const uint32_t ntiles = (nh + 15) / 16;
+  for (uint32_t tile = blockIdx.x * kInfWaves + wave; tile < ntiles; tile += gridDim.x * kInfWaves) {
+    // 1. features of 16 hosts: lane = 4 * row + quarter
+    const int row = lane >> 2, q = lane & 3;
+    const uint32_t h = tile * 16 + row;
+    const bool live = h < nh;
+    uint64_t U = 0;
+    uint32_t V = 0;
+    int bad = 0;
+    for (int r = q; r < kBins; r += 4) {
+      uint32_t c = 0;
+      if (live)
+        for (uint32_t x = 0; x < parts; ++x) c += hws[((uint64_t)x * kLearnChunk + h) * kBins + r];
+      const float f = (float)((double)c / (double)g);
+      X[row * kInPad + r] = f2bf(f);
+      U += (uint64_t)c << (32 - r);
+      if (r == 0) V = c;
+      if (mlp->has_env && !(f >= mlp->env_lo[r] && f <= mlp->env_hi[r])) bad = 1;
+    }
+    for (int c = kBins + q; c < kInPad; c += 4) X[row * kInPad + c] = spool_bf[c];
+    U += __shfl_xor(U, 1);
+    U += __shfl_xor(U, 2);
+    V += __shfl_xor(V, 1);
+    V += __shfl_xor(V, 2);
+    bad |= __shfl_xor(bad, 1);
+    bad |= __shfl_xor(bad, 2);
+    if (q == 0) {
+      const double Es = hll_estimate(U, V, (double)g);
+      const double n = noise_removed(Es, Em, (double)m, (double)g);
+      splain[wave][row] = (float)(n > 0.0 ? n : 0.0);
+      sflag[wave][row] = bad | spool_bad;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // 2. layer 1: Z1 (16 x 64) = X (16 x 96) W1^T, three K steps of 32
+    const int mr = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 3; ++ks) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(X + mr * kInPad + ks * 32 + kq * 8);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(sw1 + (nt * 16 + mr) * kInPad + ks * 32 + kq * 8);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+      }
+      const int col = nt * 16 + mr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) H1[(kq * 4 + i) * kHid + col] = f2bf(gelu(acc[i] + mlp->b1[col]));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // 3. layer 2 and the output unit
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(H1 + mr * kHid + ks * 32 + kq * 8);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(sw2 + (nt * 16 + mr) * kHid + ks * 32 + kq * 8);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+      }
+      const int col = nt * 16 + mr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part[i] += gelu(acc[i] + mlp->b2[col]) * mlp->w3[col];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      part[i] += __shfl_xor(part[i], 8);
+      part[i] += __shfl_xor(part[i], 4);
+      part[i] += __shfl_xor(part[i], 2);
+      part[i] += __shfl_xor(part[i], 1);
+    }
+    if (mr == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = kq * 4 + i;
+        const uint32_t hh = tile * 16 + r;
+        if (hh < nh) {
+          const float y = part[i] + mlp->b3;
+          float est = expf(y) - 1.0f;
+          int fb = sflag[wave][r];
+          if (!isfinite(est)) fb = 1;
+          if (fb) est = splain[wave][r];
+          out[hh] = est > 0.0f ? est : 0.0f;
+          if (used_fallback) used_fallback[hh] = (uint8_t)fb;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// ------------------------------------------------------------ training
+constexpr int kW2Pad = kHid + 1;  // padded LDS row of W2 (bank conflicts)
+
+// One wave per block; lane j owns hidden unit j of both layers: its W1 row
+// and gradient rows live in registers, W2 (read by rows forward and by
+// columns backward) in LDS.  Each block runs spb samples, then adds its
+// gradient of the batch-mean loss into grads with atomics.
+__global__ __launch_bounds__(64) void k_train_grad(const float* __restrict__ params, const float* __restrict__ feats,
+                                                   const float* __restrict__ targets, uint32_t B, uint32_t spb,
+                                                   float* __restrict__ grads, float* __restrict__ loss) {
+  __shared__ float w2[kHid * kW2Pad];
+  __shared__ float xs[kIn], h1s[kHid], dz2s[kHid];
+  const int j = threadIdx.x;
+  float w1r[kIn], g1r[kIn], g2r[kHid];
+#pragma unroll
+  for (int k = 0; k < kIn; ++k) {
+    w1r[k] = params[kOffW1 + j * kIn + k];
+    g1r[k] = 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < kHid; ++k) g2r[k] = 0.f;
+  for (int i = j; i < kHid * kHid; i += 64) w2[(i / kHid) * kW2Pad + i % kHid] = params[kOffW2 + i];
+  const float b1 = params[kOffB1 + j], b2 = params[kOffB2 + j], w3 = params[kOffW3 + j], b3 = params[kOffB3];
+  float gb1 = 0.f, gb2 = 0.f, gw3 = 0.f, gb3 = 0.f, lsum = 0.f;
+  __syncthreads();
+  const uint32_t s0 = blockIdx.x * spb, s1 = min(B, s0 + spb);
+  const float inv_b = 1.0f / (float)B;
+  for (uint32_t s = s0; s < s1; ++s) {
+    for (int i = j; i < kIn; i += 64) xs[i] = feats[(uint64_t)s * kIn + i];
+    __syncthreads();
+    float z1 = b1;
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) z1 += w1r[k] * xs[k];
+    h1s[j] = gelu(z1);
+    __syncthreads();
+    float z2 = b2;
+#pragma unroll
+    for (int k = 0; k < kHid; ++k) z2 += w2[j * kW2Pad + k] * h1s[k];
+    const float h2 = gelu(z2);
+    float y = w3 * h2;
+    for (int off = 32; off > 0; off >>= 1) y += __shfl_xor(y, off);
+    y += b3;
+    const float r = y - targets[s];
+    const float dy = 2.0f * r * inv_b;
+    lsum += r * r * inv_b;
+    gw3 += dy * h2;
+    gb3 += dy;
+    const float dz2 = dy * w3 * gelu_grad(z2);
+    dz2s[j] = dz2;
+    gb2 += dz2;
+#pragma unroll
+    for (int k = 0; k < kHid; ++k) g2r[k] += dz2 * h1s[k];
+    __syncthreads();
+    float dh1 = 0.f;
+#pragma unroll
+    for (int i = 0; i < kHid; ++i) dh1 += w2[i * kW2Pad + j] * dz2s[i];
+    const float dz1 = dh1 * gelu_grad(z1);
+    gb1 += dz1;
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) g1r[k] += dz1 * xs[k];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kIn; ++k) atomicAdd(&grads[kOffW1 + j * kIn + k], g1r[k]);
+#pragma unroll
+  for (int k = 0; k < kHid; ++k) atomicAdd(&grads[kOffW2 + j * kHid + k], g2r[k]);
+  atomicAdd(&grads[kOffB1 + j], gb1);
+  atomicAdd(&grads[kOffB2 + j], gb2);
+  atomicAdd(&grads[kOffW3 + j], gw3);
+  if (j == 0) {
+    atomicAdd(&grads[kOffB3], gb3);
+    if (loss) atomicAdd(loss, lsum);
+  }
+}
+
+__global__ void k_adam(float* __restrict__ params, float* __restrict__ grads, float* __restrict__ m1,
+                       float* __restrict__ m2, float lr, float beta1, float beta2, float eps, float bc1, float bc2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kParams) return;
+  const float gr = grads[i];
+  const float a = beta1 * m1[i] + (1.0f - beta1) * gr;
+  const float v = beta2 * m2[i] + (1.0f - beta2) * gr * gr;
+  m1[i] = a;
+  m2[i] = v;
+  params[i] -= lr * (a / bc1) / (sqrtf(v / bc2) + eps);
+  grads[i] = 0.f;
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+}  // namespace
+
+struct vbdr_mlp {
+  int device;
+  MlpDev* dev;
+};
+
+struct vbdr_trainer {
+  int device;
+  float *params, *grads, *m1, *m2;
+  uint64_t step;
+  float lr, beta1, beta2, eps;
+};
+
+extern "C" {
+
+int vbdr_mlp_create(const float* params_host, const float* env_lo, const float* env_hi, vbdr_mlp** out) {
+  if (!params_host || !out) return vbdr_fail(VBDR_EINVAL, "NULL argument");
+  if ((env_lo == nullptr) != (env_hi == nullptr)) return vbdr_fail(VBDR_EINVAL, "give both envelope bounds or none");
+  *out = nullptr;
+  std::vector<uint8_t> buf(sizeof(MlpDev), 0);
+  MlpDev* h = reinterpret_cast<MlpDev*>(buf.data());
+  for (int j = 0; j < kHid; ++j) {
+    for (int k = 0; k < kIn; ++k) h->w1[j * kInPad + k] = f2bf(params_host[kOffW1 + j * kIn + k]);
+    for (int k = 0; k < kHid; ++k) h->w2[j * kHid + k] = f2bf(params_host[kOffW2 + j * kHid + k]);
+    h->b1[j] = params_host[kOffB1 + j];
+    h->b2[j] = params_host[kOffB2 + j];
+    h->w3[j] = bf2f(f2bf(params_host[kOffW3 + j]));
+  }
+  h->b3 = params_host[kOffB3];
+  h->has_env = env_lo != nullptr;
+  for (int k = 0; k < kIn; ++k) {
+    h->env_lo[k] = env_lo ? env_lo[k] : 0.f;
+    h->env_hi[k] = env_hi ? env_hi[k] : 0.f;
+  }
+  vbdr_mlp* mlp = new (std::nothrow) vbdr_mlp();
+  if (!mlp) return vbdr_fail(VBDR_ENOMEM, "host allocation failed");
+  if (hipGetDevice(&mlp->device) != hipSuccess || hipMalloc(&mlp->dev, sizeof(MlpDev)) != hipSuccess) {
+    delete mlp;
+    return vbdr_fail(VBDR_ENOMEM, "device allocation of the MLP failed");
+  }
+  if (hipMemcpy(mlp->dev, h, sizeof(MlpDev), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(mlp->dev);
+    delete mlp;
+    return vbdr_fail(VBDR_EHIP, "upload of the MLP failed");
+  }
+  *out = mlp;
+  return VBDR_OK;
+}
+
+void vbdr_mlp_destroy(vbdr_mlp* mlp) {
+  if (!mlp) return;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(mlp->dev);
+  delete mlp;
+}
+
+int vbdr_features(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, float* feats_dev, void* stream) {
+  if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
+  if (n_hosts == 0) return VBDR_OK;
+  if (!hosts_dev || !feats_dev) return vbdr_fail(VBDR_EINVAL, "hosts_dev and feats_dev must not be NULL");
+  if (int rc = vbdr_check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (uint64_t c = 0; c < n_hosts; c += kLearnChunk) {
+    const uint32_t nh = (uint32_t)(n_hosts - c < kLearnChunk ? n_hosts - c : kLearnChunk);
+    if (int rc = vbdr_hist_pass(sk, hosts_dev + c, nh, st)) return rc;
+    hipLaunchKernelGGL(k_features, dim3((nh + 255) / 256), dim3(256), 0, st, nh, (uint32_t)sk->parts, sk->hist_ws,
+                       sk->hist, sk->g, (uint32_t)sk->m, feats_dev + c * kIn);
+    VBDR_LAUNCHED("k_features");
+  }
+  return VBDR_OK;
+}
+
+int vbdr_estimate_learned(vbdr_sketch* sk, const vbdr_mlp* mlp, const uint32_t* hosts_dev, uint64_t n_hosts,
+                          float* out_dev, uint8_t* used_fallback_dev, void* stream) {
+  if (!sk || !mlp) return vbdr_fail(VBDR_EINVAL, "sketch and mlp must not be NULL");
+  if (n_hosts == 0) return VBDR_OK;
+  if (!hosts_dev || !out_dev) return vbdr_fail(VBDR_EINVAL, "hosts_dev and out_dev must not be NULL");
+  if (mlp->device != sk->device) return vbdr_fail(VBDR_EINVAL, "mlp and sketch live on different devices");
+  if (int rc = vbdr_check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (uint64_t c = 0; c < n_hosts; c += kLearnChunk) {
+    const uint32_t nh = (uint32_t)(n_hosts - c < kLearnChunk ? n_hosts - c : kLearnChunk);
+    if (int rc = vbdr_hist_pass(sk, hosts_dev + c, nh, st)) return rc;
+    const uint32_t tiles = (nh + 15) / 16;
+    const uint32_t want = (tiles + kInfWaves - 1) / kInfWaves;
+    const uint32_t cap = (uint32_t)sk->n_cu * 4;
+    hipLaunchKernelGGL(k_learned, dim3(want < cap ? want : cap), dim3(kInfBlock), 0, st, nh, (uint32_t)sk->parts,
+                       sk->hist_ws, sk->hist, sk->g, (uint32_t)sk->m, mlp->dev, out_dev + c,
+                       used_fallback_dev ? used_fallback_dev + c : nullptr);
+    VBDR_LAUNCHED("k_learned");
+  }
+  return VBDR_OK;
+}
+
+int vbdr_trainer_create(const float* params_host, float lr, vbdr_trainer** out) {
+  if (!params_host || !out) return vbdr_fail(VBDR_EINVAL, "NULL argument");
+  if (!(lr > 0.f)) return vbdr_fail(VBDR_EINVAL, "learning rate must be positive");
+  *out = nullptr;
+  vbdr_trainer* tr = new (std::nothrow) vbdr_trainer();
+  if (!tr) return vbdr_fail(VBDR_ENOMEM, "host allocation failed");
+  std::memset(tr, 0, sizeof(*tr));
+  tr->lr = lr, tr->beta1 = 0.9f, tr->beta2 = 0.999f, tr->eps = 1e-8f;
+  const size_t bytes = kParams * sizeof(float);
+  if (hipGetDevice(&tr->device) != hipSuccess || hipMalloc(&tr->params, bytes) != hipSuccess ||
+      hipMalloc(&tr->grads, bytes) != hipSuccess || hipMalloc(&tr->m1, bytes) != hipSuccess ||
+      hipMalloc(&tr->m2, bytes) != hipSuccess) {
+    vbdr_trainer_destroy(tr);
+    return vbdr_fail(VBDR_ENOMEM, "device allocation of the trainer failed");
+  }
+  const uint32_t grid = (kParams + 255) / 256;
+  hipLaunchKernelGGL(k_zero_f32, dim3(grid), dim3(256), 0, nullptr, tr->grads, (uint32_t)kParams);
+  hipLaunchKernelGGL(k_zero_f32, dim3(grid), dim3(256), 0, nullptr, tr->m1, (uint32_t)kParams);
+  hipLaunchKernelGGL(k_zero_f32, dim3(grid), dim3(256), 0, nullptr, tr->m2, (uint32_t)kParams);
+  if (hipGetLastError() != hipSuccess || hipMemcpy(tr->params, params_host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    vbdr_trainer_destroy(tr);
+    return vbdr_fail(VBDR_EHIP, "trainer initialisation failed");
+  }
+  *out = tr;
+  return VBDR_OK;
+}
+
+void vbdr_trainer_destroy(vbdr_trainer* tr) {
+  if (!tr) return;
+  (void)hipDeviceSynchronize();
+  if (tr->params) (void)hipFree(tr->params);
+  if (tr->grads) (void)hipFree(tr->grads);
+  if (tr->m1) (void)hipFree(tr->m1);
+  if (tr->m2) (void)hipFree(tr->m2);
+  delete tr;
+}
+
+int vbdr_trainer_set_lr(vbdr_trainer* tr, float lr) {
+  if (!tr || !(lr > 0.f)) return vbdr_fail(VBDR_EINVAL, "bad trainer or learning rate");
+  tr->lr = lr;
+  return VBDR_OK;
+}
+
+int vbdr_trainer_grad(vbdr_trainer* tr, const float* feats_dev, const float* targets_dev, uint64_t n, float* grads_out_dev,
+                      float* loss_dev, void* stream) {
+  if (!tr || !feats_dev || !targets_dev || !grads_out_dev) return vbdr_fail(VBDR_EINVAL, "NULL argument");
+  if (n == 0 || n >= (1ull << 31)) return vbdr_fail(VBDR_EINVAL, "batch size out of range");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const uint32_t spb = 32;
+  const uint32_t grid = (uint32_t)((n + spb - 1) / spb);
+  hipLaunchKernelGGL(k_train_grad, dim3(grid), dim3(64), 0, st, tr->params, feats_dev, targets_dev, (uint32_t)n, spb,
+                     grads_out_dev, loss_dev);
+  VBDR_LAUNCHED("k_train_grad");
+  return VBDR_OK;
+}
+
+int vbdr_trainer_step(vbdr_trainer* tr, const float* feats_dev, const float* targets_dev, uint64_t n, float* loss_dev,
+                      void* stream) {
+  if (int rc = vbdr_trainer_grad(tr, feats_dev, targets_dev, n, tr ? tr->grads : nullptr, loss_dev, stream)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  tr->step++;
+  const float bc1 = 1.0f - powf(tr->beta1, (float)tr->step), bc2 = 1.0f - powf(tr->beta2, (float)tr->step);
+  hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, st, tr->params, tr->grads, tr->m1, tr->m2,
+                     tr->lr, tr->beta1, tr->beta2, tr->eps, bc1, bc2);
+  VBDR_LAUNCHED("k_adam");
+  return VBDR_OK;
+}
+
+int vbdr_trainer_params(vbdr_trainer* tr, float* params_host, void* stream) {
+  if (!tr || !params_host) return vbdr_fail(VBDR_EINVAL, "NULL argument");
+  VBDR_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  VBDR_HIP(hipMemcpy(params_host, tr->params, kParams * sizeof(float), hipMemcpyDeviceToHost));
+  return VBDR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,191 @@
+"""Train and evaluate the learned estimator (GPU).
+
+Samples are (features, ln(1 + n)) of every host after every slice once the
+window is full, on streams shaped like the tiny workload (2^12 hosts, 2^20
+pairs per slice, 12 slices, m = 2^18, g = 256, k = 4): training seeds 0..99
+(10^6 samples drawn from the 368,640), evaluation seeds 100..109.  Features
+come from the library's own scan / advance / feature kernels; the truth is the
+exact distinct count of the window's pairs (Definition 1), computed on the
+device with sort-unique.  Training runs the library's float32 Adam kernels.
+
+    python -m paper_1810_13132_amd.learn --out paper_1810_13132_amd/weights/mlp_tiny.npz
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from paper_1810_13132_amd import synth, vbdr
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(PKG, "weights", "mlp_tiny.npz")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def window_truth(window_keys, host_keys):
+    """Exact |OP(aip)| over the window for each host (int64 aip keys)."""
+    u = torch.unique(torch.cat(window_keys))
+    vals, cnts = torch.unique(u >> 32, return_counts=True)
+    pos = torch.searchsorted(vals, host_keys).clamp(max=max(len(vals) - 1, 0))
+    hit = vals[pos] == host_keys
+    return torch.where(hit, cnts[pos], torch.zeros_like(cnts[pos]))
+
+
+def stream_samples(seed: int, w=synth.TINY, layout="fast", mlp=None):
+    """Per full window: features, truth, plain (and learned) estimates of all hosts."""
+    st = synth.Stream(w.scaled(seed=seed))
+    sk = vbdr.Sketch(w.m, w.g, w.k, seed, layout)
+    hosts = vbdr.to_device_u32(st.aip)
+    host_keys = torch.from_numpy(st.aip.astype(np.int64)).cuda()
+    window, out = [], []
+    for t in range(w.slices):
+        pd = vbdr.to_device_u32(st.slice(t).reshape(-1))
+        sk.scan_slice(pd)
+        sk.advance_slice()
+        p = pd.view(-1, 2).to(torch.int64) & 0xFFFFFFFF
+        window.append((p[:, 0] << 32) | p[:, 1])
+        window = window[-w.k:]
+        if t >= w.k - 1:
+            rec = {"feats": sk.features(hosts), "truth": window_truth(window, host_keys),
+                   "plain": sk.estimate(hosts)}
+            if mlp is not None:
+                rec["learned"], rec["fallback"] = sk.estimate_learned(mlp, hosts, with_fallback=True)
+            out.append(rec)
+    sk.close()
+    return out
+
+
+def rms_rel(est, truth):
+    t = truth.to(torch.float64)
+    keep = t >= 1
+    r = (est.to(torch.float64)[keep] - t[keep]) / t[keep]
+    return float(torch.sqrt(torch.mean(r * r)))
+
+
+def envelope(feats: torch.Tensor):
+    lo = feats.min(0).values.double()
+    hi = feats.max(0).values.double()
+    span = hi - lo
+    pad = torch.maximum(0.05 * span, 1e-3 * torch.maximum(lo.abs(), hi.abs()) + 1e-6)
+    return (lo - pad).float().cpu().numpy(), (hi + pad).float().cpu().numpy()
+
+
+def init_params(seed: int):
+    """He-uniform init; output bias at the mean target."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape, fan in (((64, 67), 67), ((64,), None), ((64, 64), 64), ((64,), None), ((64,), 64), ((1,), None)):
+        n = int(np.prod(shape))
+        parts.append(rng.uniform(-math.sqrt(6 / fan), math.sqrt(6 / fan), n) if fan else np.zeros(n))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(train_seeds=range(100), n_samples=10**6, epochs=30, batch=4096, lr=3e-3, seed=0):
+    t0 = time.time()
+    feats, targets = [], []
+    for s in train_seeds:
+        for rec in stream_samples(s):
+            feats.append(rec["feats"])
+            targets.append(torch.log1p(rec["truth"].to(torch.float32)))
+        if s % 10 == 9:
+            log(f"train seed {s}: {sum(len(t) for t in targets)} samples ({time.time() - t0:.1f}s)")
+    X = torch.cat(feats)
+    Y = torch.cat(targets)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    pick = torch.randperm(len(Y), generator=g)[:n_samples].cuda()
+    X, Y = X[pick].contiguous(), Y[pick].contiguous()
+    lo, hi = envelope(X)
+    params = init_params(seed)
+    params[-1] = float(Y.mean())
+    tr = vbdr.Trainer(params, lr)
+    steps_per_epoch = len(Y) // batch
+    total = epochs * steps_per_epoch
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    step = 0
+    for ep in range(epochs):
+        perm = torch.randperm(len(Y), generator=g).cuda()
+        loss.zero_()
+        for b in range(steps_per_epoch):
+            idx = perm[b * batch:(b + 1) * batch]
+            tr.set_lr(lr * 0.5 * (1 + math.cos(math.pi * step / total)) + 1e-5)
+            tr.step(X[idx].contiguous(), Y[idx].contiguous(), loss)
+            step += 1
+        log(f"epoch {ep}: mean batch loss {float(loss.cpu()[0]) / steps_per_epoch:.5f} ({time.time() - t0:.1f}s)")
+    return tr.params(), lo, hi, {"samples": int(len(Y)), "epochs": epochs, "batch": batch, "lr": lr,
+                                 "train_seeds": [min(train_seeds), max(train_seeds)]}
+
+
+def evaluate(params, lo, hi, eval_seeds=range(100, 110)):
+    mlp = vbdr.MLP(params, lo, hi)
+    ests, truths, plains, fbs = [], [], [], []
+    for s in eval_seeds:
+        for rec in stream_samples(s, mlp=mlp):
+            ests.append(rec["learned"])
+            plains.append(rec["plain"])
+            truths.append(rec["truth"])
+            fbs.append(rec["fallback"])
+    est, plain, truth, fb = torch.cat(ests), torch.cat(plains), torch.cat(truths), torch.cat(fbs)
+    res = {"samples": int(len(truth)), "samples_n_ge_1": int((truth >= 1).sum()),
+           "rms_rel_plain": rms_rel(plain, truth), "rms_rel_learned": rms_rel(est, truth),
+           "fallback_frac": float(fb.float().mean()), "eval_seeds": [min(eval_seeds), max(eval_seeds)]}
+    # estimation throughput on the same sketch shape, all 2^12 hosts, plain vs learned
+    w = synth.TINY
+    st = synth.Stream(w.scaled(seed=min(eval_seeds)))
+    sk = vbdr.Sketch(w.m, w.g, w.k, 0, "fast")
+    for t in range(w.k):
+        sk.scan_slice(vbdr.to_device_u32(st.slice(t).reshape(-1)))
+        sk.advance_slice()
+    hosts = vbdr.to_device_u32(np.tile(st.aip, 64))  # 2^18 estimates per launch
+    out = torch.empty(hosts.numel(), dtype=torch.float32, device="cuda")
+
+    def rate(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(10):
+            fn()
+        b.record()
+        b.synchronize()
+        return hosts.numel() * 10 / (a.elapsed_time(b) * 1e-3)
+
+    res["hosts_per_s_plain"] = rate(lambda: sk.estimate(hosts, out))
+    res["hosts_per_s_learned"] = rate(lambda: sk.estimate_learned(mlp, hosts, out))
+    return res
+
+
+def load(path=DEFAULT_WEIGHTS):
+    z = np.load(path, allow_pickle=False)
+    return z["params"], z["env_lo"], z["env_hi"], json.loads(str(z["meta"]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--train-seeds", type=int, default=100)
+    ap.add_argument("--samples", type=int, default=10**6)
+    ap.add_argument("--eval-only", action="store_true")
+    args = ap.parse_args()
+    if args.eval_only:
+        params, lo, hi, meta = load(args.out)
+    else:
+        params, lo, hi, meta = train(range(args.train_seeds), args.samples, args.epochs)
+    res = evaluate(params, lo, hi)
+    meta["eval"] = res
+    if not args.eval_only:
+        os.makedirs(os.path.dirname(args.out), exist_ok=True)
+        np.savez(args.out, params=params, env_lo=lo, env_hi=hi, meta=np.array(json.dumps(meta)))
+    print(json.dumps(meta), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -91,6 +91,23 @@ STRESS = Workload("stress", seed=5, hosts=1 << 24, zipf_s=1.5, nmax=10**4, pairs
                   slices=144, m=1 << 24, g=2048, k=128, n_heavy=16)
 
 
+def batched_workloads(seed: int = 4, n: int = 32):
+    """Independent edge-router streams of uneven size: N_s = floor(2^U(16,24))
+    pairs per slice, k in {4,...,128}, g in {128,...,1024}, pool 2^floor(U(16,25))
+    clipped to 2^24, max(256, N_s/256) hosts with Zipf(1.1) opposite sets on
+    1..10^4; 32 slices."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n):
+        N = int(2 ** rng.uniform(16, 24))
+        k = int(rng.choice([4, 8, 16, 32, 64, 128]))
+        g = int(rng.choice([128, 256, 512, 1024]))
+        m = min(1 << int(rng.uniform(16, 25)), 1 << 24)
+        out.append(Workload(f"batched{s}", seed=seed * 1000 + s, hosts=max(256, N // 256), zipf_s=1.1, nmax=10**4,
+                            pairs_per_slice=N, slices=32, m=max(m, 2 * g), g=g, k=k))
+    return out
+
+
 class Stream:
     """A regenerable stream: ``slice(t)`` returns the N x 2 uint32 pairs of slice t."""
 

@@ -37,12 +37,29 @@ class Info(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("scan_test_first", C.c_int32), ("scan_blocks_per_cu", C.c_uint32),
-                ("est_blocks_per_cu", C.c_uint32)]
+                ("est_blocks_per_cu", C.c_uint32), ("scan_binned", C.c_int32)]
+
+
+class BatchParams(C.Structure):
+    _fields_ = [("m", C.c_uint64), ("g", C.c_uint32), ("k", C.c_uint32), ("hash_seed", C.c_uint64),
+                ("layout", C.c_int32)]
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("scan_tile", C.c_uint32), ("est_tile", C.c_uint32), ("blocks_per_cu", C.c_uint32),
+                ("use_graph", C.c_int32)]
 
 
 EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_destroy", "vbdr_scan_slice",
            "vbdr_advance_slice", "vbdr_estimate", "vbdr_estimate_ex", "vbdr_sketch_info", "vbdr_export_state",
-           "vbdr_import_state", "vbdr_last_error", "vbdr_sketch_set_tuning", "vbdr_sketch_get_tuning"]
+           "vbdr_import_state", "vbdr_last_error", "vbdr_sketch_set_tuning", "vbdr_sketch_get_tuning",
+           "vbdr_mlp_create", "vbdr_mlp_destroy", "vbdr_features", "vbdr_estimate_learned", "vbdr_trainer_create",
+           "vbdr_trainer_destroy", "vbdr_trainer_set_lr", "vbdr_trainer_step", "vbdr_trainer_grad",
+           "vbdr_trainer_params", "vbdr_batch_create", "vbdr_batch_destroy", "vbdr_batch_sketch",
+           "vbdr_batch_set_tuning", "vbdr_batch_get_tuning", "vbdr_batch_step"]
+VOID_EXPORTS = ("vbdr_sketch_destroy", "vbdr_last_error", "vbdr_mlp_destroy", "vbdr_trainer_destroy",
+                "vbdr_batch_destroy", "vbdr_batch_sketch")
+MLP_IN, MLP_PARAMS = 67, 8577
 
 _lib = None
 
@@ -68,9 +85,31 @@ def lib():
         L.vbdr_import_state.argtypes = [vp, vp, vp, vp, vp, u64, vp]
         L.vbdr_sketch_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.vbdr_sketch_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.vbdr_mlp_create.argtypes = [vp, vp, vp, C.POINTER(vp)]
+        L.vbdr_mlp_destroy.argtypes = [vp]
+        L.vbdr_features.argtypes = [vp, vp, u64, vp, vp]
+        L.vbdr_estimate_learned.argtypes = [vp, vp, vp, u64, vp, vp, vp]
+        L.vbdr_trainer_create.argtypes = [vp, C.c_float, C.POINTER(vp)]
+        L.vbdr_trainer_destroy.argtypes = [vp]
+        L.vbdr_trainer_set_lr.argtypes = [vp, C.c_float]
+        L.vbdr_trainer_step.argtypes = [vp, vp, vp, u64, vp, vp]
+        L.vbdr_trainer_grad.argtypes = [vp, vp, vp, u64, vp, vp, vp]
+        L.vbdr_trainer_params.argtypes = [vp, vp, vp]
+        L.vbdr_batch_create.argtypes = [u32, C.POINTER(BatchParams), C.POINTER(vp)]
+        L.vbdr_batch_destroy.argtypes = [vp]
+        L.vbdr_batch_sketch.argtypes = [vp, u32]
+        L.vbdr_batch_set_tuning.argtypes = [vp, C.POINTER(BatchTuning)]
+        L.vbdr_batch_get_tuning.argtypes = [vp, C.POINTER(BatchTuning)]
+        L.vbdr_batch_step.argtypes = [vp, C.POINTER(vp), C.POINTER(u64), C.POINTER(vp), C.POINTER(u64),
+                                      C.POINTER(vp), vp]
         L.vbdr_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("vbdr_sketch_destroy", "vbdr_last_error"):
+            if name in VOID_EXPORTS:
+                if name == "vbdr_batch_sketch":
+                    L.vbdr_batch_sketch.restype = vp
+                elif name != "vbdr_last_error":
+                    getattr(L, name).restype = None
+            else:
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -102,18 +141,22 @@ _U32 = (torch.int32, torch.uint32)
 class Sketch:
     """A VBDR sketch living on the current device."""
 
-    def __init__(self, m: int, g: int, k: int, hash_seed: int = 0, layout: str = "fast"):
-        h = C.c_void_p()
-        _check(lib().vbdr_sketch_create_layout(m, g, k, hash_seed, LAYOUTS[layout], C.byref(h)))
+    def __init__(self, m: int, g: int, k: int, hash_seed: int = 0, layout: str = "fast", _borrow=None):
+        self._owned = _borrow is None
+        if _borrow is None:
+            h = C.c_void_p()
+            _check(lib().vbdr_sketch_create_layout(m, g, k, hash_seed, LAYOUTS[layout], C.byref(h)))
+        else:
+            h = C.c_void_p(_borrow)
         self._h = h
-        self.layout = layout
         i = self.info()
+        self.layout = {v: key for key, v in LAYOUTS.items()}[i.layout]
         self.m, self.g, self.b, self.L, self.k = i.m, i.g, i.b, i.L, i.k
         self.A0, self.A1 = i.A0, i.A1
 
     def close(self):
         h = getattr(self, "_h", None)
-        if h and h.value:
+        if h and h.value and getattr(self, "_owned", True):
             lib().vbdr_sketch_destroy(h)
         self._h = None
 
@@ -128,15 +171,16 @@ class Sketch:
         _check(lib().vbdr_sketch_info(self._h, C.byref(out)))
         return out
 
-    def set_tuning(self, scan_test_first: int = 0, scan_blocks_per_cu: int = 0, est_blocks_per_cu: int = 0):
-        t = Tuning(scan_test_first, scan_blocks_per_cu, est_blocks_per_cu)
+    def set_tuning(self, scan_test_first: int = 0, scan_blocks_per_cu: int = 0, est_blocks_per_cu: int = 0,
+                   scan_binned: int = 0):
+        t = Tuning(scan_test_first, scan_blocks_per_cu, est_blocks_per_cu, scan_binned)
         _check(lib().vbdr_sketch_set_tuning(self._h, C.byref(t)))
 
     def get_tuning(self) -> dict:
         t = Tuning()
         _check(lib().vbdr_sketch_get_tuning(self._h, C.byref(t)))
         return {"scan_test_first": t.scan_test_first, "scan_blocks_per_cu": t.scan_blocks_per_cu,
-                "est_blocks_per_cu": t.est_blocks_per_cu}
+                "est_blocks_per_cu": t.est_blocks_per_cu, "scan_binned": t.scan_binned}
 
     @property
     def t(self) -> int:
@@ -174,6 +218,28 @@ class Sketch:
                                           _dev_ptr(hist, (torch.int32,), "hist"), _stream(stream)))
         return out, raw, hist
 
+    def features(self, hosts: torch.Tensor, stream=None) -> torch.Tensor:
+        """(n, 67) float32 features of the learned estimator for these hosts."""
+        n = hosts.numel()
+        feats = torch.empty((n, MLP_IN), dtype=torch.float32, device=hosts.device)
+        if n:
+            _check(lib().vbdr_features(self._h, _dev_ptr(hosts, _U32, "hosts"), n,
+                                       _dev_ptr(feats, (torch.float32,), "feats"), _stream(stream)))
+        return feats
+
+    def estimate_learned(self, mlp: "MLP", hosts: torch.Tensor, out: torch.Tensor = None, with_fallback=False,
+                         stream=None):
+        n = hosts.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=hosts.device)
+        fb = torch.empty(n, dtype=torch.uint8, device=hosts.device) if with_fallback else None
+        if n:
+            _check(lib().vbdr_estimate_learned(self._h, mlp._h, _dev_ptr(hosts, _U32, "hosts"), n,
+                                               _dev_ptr(out, (torch.float32,), "out"),
+                                               None if fb is None else _dev_ptr(fb, (torch.uint8,), "fallback"),
+                                               _stream(stream)))
+        return (out, fb) if with_fallback else out
+
     def state(self, stream=None) -> dict:
         """Canonical state as numpy arrays: dr (m, L) uint8, bs (m,) uint32, reg (m,) uint8, hist (33,) uint64."""
         m, L = self.m, self.L
@@ -201,3 +267,141 @@ def to_device_u32(a: np.ndarray, device="cuda") -> torch.Tensor:
     """Copy a uint32 numpy array to the device (as int32 storage, same bits)."""
     a = np.ascontiguousarray(a, dtype=np.uint32)
     return torch.from_numpy(a.view(np.int32)).to(device)
+
+
+def _host_f32(a, n, name):
+    a = np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+    if a.shape != (n,):
+        raise ValueError(f"{name} must hold {n} floats")
+    return a
+
+
+class MLP:
+    """A learned-estimator network on the current device (bf16 weights)."""
+
+    def __init__(self, params, env_lo=None, env_hi=None):
+        p = _host_f32(params, MLP_PARAMS, "params")
+        lo = None if env_lo is None else _host_f32(env_lo, MLP_IN, "env_lo")
+        hi = None if env_hi is None else _host_f32(env_hi, MLP_IN, "env_hi")
+        h = C.c_void_p()
+        _check(lib().vbdr_mlp_create(p.ctypes.data, None if lo is None else lo.ctypes.data,
+                                     None if hi is None else hi.ctypes.data, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and h.value:
+            lib().vbdr_mlp_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Trainer:
+    """Float32 Adam training of the learned estimator on the current device."""
+
+    def __init__(self, params, lr: float = 1e-3):
+        p = _host_f32(params, MLP_PARAMS, "params")
+        h = C.c_void_p()
+        _check(lib().vbdr_trainer_create(p.ctypes.data, lr, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and h.value:
+            lib().vbdr_trainer_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_lr(self, lr: float):
+        _check(lib().vbdr_trainer_set_lr(self._h, lr))
+
+    def step(self, feats: torch.Tensor, targets: torch.Tensor, loss: torch.Tensor = None, stream=None):
+        n = targets.numel()
+        _check(lib().vbdr_trainer_step(self._h, _dev_ptr(feats, (torch.float32,), "feats"),
+                                       _dev_ptr(targets, (torch.float32,), "targets"), n,
+                                       None if loss is None else _dev_ptr(loss, (torch.float32,), "loss"),
+                                       _stream(stream)))
+
+    def grad(self, feats: torch.Tensor, targets: torch.Tensor, stream=None):
+        n = targets.numel()
+        g = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=feats.device)
+        loss = torch.zeros(1, dtype=torch.float32, device=feats.device)
+        _check(lib().vbdr_trainer_grad(self._h, _dev_ptr(feats, (torch.float32,), "feats"),
+                                       _dev_ptr(targets, (torch.float32,), "targets"), n,
+                                       _dev_ptr(g, (torch.float32,), "grads"),
+                                       _dev_ptr(loss, (torch.float32,), "loss"), _stream(stream)))
+        return g, loss
+
+    def params(self, stream=None) -> np.ndarray:
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(lib().vbdr_trainer_params(self._h, out.ctypes.data, _stream(stream)))
+        return out
+
+
+class Batch:
+    """Independent sketches stepped together (persistent kernels, graph replay).
+
+    params: list of dicts with m, g, k, hash_seed and layout ("fast"/"small")."""
+
+    def __init__(self, params):
+        arr = (BatchParams * len(params))()
+        for i, p in enumerate(params):
+            arr[i] = BatchParams(p["m"], p["g"], p["k"], p.get("hash_seed", 0), LAYOUTS[p.get("layout", "fast")])
+        h = C.c_void_p()
+        _check(lib().vbdr_batch_create(len(params), arr, C.byref(h)))
+        self._h = h
+        self.n = len(params)
+        self.sketches = [Sketch(0, 0, 0, _borrow=lib().vbdr_batch_sketch(h, i)) for i in range(self.n)]
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and h.value:
+            for s in getattr(self, "sketches", []):
+                s._h = None
+            lib().vbdr_batch_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, scan_tile=8192, est_tile=64, blocks_per_cu=8, use_graph=True):
+        t = BatchTuning(scan_tile, est_tile, blocks_per_cu, 1 if use_graph else 0)
+        _check(lib().vbdr_batch_set_tuning(self._h, C.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = BatchTuning()
+        _check(lib().vbdr_batch_get_tuning(self._h, C.byref(t)))
+        return {"scan_tile": t.scan_tile, "est_tile": t.est_tile, "blocks_per_cu": t.blocks_per_cu,
+                "use_graph": bool(t.use_graph)}
+
+    def step(self, pairs, hosts, outs, stream=None):
+        """pairs, hosts, outs: lists (one per sketch) of device tensors."""
+        n = self.n
+        if not (len(pairs) == len(hosts) == len(outs) == n):
+            raise ValueError("one pairs, hosts and out tensor per sketch")
+        P, NP, Hh, NH, O = (C.c_void_p * n)(), (C.c_uint64 * n)(), (C.c_void_p * n)(), (C.c_uint64 * n)(), \
+            (C.c_void_p * n)()
+        for i in range(n):
+            npairs = pairs[i].numel() // 2
+            P[i] = _dev_ptr(pairs[i], _U32, "pairs").value if npairs else None
+            NP[i] = npairs
+            nh = hosts[i].numel()
+            if outs[i].numel() != nh:
+                raise ValueError("out must have one float per host")
+            Hh[i] = _dev_ptr(hosts[i], _U32, "hosts").value if nh else None
+            O[i] = _dev_ptr(outs[i], (torch.float32,), "out").value if nh else None
+            NH[i] = nh
+        _check(lib().vbdr_batch_step(self._h, P, NP, Hh, NH, O, _stream(stream)))

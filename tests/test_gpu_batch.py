@@ -1,0 +1,123 @@
+"""Batched steps (persistent work-queue kernels, graph replay) against the
+same sketches stepped one by one through the single-sketch C ABI and against
+the CPU oracle: BDR state bit-exact, estimates bit-exact (both sides form the
+same exact integer sums and the same FP64 epilogue)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PARAMS = [
+    dict(m=70001, g=128, k=4, hash_seed=1, layout="fast"),
+    dict(m=3 * 4096 + 17, g=256, k=16, hash_seed=2, layout="small"),
+    dict(m=1 << 16, g=1024, k=128, hash_seed=3, layout="fast"),
+    dict(m=20000, g=512, k=8, hash_seed=4, layout="small"),
+    dict(m=(1 << 22) + 3, g=256, k=32, hash_seed=5, layout="fast"),
+]
+
+
+@pytest.fixture(scope="module")
+def V():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_13132_amd import vbdr
+    vbdr.lib()
+    return vbdr
+
+
+def _streams(seed, n_steps, sizes):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_steps):
+        step = []
+        for n in sizes:
+            aips = rng.integers(0, 2**32, 200, dtype=np.uint64).astype(np.uint32)
+            a = aips[rng.integers(0, 200, n)]
+            b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32) % np.uint32(rng.integers(1000, 10**6))
+            step.append(np.stack([a, b], 1).astype(np.uint32))
+        out.append(step)
+    return out
+
+
+def _hosts(steps):
+    return [np.unique(np.concatenate([st[i][:, 0] for st in steps] + [np.array([7, 8], np.uint32)]))
+            for i in range(len(steps[0]))]
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_matches_single_sketches(V, use_graph):
+    sizes = [5000, 0, 300000, 12345, 70000]  # uneven, one empty stream
+    steps = _streams(1, 4, sizes)
+    hosts = _hosts(steps)
+    bt = V.Batch(PARAMS)
+    bt.set_tuning(2048, 16, 4, use_graph)
+    singles = [V.Sketch(p["m"], p["g"], p["k"], p["hash_seed"], p["layout"]) for p in PARAMS]
+    hd = [V.to_device_u32(h) for h in hosts]
+    for t, step in enumerate(steps):
+        pd = [V.to_device_u32(p.reshape(-1)) for p in step]
+        outs = [torch.empty(len(h), dtype=torch.float32, device="cuda") for h in hosts]
+        bt.step(pd, hd, outs)
+        # eager work between replays on the caller's stream
+        scratch = torch.ones(1 << 20, device="cuda").sum()
+        for i, sk in enumerate(singles):
+            sk.scan_slice(pd[i])
+            sk.advance_slice()
+        for i, sk in enumerate(singles):
+            ref = sk.estimate(hd[i])
+            assert torch.equal(outs[i], ref), f"step {t} sketch {i} estimates differ"
+        assert float(scratch) == float(1 << 20)
+    for i, (b, s) in enumerate(zip(bt.sketches, singles)):
+        sb, ss = b.state(), s.state()
+        for key in ("dr", "bs", "reg", "hist"):
+            assert np.array_equal(sb[key], ss[key]), (i, key)
+        assert sb["t"] == ss["t"] == len(steps)
+
+
+def test_batch_matches_oracle(V):
+    from oracle import oracle as O
+    params = PARAMS[:4]
+    sizes = [4000, 900, 20000, 3000]
+    steps = _streams(2, 3, sizes)
+    hosts = _hosts(steps)
+    bt = V.Batch(params)
+    osks = [O.Sketch(p["m"], p["g"], p["k"], p["hash_seed"], O.GFAST if p["layout"] == "fast" else O.GSMALL)
+            for p in params]
+    hd = [V.to_device_u32(h) for h in hosts]
+    for step in steps:
+        outs = [torch.empty(len(h), dtype=torch.float32, device="cuda") for h in hosts]
+        bt.step([V.to_device_u32(p.reshape(-1)) for p in step], hd, outs)
+        for i, osk in enumerate(osks):
+            osk.scan(step[i])
+            osk.advance()
+            ref, raw = osk.estimate(hosts[i], with_raw=True)
+            ref = ref.astype(np.float64)
+            em = O.hll_from_hist(osk.state()["hist"], osk.m)
+            floor = 1e-12 * (osk.m * np.abs(raw) + osk.g * em) / (osk.m - osk.g)
+            got = outs[i].cpu().numpy().astype(np.float64)
+            assert np.all(np.abs(got - ref) <= 1e-6 * np.abs(ref) + floor)
+    for i, osk in enumerate(osks):
+        sb, so = bt.sketches[i].state(), osk.state()
+        for key in ("dr", "reg", "hist"):
+            assert np.array_equal(sb[key], so[key]), (i, key)
+
+
+def test_retuning_recaptures_and_autotuner(V):
+    from paper_1810_13132_amd import autotune
+    sizes = [20000, 5000, 60000, 1000, 8000]
+    steps = _streams(3, 2, sizes)
+    hosts = _hosts(steps)
+    hd = [V.to_device_u32(h) for h in hosts]
+    a, b = V.Batch(PARAMS), V.Batch(PARAMS)
+    pd = [V.to_device_u32(p.reshape(-1)) for p in steps[0]]
+    outs_a = [torch.empty(len(h), dtype=torch.float32, device="cuda") for h in hosts]
+    outs_b = [torch.empty(len(h), dtype=torch.float32, device="cuda") for h in hosts]
+    a.set_tuning(32768, 256, 16, True)
+    a.step(pd, hd, outs_a)
+    b.set_tuning(2048, 16, 4, True)
+    b.step(pd, hd, outs_b)
+    for x, y in zip(outs_a, outs_b):
+        assert torch.equal(x, y)
+    best, timings = autotune.tune(a, pd, hd, outs_a, candidates=[(2048, 16, 4), (8192, 64, 8)], reps=1)
+    assert len(timings) == 2 and best["scan_tile"] in (2048, 8192)
+    assert a.get_tuning()["scan_tile"] == best["scan_tile"]

@@ -197,6 +197,37 @@ def test_parity_large_pool_partitioned_estimate(V, O, layout):
     assert torch.equal(b.estimate(hd), sk.estimate(hd))
 
 
+@pytest.mark.parametrize("layout", ["fast", "small"])
+def test_binned_scan_matches_direct_and_overflows_safely(V, O, layout):
+    """Large pools scan in two passes through per-XCD bins.  A slice of one
+    repeated pair plus noise sends more records to one bin than it holds
+    (2^21 + 2^19 + 2^16 per 2^24-pair pass), exercising the direct fallback."""
+    m, g, k, seed = (1 << 22) + 5, 256, 5, 17
+    rng = np.random.default_rng(seed)
+    n_rep, n_rand = 3 << 20, 1 << 18
+    rep = np.tile(np.array([[123456789, 987654321]], np.uint32), (n_rep, 1))
+    rnd = rng.integers(0, 2**32, (n_rand, 2), dtype=np.uint64).astype(np.uint32)
+    slices = [np.concatenate([rep, rnd])[rng.permutation(n_rep + n_rand)], rnd[::-1].copy()]
+    a = V.Sketch(m, g, k, seed, layout)  # binned (default for this pool)
+    b = V.Sketch(m, g, k, seed, layout)
+    b.set_tuning(scan_binned=2)  # direct
+    assert a.get_tuning()["scan_binned"] == 1
+    osk = O.Sketch(m, g, k, seed, LAYOUT_CODE[layout])
+    for pairs in slices:
+        pd = _dev(V, pairs.reshape(-1))
+        a.scan_slice(pd)
+        b.scan_slice(pd)
+        osk.scan(pairs)
+        sa, sb = a.state(), b.state()
+        assert_state_equal(sa, osk.state(), layout, "binned scan vs oracle (open slice)")
+        for key in ("dr", "bs", "reg", "hist"):
+            assert np.array_equal(sa[key], sb[key]), key
+        a.advance_slice()
+        b.advance_slice()
+        osk.advance()
+    assert_state_equal(a.state(), osk.state(), layout, "binned scan vs oracle (closed)")
+
+
 def test_resume_from_exported_state(V, O):
     """Export after 5 slices, import into a fresh sketch, continue: identical
     to an uninterrupted run."""
