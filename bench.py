@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--layout", default="small", choices=["small", "fast"])
     ap.add_argument("--workload", default="line_rate", choices=["line_rate", "tiny", "batched"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -268,6 +270,14 @@ def main():
     acc = learned_accuracy()
     if acc:
         res["accuracy"] = acc
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["calibration_copy_bytes"] = src.numel() * 4
+        del src, dst
     if not args.no_cpu_baseline:
         rng = np.random.default_rng(0)
         act_last = hosts_all[np.nonzero(np.logical_or.reduce(window))[0]]

@@ -32,6 +32,7 @@ static vbdr_tuning default_tuning(int layout) {
   t.scan_blocks_per_cu = 16;
   t.est_blocks_per_cu = 32;
   t.scan_binned = 1;
+  t.est_binned = 2;
   return t;
 }
 
@@ -417,7 +418,9 @@ __global__ __launch_bounds__(kEstBlock) void k_estimate_part(const uint32_t* __r
 __global__ __launch_bounds__(256) void k_estimate_final(uint32_t nh, uint32_t g, uint32_t m, uint32_t parts,
                                                         const unsigned long long* __restrict__ hist,
                                                         const unsigned long long* __restrict__ part_u,
-                                                        const uint32_t* __restrict__ part_v, float* __restrict__ out) {
+                                                        const uint32_t* __restrict__ part_v,
+                                                        const unsigned long long* __restrict__ ovf_u,
+                                                        const uint32_t* __restrict__ ovf_v, float* __restrict__ out) {
   __shared__ double em_sh;
   if (threadIdx.x == 0) {
     uint64_t U = 0;
@@ -432,9 +435,107 @@ __global__ __launch_bounds__(256) void k_estimate_final(uint32_t nh, uint32_t g,
     U += part_u[(uint64_t)x * kPartChunk + h];
     V += part_v[(uint64_t)x * kPartChunk + h];
   }
+  if (ovf_u) {
+    U += ovf_u[h];
+    V += ovf_v[h];
+  }
   const double Es = hll_estimate(U, V, (double)g);
   const double n = noise_removed(Es, em_sh, (double)m, (double)g);
   out[h] = (float)(n > 0.0 ? n : 0.0);
+}
+
+// ------------------------------------------------ estimate, XCD-binned
+// The partitioned estimate hashes every (host, i) on all 8 XCDs.  Binned
+// instead: pass 1 hashes each (host, i) once and compacts its pidx into the
+// slot run of (range x, host) with wave ballots; pass 2 runs range x on the
+// workgroups of XCD x and gathers from the L2-resident nibble registers.
+// Entries beyond a run's capacity are gathered directly in pass 1 and kept as
+// a per-host overflow sum, so every (host, i) is counted exactly once.
+
+__global__ __launch_bounds__(kEstBlock) void k_est_bin(const uint32_t* __restrict__ hosts, uint32_t nh,
+                                                       const uint32_t* __restrict__ s1g, uint32_t g, uint32_t m,
+                                                       const uint8_t* __restrict__ reg, uint32_t cap, uint32_t hc,
+                                                       uint32_t* __restrict__ slots, uint32_t* __restrict__ cnt,
+                                                       unsigned long long* __restrict__ ovf_u,
+                                                       uint32_t* __restrict__ ovf_v) {
+  extern __shared__ uint32_t s1_lds[];
+  for (uint32_t i = threadIdx.x; i < g; i += kEstBlock) s1_lds[i] = s1g[i];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes < this one
+  for (uint32_t h = blockIdx.x * kEstWaves + wave; h < nh; h += gridDim.x * kEstWaves) {
+    const uint32_t kmix = mm3_key(hosts[h]);
+    uint32_t pos[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t oU = 0;
+    uint32_t oV = 0;
+    for (uint32_t i0 = 0; i0 < g; i0 += 64) {
+      const uint32_t i = i0 + lane;
+      const bool valid = i < g;
+      const uint32_t hh = valid ? mm3_seeded(kmix, s1_lds[i]) : 0u;
+      const uint32_t x = hh >> 29, p = reduce_m(hh, m);
+      uint32_t slot = 0;
+#pragma unroll
+      for (uint32_t xx = 0; xx < 8; ++xx) {
+        const uint64_t mask = __ballot(valid && x == xx);
+        if (valid && x == xx) slot = pos[xx] + (uint32_t)__popcll(mask & below);
+        pos[xx] += (uint32_t)__popcll(mask);
+      }
+      if (valid) {
+        if (slot < cap) {
+          slots[((uint64_t)x * hc + h) * cap + slot] = p;
+        } else {
+          const uint32_t r = reg[p];
+          oU += 1ull << (32 - r);
+          oV += r == 0;
+        }
+      }
+    }
+    oU = wave_sum_u64(oU);
+    oV = (uint32_t)wave_sum_u64(oV);
+#pragma unroll
+    for (uint32_t xx = 0; xx < 8; ++xx)
+      if (lane == (int)xx) cnt[(uint64_t)xx * hc + h] = pos[xx] < cap ? pos[xx] : cap;
+    if (lane == 0) {
+      ovf_u[h] = oU;
+      ovf_v[h] = oV;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kEstBlock) void k_est_gather(uint32_t nh, const uint8_t* __restrict__ reg,
+                                                          const uint8_t* __restrict__ reg4, uint32_t cap, uint32_t hc,
+                                                          const uint32_t* __restrict__ slots,
+                                                          const uint32_t* __restrict__ cnt,
+                                                          unsigned long long* __restrict__ part_u,
+                                                          uint32_t* __restrict__ part_v) {
+  const uint32_t x = blockIdx.x & 7u;  // workgroups are dispatched round-robin over the 8 XCDs
+  const uint32_t tiles = gridDim.x >> 3;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint32_t h = (blockIdx.x >> 3) * kEstWaves + wave; h < nh; h += tiles * kEstWaves) {
+    const uint32_t n = cnt[(uint64_t)x * hc + h];
+    const uint32_t* run = slots + ((uint64_t)x * hc + h) * cap;
+    uint64_t U = 0;
+    uint32_t V = 0;
+    for (uint32_t j0 = lane; j0 < n; j0 += 128) {
+      uint32_t p[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) p[u] = j0 + 64u * u < n ? run[j0 + 64u * u] : 0u;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (j0 + 64u * u >= n) continue;
+        const uint32_t nib = (reg4[p[u] >> 1] >> ((p[u] & 1u) << 2)) & 15u;
+        const uint32_t r = nib < 15u ? nib : (uint32_t)reg[p[u]];
+        U += 1ull << (32 - r);
+        V += r == 0;
+      }
+    }
+    U = wave_sum_u64(U);
+    V = (uint32_t)wave_sum_u64(V);
+    if (lane == 0) {
+      part_u[(uint64_t)x * kPartChunk + h] = U;
+      part_v[(uint64_t)x * kPartChunk + h] = V;
+    }
+  }
 }
 
 // Nibble copy of the registers (after a state import).
@@ -554,6 +655,15 @@ int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_
     const uint64_t part_bytes = sk->parts > 1 ? (uint64_t)sk->parts * kPartChunk * (8 + 4) : 0;
     // the binned scan needs 8 XCDs and pidx < 2^27 to pack its records
     const uint64_t bin_bytes = (sk->parts == 8 && m <= kBinMaxM) ? 8ull * kBinCap * 4 : 0;
+    // binned estimate: runs of g/8 + g/16 + 32 slots per (range, host), <= 512 MiB of runs
+    uint64_t est_bytes = 0;
+    if (sk->parts == 8 && g >= 64 && g <= kStageMaxG) {
+      sk->est_cap = g / 8 + g / 16 + 32;
+      uint64_t hc = (512ull << 20) / (8ull * sk->est_cap * 4);
+      hc = hc < kPartChunk ? hc : kPartChunk;
+      sk->est_hc = (uint32_t)(hc / 64 * 64);
+      est_bytes = 8ull * sk->est_hc * sk->est_cap * 4 + 8ull * sk->est_hc * 4 + (uint64_t)sk->est_hc * 12;
+    }
     if (hipMalloc(&sk->dr, dr_bytes) != hipSuccess || hipMalloc(&sk->reg, sk->mstride) != hipSuccess ||
         hipMalloc(&sk->reg4, sk->mstride / 2) != hipSuccess ||
         hipMalloc(&sk->hist, 64 * sizeof(unsigned long long)) != hipSuccess ||
@@ -564,14 +674,18 @@ int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_
         hipMalloc(&sk->hist_ws, (uint64_t)sk->parts * kLearnChunk * kBins * 4) != hipSuccess ||
         hipMalloc(&sk->est_ws, (uint64_t)kLearnChunk * 4) != hipSuccess ||
         (bin_bytes && hipMalloc(&sk->bins, bin_bytes) != hipSuccess) ||
-        (bin_bytes && hipMalloc(&sk->bin_fill, 64) != hipSuccess)) {
+        (bin_bytes && hipMalloc(&sk->bin_fill, 64) != hipSuccess) ||
+        (est_bytes && hipMalloc(&sk->est_slots, 8ull * sk->est_hc * sk->est_cap * 4) != hipSuccess) ||
+        (est_bytes && hipMalloc(&sk->est_cnt, 8ull * sk->est_hc * 4) != hipSuccess) ||
+        (est_bytes && hipMalloc(&sk->ovf_u, (uint64_t)sk->est_hc * 8) != hipSuccess) ||
+        (est_bytes && hipMalloc(&sk->ovf_v, (uint64_t)sk->est_hc * 4) != hipSuccess)) {
       (void)hipGetLastError();
       rc = vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed",
                 (unsigned long long)(dr_bytes + seen_bytes + sk->mstride * 3 / 2 + part_bytes));
       break;
     }
     sk->bytes = dr_bytes + seen_bytes + sk->mstride * 3 / 2 + 64 * sizeof(unsigned long long) + (uint64_t)g * 4 +
-                part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + bin_bytes;
+                part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + bin_bytes + est_bytes;
     hipStream_t st = nullptr;
     if ((rc = init_state(sk, st)) != VBDR_OK) break;
     hipLaunchKernelGGL(k_seeds, dim3((g + 255) / 256), dim3(256), 0, st, sk->s1, g, sk->A0);
@@ -610,6 +724,10 @@ void vbdr_sketch_destroy(vbdr_sketch* sk) {
   if (sk->est_ws) (void)hipFree(sk->est_ws);
   if (sk->bins) (void)hipFree(sk->bins);
   if (sk->bin_fill) (void)hipFree(sk->bin_fill);
+  if (sk->est_slots) (void)hipFree(sk->est_slots);
+  if (sk->est_cnt) (void)hipFree(sk->est_cnt);
+  if (sk->ovf_u) (void)hipFree(sk->ovf_u);
+  if (sk->ovf_v) (void)hipFree(sk->ovf_v);
   if (prev >= 0 && prev != sk->device) (void)hipSetDevice(prev);
   delete sk;
 }
@@ -618,6 +736,7 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
   if (!sk || !tuning) return vbdr_fail(VBDR_EINVAL, "NULL argument");
   if (tuning->scan_test_first < 0 || tuning->scan_test_first > 2) return vbdr_fail(VBDR_EINVAL, "scan_test_first must be 0, 1 or 2");
   if (tuning->scan_binned < 0 || tuning->scan_binned > 2) return vbdr_fail(VBDR_EINVAL, "scan_binned must be 0, 1 or 2");
+  if (tuning->est_binned < 0 || tuning->est_binned > 2) return vbdr_fail(VBDR_EINVAL, "est_binned must be 0, 1 or 2");
   if (tuning->scan_blocks_per_cu > 64 || tuning->est_blocks_per_cu > 64)
     return vbdr_fail(VBDR_EINVAL, "blocks per CU must be at most 64");
   sk->tune = default_tuning(sk->layout);
@@ -625,6 +744,7 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
   if (tuning->scan_blocks_per_cu) sk->tune.scan_blocks_per_cu = tuning->scan_blocks_per_cu;
   if (tuning->est_blocks_per_cu) sk->tune.est_blocks_per_cu = tuning->est_blocks_per_cu;
   if (tuning->scan_binned) sk->tune.scan_binned = tuning->scan_binned;
+  if (tuning->est_binned) sk->tune.est_binned = tuning->est_binned;
   return VBDR_OK;
 }
 
@@ -723,6 +843,26 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
   const bool stage = sk->g <= kStageMaxG;
   const bool extra = raw_es_dev || hist_dev;
   const size_t lds = stage ? (size_t)sk->g * 4 : 0;
+  if (sk->est_slots && sk->tune.est_binned == 1 && !extra) {
+    const uint32_t hc = sk->est_hc, cap = sk->est_cap;
+    for (uint64_t c = 0; c < n_hosts; c += hc) {
+      const uint32_t nh = (uint32_t)(n_hosts - c < hc ? n_hosts - c : hc);
+      const uint32_t bgrid = grid_cap(sk, (nh + kEstWaves - 1) / kEstWaves, sk->tune.est_blocks_per_cu);
+      hipLaunchKernelGGL(k_est_bin, dim3(bgrid), dim3(kEstBlock), (size_t)sk->g * 4, st, hosts_dev + c, nh, sk->s1,
+                         sk->g, (uint32_t)sk->m, sk->reg, cap, hc, sk->est_slots, sk->est_cnt, sk->ovf_u, sk->ovf_v);
+      VBDR_LAUNCHED("k_est_bin");
+      const uint64_t want = (nh + kEstWaves - 1) / kEstWaves;
+      const uint64_t capb = (uint64_t)sk->n_cu * sk->tune.est_blocks_per_cu / 8;
+      const uint32_t tiles = (uint32_t)(want < capb ? want : (capb ? capb : 1));
+      hipLaunchKernelGGL(k_est_gather, dim3(tiles * 8), dim3(kEstBlock), 0, st, nh, sk->reg, sk->reg4, cap, hc,
+                         sk->est_slots, sk->est_cnt, sk->part_u, sk->part_v);
+      VBDR_LAUNCHED("k_est_gather");
+      hipLaunchKernelGGL(k_estimate_final, dim3((nh + 255) / 256), dim3(256), 0, st, nh, sk->g, (uint32_t)sk->m, 8u,
+                         sk->hist, sk->part_u, sk->part_v, sk->ovf_u, sk->ovf_v, out_dev + c);
+      VBDR_LAUNCHED("k_estimate_final");
+    }
+    return VBDR_OK;
+  }
   if (sk->parts > 1 && !extra) {
     const uint32_t parts = (uint32_t)sk->parts, shift = parts == 8 ? 29u : 30u;
     auto kern = stage ? k_estimate_part<true, false> : k_estimate_part<false, false>;
@@ -735,7 +875,8 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
                          (uint32_t)sk->m, sk->reg, sk->reg4, parts, shift, sk->part_u, sk->part_v, nullptr);
       VBDR_LAUNCHED("k_estimate_part");
       hipLaunchKernelGGL(k_estimate_final, dim3((nh + 255) / 256), dim3(256), 0, st, nh, sk->g, (uint32_t)sk->m,
-                         parts, sk->hist, sk->part_u, sk->part_v, out_dev + c);
+                         parts, sk->hist, sk->part_u, sk->part_v, (const unsigned long long*)nullptr,
+                         (const uint32_t*)nullptr, out_dev + c);
       VBDR_LAUNCHED("k_estimate_final");
     }
     return VBDR_OK;

@@ -39,6 +39,11 @@ struct vbdr_sketch {
   float* est_ws;               // [kLearnChunk] plain estimates of a histogram pass
   uint32_t* bins;              // [parts][kBinCap] binned scan records (large pools)
   uint32_t* bin_fill;          // [parts] records written per bin
+  uint32_t* est_slots;         // [8][est_hc][est_cap] binned-estimate pidx runs
+  uint32_t* est_cnt;           // [8][est_hc] run lengths
+  unsigned long long* ovf_u;   // [est_hc] overflow partial sums
+  uint32_t* ovf_v;             // [est_hc]
+  uint32_t est_cap, est_hc;
   uint64_t bytes;
   vbdr_tuning tune;
 };

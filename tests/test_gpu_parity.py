@@ -194,7 +194,11 @@ def test_parity_large_pool_partitioned_estimate(V, O, layout):
     b = V.Sketch(m, g, k, seed, layout)
     b.load_state(sk.state())
     hd = _dev(V, hosts)
-    assert torch.equal(b.estimate(hd), sk.estimate(hd))
+    plain = sk.estimate(hd)
+    assert torch.equal(b.estimate(hd), plain)
+    # the binned estimate (each (host, i) hashed once) gives the same bits
+    sk.set_tuning(est_binned=1)
+    assert torch.equal(sk.estimate(hd), plain)
 
 
 @pytest.mark.parametrize("layout", ["fast", "small"])
