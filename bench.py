@@ -153,13 +153,69 @@ def run_batched(args):
     print(json.dumps(res), flush=True)
 
 
+def run_stress(args):
+    """Skewed contention: 16 planted superspreaders (10^6..10^7 opposite hosts)
+    among 2^24 hosts, 2^27 pairs per slice into m = 2^24 BDRs (g = 2048,
+    k = 128).  Each step estimates the superspreaders plus 2^16 sampled
+    background hosts; errors are reported per group over the slices seen."""
+    import numpy as np
+    import torch
+    from paper_1810_13132_amd import learn, synth, vbdr
+    torch.cuda.set_device(0)
+    w = synth.STRESS
+    K, W = args.steps, args.warmup
+    st = synth.Stream(w)
+    rng = np.random.default_rng(5)
+    heavy = np.arange(w.n_heavy)
+    background = rng.choice(np.arange(w.n_heavy, w.hosts), size=1 << 16, replace=False)
+    sel = np.concatenate([heavy, background])
+    hosts = vbdr.to_device_u32(st.aip[sel])
+    host_keys = torch.from_numpy(st.aip[sel].astype(np.int64)).cuda()
+    sk = vbdr.Sketch(w.m, w.g, w.k, w.seed, args.layout)
+    out = torch.empty(len(sel), dtype=torch.float32, device="cuda")
+    seen_keys = []
+    times = []
+    for t in range(W + K):
+        pd = vbdr.to_device_u32(st.slice(t).reshape(-1))
+        p = pd.view(-1, 2).to(torch.int64) & 0xFFFFFFFF
+        keep = torch.isin(p[:, 0], host_keys)
+        seen_keys.append(torch.unique((p[keep, 0] << 32) | p[keep, 1]))
+        del p, keep
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        sk.scan_slice(pd)
+        sk.advance_slice()
+        sk.estimate(hosts, out)
+        b.record()
+        b.synchronize()
+        if t >= W:
+            times.append(a.elapsed_time(b))
+        log(f"stress slice {t}: {times[-1] if t >= W else a.elapsed_time(b):.2f} ms")
+        del pd
+    truth = learn.window_truth(seen_keys[-w.k:], host_keys)
+    est = out.to(torch.float64)
+    ms = float(np.mean(times))
+    res = {"metric": METRIC, "value": w.pairs_per_slice / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": K,
+           "warmup": W, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "stress", "hosts": w.hosts, "pairs_per_slice": w.pairs_per_slice, "m": w.m,
+                      "g": w.g, "k": w.k, "layout": args.layout, "estimated_hosts": len(sel)},
+           "rms_rel_superspreaders": learn.rms_rel(est[:w.n_heavy], truth[:w.n_heavy]),
+           "rms_rel_background": learn.rms_rel(est[w.n_heavy:], truth[w.n_heavy:]),
+           "superspreader_truth": [int(v) for v in truth[:w.n_heavy].cpu()],
+           "superspreader_estimate": [float(v) for v in est[:w.n_heavy].cpu()],
+           "slices_in_window": min(W + K, w.k)}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--layout", default="small", choices=["small", "fast"])
-    ap.add_argument("--workload", default="line_rate", choices=["line_rate", "tiny", "batched"])
+    ap.add_argument("--workload", default="line_rate", choices=["line_rate", "tiny", "batched", "stress"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for rocprofv3 byte counters)")
@@ -176,6 +232,8 @@ def main():
 
     if args.workload == "batched":
         return run_batched(args)
+    if args.workload == "stress":
+        return run_stress(args)
     w = synth.LINE_RATE if args.workload == "line_rate" else synth.TINY
     K, W = args.steps, args.warmup
     n_slices = W + K

@@ -143,11 +143,14 @@ int vbdr_sketch_info(const vbdr_sketch *sk, vbdr_info *out);
  *   scan_binned        1: pools of 2^22..2^27 BDRs scan in two passes, the
  *                      pairs first binned by pool range so that each XCD
  *                      updates only its own range; 2: always scan directly
- *                      (default: 1);
+ *                      (default: 2);
  *   est_binned         for pools of 2^22 BDRs and more: 1 = hash every
  *                      (host, i) once and bin the gathers by XCD range;
  *                      2 = hash on every XCD and gather only the own range
- *                      (default: 2).
+ *                      (default: 2);
+ *   est_parts          pool ranges of the XCD-partitioned estimate, 8 (one
+ *                      per XCD, default) or 4 (two XCDs per range: half the
+ *                      hashing, twice the cache footprint per XCD).
  */
 typedef struct vbdr_tuning {
     int32_t scan_test_first;
@@ -155,6 +158,7 @@ typedef struct vbdr_tuning {
     uint32_t est_blocks_per_cu;
     int32_t scan_binned;
     int32_t est_binned;
+    int32_t est_parts;
 } vbdr_tuning;
 int vbdr_sketch_set_tuning(vbdr_sketch *sk, const vbdr_tuning *tuning);
 int vbdr_sketch_get_tuning(const vbdr_sketch *sk, vbdr_tuning *tuning);

@@ -40,7 +40,7 @@ __device__ __forceinline__ uint32_t mm3_key(uint32_t x) {
 __device__ __forceinline__ uint32_t mm3_seeded(uint32_t kmix, uint32_t seed) {
   uint32_t h = seed ^ kmix;
   h = (h << 13) | (h >> 19);
-  h = h * 5u + 0xe6546b64u;
+  h = (h << 2) + h + 0xe6546b64u;  // h * 5 + c
   h ^= 4u;
   h ^= h >> 16;
   h *= 0x85ebca6bu;

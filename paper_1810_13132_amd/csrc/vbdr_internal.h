@@ -11,10 +11,10 @@ constexpr uint64_t kPad = 4096;             // BDR padding granule of a plane
 constexpr uint32_t kStageMaxG = 8192;       // s1 staged in LDS up to 32 KiB
 constexpr uint32_t kCusPerXcd = 32;         // gfx950: 8 XCDs x 32 CUs
 constexpr uint64_t kPartMinM = 1ull << 22;  // pools whose registers outgrow one XCD's L2
-constexpr uint32_t kPartChunk = 1u << 17;   // hosts per partitioned-estimate pass
+constexpr uint32_t kPartChunk = 1u << 20;   // hosts per partitioned-estimate pass
 constexpr uint32_t kLearnChunk = 1u << 15;  // hosts per histogram pass of the learned estimate
 constexpr uint64_t kBinMaxM = 1ull << 27;   // binned scan records pack (pidx << 5) | (LBP1 - 1)
-constexpr uint32_t kBinChunk = 1u << 24;    // pairs per binned-scan pass
+constexpr uint32_t kBinChunk = 1u << 24;    // pairs per binned-scan pass (records stay cache resident)
 constexpr uint32_t kBinCap = kBinChunk / 8 + kBinChunk / 32 + 65536;  // records per bin per pass
 
 struct vbdr_sketch {

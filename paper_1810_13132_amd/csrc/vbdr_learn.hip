@@ -77,10 +77,18 @@ __global__ __launch_bounds__(256) void k_features(uint32_t nh, uint32_t parts, c
 constexpr int kInfBlock = 256;
 constexpr int kInfWaves = kInfBlock / 64;
 
+// DIRECT: each wave gathers its 16 hosts' registers itself (pools whose
+// registers are cache resident), building each histogram in LDS; otherwise
+// the histograms come from a histogram pass (hws, summed over parts).
+template <bool DIRECT>
 __global__ __launch_bounds__(kInfBlock) void k_learned(uint32_t nh, uint32_t parts, const uint32_t* __restrict__ hws,
+                                                       const uint32_t* __restrict__ hosts,
+                                                       const uint32_t* __restrict__ s1g, const uint8_t* __restrict__ reg,
                                                        const unsigned long long* __restrict__ hist, uint32_t g,
                                                        uint32_t m, const MlpDev* __restrict__ mlp,
                                                        float* __restrict__ out, uint8_t* __restrict__ used_fallback) {
+  extern __shared__ uint32_t s1_lds[];
+  __shared__ uint32_t lh[kInfWaves][4][kBins];  // DIRECT: four histogram copies per wave
   __shared__ __attribute__((aligned(16))) uint16_t sw1[kHid * kInPad];
   __shared__ __attribute__((aligned(16))) uint16_t sw2[kHid * kHid];
   __shared__ __attribute__((aligned(16))) uint16_t sx[kInfWaves][16 * kInPad];
@@ -98,6 +106,10 @@ __global__ __launch_bounds__(kInfBlock) void k_learned(uint32_t nh, uint32_t par
   if (threadIdx.x == 0) {
     sem = pool_estimate(hist, (double)m);
     spool_bad = 0;
+  }
+  if constexpr (DIRECT) {
+    for (uint32_t i = threadIdx.x; i < g; i += kInfBlock) s1_lds[i] = s1g[i];
+    for (int i = threadIdx.x; i < kInfWaves * 4 * kBins; i += kInfBlock) (&lh[0][0][0])[i] = 0;
   }
   if (threadIdx.x < kInPad) {
     const int c = threadIdx.x;
@@ -119,35 +131,83 @@ __global__ __launch_bounds__(kInfBlock) void k_learned(uint32_t nh, uint32_t par
   uint16_t* H1 = sh1[wave];
   const uint32_t ntiles = (nh + 15) / 16;
   for (uint32_t tile = blockIdx.x * kInfWaves + wave; tile < ntiles; tile += gridDim.x * kInfWaves) {
-    // 1. features of 16 hosts: lane = 4 * row + quarter
-    const int row = lane >> 2, q = lane & 3;
-    const uint32_t h = tile * 16 + row;
-    const bool live = h < nh;
-    uint64_t U = 0;
-    uint32_t V = 0;
-    int bad = 0;
-    for (int r = q; r < kBins; r += 4) {
-      uint32_t c = 0;
-      if (live)
-        for (uint32_t x = 0; x < parts; ++x) c += hws[((uint64_t)x * kLearnChunk + h) * kBins + r];
-      const float f = (float)((double)c / (double)g);
-      X[row * kInPad + r] = f2bf(f);
-      U += (uint64_t)c << (32 - r);
-      if (r == 0) V = c;
-      if (mlp->has_env && !(f >= mlp->env_lo[r] && f <= mlp->env_hi[r])) bad = 1;
-    }
-    for (int c = kBins + q; c < kInPad; c += 4) X[row * kInPad + c] = spool_bf[c];
-    U += __shfl_xor(U, 1);
-    U += __shfl_xor(U, 2);
-    V += __shfl_xor(V, 1);
-    V += __shfl_xor(V, 2);
-    bad |= __shfl_xor(bad, 1);
-    bad |= __shfl_xor(bad, 2);
-    if (q == 0) {
-      const double Es = hll_estimate(U, V, (double)g);
-      const double n = noise_removed(Es, Em, (double)m, (double)g);
-      splain[wave][row] = (float)(n > 0.0 ? n : 0.0);
-      sflag[wave][row] = bad | spool_bad;
+    if constexpr (DIRECT) {
+      // 1. per host: gathers -> LDS histogram -> features, plain estimate
+      for (int row = 0; row < 16; ++row) {
+        const uint32_t h = tile * 16 + row;
+        if (h < nh) {
+          const uint32_t kmix = mm3_key(hosts[h]);
+          uint32_t* my = lh[wave][lane & 3];
+          for (uint32_t i0 = lane; i0 < g; i0 += 64 * 8) {
+            uint32_t r[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const uint32_t i = i0 + 64u * u;
+              r[u] = i < g ? (uint32_t)reg[reduce_m(mm3_seeded(kmix, s1_lds[i]), m)] : 255u;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (r[u] != 255u) atomicAdd(&my[r[u]], 1u);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        uint32_t c = 0;
+        if (lane < kBins) {
+          c = lh[wave][0][lane] + lh[wave][1][lane] + lh[wave][2][lane] + lh[wave][3][lane];
+          lh[wave][0][lane] = lh[wave][1][lane] = lh[wave][2][lane] = lh[wave][3][lane] = 0;
+          const float f = (float)((double)c / (double)g);
+          X[row * kInPad + lane] = f2bf(f);
+        } else if (lane < kInPad - kBins + kBins && lane >= kBins) {
+          X[row * kInPad + lane] = spool_bf[lane];  // columns 33..63
+        }
+        if (lane + 64 < kInPad) X[row * kInPad + lane + 64] = spool_bf[lane + 64];  // columns 64..95
+        const bool bad_bin = lane < kBins && mlp->has_env &&
+                             !((float)((double)c / (double)g) >= mlp->env_lo[lane] &&
+                               (float)((double)c / (double)g) <= mlp->env_hi[lane]);
+        const uint64_t Ub = wave_sum_u64(lane < kBins ? (uint64_t)c << (32 - lane) : 0ull);
+        const uint32_t Vb = (uint32_t)__shfl(c, 0);
+        const int bad = __ballot(bad_bin) != 0ull;
+        if (lane == 0) {
+          const double Es = hll_estimate(Ub, Vb, (double)g);
+          const double n = noise_removed(Es, Em, (double)m, (double)g);
+          splain[wave][row] = (float)(n > 0.0 ? n : 0.0);
+          sflag[wave][row] = bad | spool_bad;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    } else {
+  // 1. features of 16 hosts: lane = 4 * row + quarter
+      const int row = lane >> 2, q = lane & 3;
+      const uint32_t h = tile * 16 + row;
+      const bool live = h < nh;
+      uint64_t U = 0;
+      uint32_t V = 0;
+      int bad = 0;
+      for (int r = q; r < kBins; r += 4) {
+        uint32_t c = 0;
+        if (live)
+          for (uint32_t x = 0; x < parts; ++x) c += hws[((uint64_t)x * kLearnChunk + h) * kBins + r];
+        const float f = (float)((double)c / (double)g);
+        X[row * kInPad + r] = f2bf(f);
+        U += (uint64_t)c << (32 - r);
+        if (r == 0) V = c;
+        if (mlp->has_env && !(f >= mlp->env_lo[r] && f <= mlp->env_hi[r])) bad = 1;
+      }
+      for (int c = kBins + q; c < kInPad; c += 4) X[row * kInPad + c] = spool_bf[c];
+      U += __shfl_xor(U, 1);
+      U += __shfl_xor(U, 2);
+      V += __shfl_xor(V, 1);
+      V += __shfl_xor(V, 2);
+      bad |= __shfl_xor(bad, 1);
+      bad |= __shfl_xor(bad, 2);
+      if (q == 0) {
+        const double Es = hll_estimate(U, V, (double)g);
+        const double n = noise_removed(Es, Em, (double)m, (double)g);
+        splain[wave][row] = (float)(n > 0.0 ? n : 0.0);
+        sflag[wave][row] = bad | spool_bad;
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -384,14 +444,27 @@ int vbdr_estimate_learned(vbdr_sketch* sk, const vbdr_mlp* mlp, const uint32_t* 
   if (mlp->device != sk->device) return vbdr_fail(VBDR_EINVAL, "mlp and sketch live on different devices");
   if (int rc = vbdr_check_device(sk)) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (sk->parts == 1 && sk->g <= kStageMaxG && n_hosts < (1ull << 32)) {
+    // registers cache resident: one fused launch, gathers feed the MLP tile directly
+    const uint32_t nh = (uint32_t)n_hosts;
+    const uint32_t tiles = (uint32_t)((n_hosts + 15) / 16);
+    const uint32_t want = (tiles + kInfWaves - 1) / kInfWaves;
+    const uint32_t cap = (uint32_t)sk->n_cu * 8;
+    hipLaunchKernelGGL(k_learned<true>, dim3(want < cap ? want : cap), dim3(kInfBlock), (size_t)sk->g * 4, st, nh, 1u,
+                       (const uint32_t*)nullptr, hosts_dev, sk->s1, sk->reg, sk->hist, sk->g, (uint32_t)sk->m,
+                       mlp->dev, out_dev, used_fallback_dev);
+    VBDR_LAUNCHED("k_learned(direct)");
+    return VBDR_OK;
+  }
   for (uint64_t c = 0; c < n_hosts; c += kLearnChunk) {
     const uint32_t nh = (uint32_t)(n_hosts - c < kLearnChunk ? n_hosts - c : kLearnChunk);
     if (int rc = vbdr_hist_pass(sk, hosts_dev + c, nh, st)) return rc;
     const uint32_t tiles = (nh + 15) / 16;
     const uint32_t want = (tiles + kInfWaves - 1) / kInfWaves;
     const uint32_t cap = (uint32_t)sk->n_cu * 4;
-    hipLaunchKernelGGL(k_learned, dim3(want < cap ? want : cap), dim3(kInfBlock), 0, st, nh, (uint32_t)sk->parts,
-                       sk->hist_ws, sk->hist, sk->g, (uint32_t)sk->m, mlp->dev, out_dev + c,
+    hipLaunchKernelGGL(k_learned<false>, dim3(want < cap ? want : cap), dim3(kInfBlock), 0, st, nh,
+                       (uint32_t)sk->parts, sk->hist_ws, (const uint32_t*)nullptr, (const uint32_t*)nullptr,
+                       (const uint8_t*)nullptr, sk->hist, sk->g, (uint32_t)sk->m, mlp->dev, out_dev + c,
                        used_fallback_dev ? used_fallback_dev + c : nullptr);
     VBDR_LAUNCHED("k_learned");
   }

@@ -33,7 +33,8 @@ def log(*a):
 def window_truth(window_keys, host_keys):
     """Exact |OP(aip)| over the window for each host (int64 aip keys)."""
     u = torch.unique(torch.cat(window_keys))
-    vals, cnts = torch.unique(u >> 32, return_counts=True)
+    # keys are aip << 32 | bip in int64: shift logically (mask the sign extension)
+    vals, cnts = torch.unique((u >> 32) & 0xFFFFFFFF, return_counts=True)
     pos = torch.searchsorted(vals, host_keys).clamp(max=max(len(vals) - 1, 0))
     hit = vals[pos] == host_keys
     return torch.where(hit, cnts[pos], torch.zeros_like(cnts[pos]))

@@ -37,7 +37,8 @@ class Info(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("scan_test_first", C.c_int32), ("scan_blocks_per_cu", C.c_uint32),
-                ("est_blocks_per_cu", C.c_uint32), ("scan_binned", C.c_int32), ("est_binned", C.c_int32)]
+                ("est_blocks_per_cu", C.c_uint32), ("scan_binned", C.c_int32), ("est_binned", C.c_int32),
+                ("est_parts", C.c_int32)]
 
 
 class BatchParams(C.Structure):
@@ -172,15 +173,16 @@ class Sketch:
         return out
 
     def set_tuning(self, scan_test_first: int = 0, scan_blocks_per_cu: int = 0, est_blocks_per_cu: int = 0,
-                   scan_binned: int = 0, est_binned: int = 0):
-        t = Tuning(scan_test_first, scan_blocks_per_cu, est_blocks_per_cu, scan_binned, est_binned)
+                   scan_binned: int = 0, est_binned: int = 0, est_parts: int = 0):
+        t = Tuning(scan_test_first, scan_blocks_per_cu, est_blocks_per_cu, scan_binned, est_binned, est_parts)
         _check(lib().vbdr_sketch_set_tuning(self._h, C.byref(t)))
 
     def get_tuning(self) -> dict:
         t = Tuning()
         _check(lib().vbdr_sketch_get_tuning(self._h, C.byref(t)))
         return {"scan_test_first": t.scan_test_first, "scan_blocks_per_cu": t.scan_blocks_per_cu,
-                "est_blocks_per_cu": t.est_blocks_per_cu, "scan_binned": t.scan_binned, "est_binned": t.est_binned}
+                "est_blocks_per_cu": t.est_blocks_per_cu, "scan_binned": t.scan_binned, "est_binned": t.est_binned,
+                "est_parts": t.est_parts}
 
     @property
     def t(self) -> int:

@@ -212,7 +212,8 @@ def test_binned_scan_matches_direct_and_overflows_safely(V, O, layout):
     rep = np.tile(np.array([[123456789, 987654321]], np.uint32), (n_rep, 1))
     rnd = rng.integers(0, 2**32, (n_rand, 2), dtype=np.uint64).astype(np.uint32)
     slices = [np.concatenate([rep, rnd])[rng.permutation(n_rep + n_rand)], rnd[::-1].copy()]
-    a = V.Sketch(m, g, k, seed, layout)  # binned (default for this pool)
+    a = V.Sketch(m, g, k, seed, layout)
+    a.set_tuning(scan_binned=1)  # binned
     b = V.Sketch(m, g, k, seed, layout)
     b.set_tuning(scan_binned=2)  # direct
     assert a.get_tuning()["scan_binned"] == 1
