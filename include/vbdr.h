@@ -76,6 +76,8 @@ typedef struct vbdr_info {
     uint32_t A0, A1;      /* hash seeds derived from hash_seed */
     uint64_t t;           /* slices closed so far */
     uint64_t state_bytes; /* device bytes held by the sketch */
+    int32_t est_parts;    /* pool ranges of the estimate's XCD-partitioned gathers (1 = direct) */
+    int32_t scan_deferred; /* 1 when scans defer their updates to the advance (scan_defer = 1) */
 } vbdr_info;
 
 /*
@@ -150,7 +152,21 @@ int vbdr_sketch_info(const vbdr_sketch *sk, vbdr_info *out);
  *                      (default: 2);
  *   est_parts          pool ranges of the XCD-partitioned estimate, 8 (one
  *                      per XCD, default) or 4 (two XCDs per range: half the
- *                      hashing, twice the cache footprint per XCD).
+ *                      hashing, twice the cache footprint per XCD);
+ *   est_bin_hosts      hosts per pass of the binned estimate (its gather
+ *                      runs take about 4*g bytes per host; default: as many
+ *                      as the run buffer holds);
+ *   est_bin_cap        slots per (host, range) run of the binned estimate,
+ *                      at most the default g/8 + g/16 + 32; entries beyond
+ *                      it are gathered directly by the first pass;
+ *   scan_defer         for pools of 2^22..2^27 BDRs: 1 = the scan only
+ *                      writes each pair's (pidx, LBP1) record, sorted by
+ *                      tile of 2^15 BDRs, and the advance applies the records
+ *                      from LDS while it streams the tile (default); 2 = the
+ *                      scan updates the pool itself (direct or binned).
+ *                      Up to 2 records per BDR per slice are deferred; the
+ *                      rest are applied by the scan.  The sketch state seen
+ *                      through vbdr_export_state is the same either way.
  */
 typedef struct vbdr_tuning {
     int32_t scan_test_first;
@@ -159,6 +175,9 @@ typedef struct vbdr_tuning {
     int32_t scan_binned;
     int32_t est_binned;
     int32_t est_parts;
+    uint32_t est_bin_hosts;
+    uint32_t est_bin_cap;
+    int32_t scan_defer;
 } vbdr_tuning;
 int vbdr_sketch_set_tuning(vbdr_sketch *sk, const vbdr_tuning *tuning);
 int vbdr_sketch_get_tuning(const vbdr_sketch *sk, vbdr_tuning *tuning);

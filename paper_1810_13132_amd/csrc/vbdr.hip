@@ -34,6 +34,9 @@ static vbdr_tuning default_tuning(int layout) {
   t.scan_binned = 2;  // measured: the direct scan is as fast or faster at 2^26 pairs per slice
   t.est_binned = 2;
   t.est_parts = 8;
+  t.est_bin_hosts = 0;
+  t.est_bin_cap = 0;
+  t.scan_defer = 1;
   return t;
 }
 
@@ -294,6 +297,226 @@ __global__ __launch_bounds__(kAdvBlock) void k_advance(uint8_t* __restrict__ dr,
   }
 }
 
+// ------------------------------------------- scan + advance, deferred apply
+// For large pools every scan update is a random access that misses every
+// cache.  Deferred: the scan only computes each pair's record
+// (pidx << 5 | LBP1-1), sorts a chunk of kDeferChunk records by tile of
+// kDeferTile BDRs in LDS and appends each tile's share to that tile's record
+// run with one atomic per (chunk, tile).  The advance that closes the slice
+// runs one workgroup per tile: it ORs the tile's records into per-plane bit
+// words in LDS and applies them while it streams the tile's DRs, which it
+// reads and writes anyway.  Records beyond a run's capacity are applied by the
+// scan itself, as the direct scan would (fast layout: the last word of
+// `fill` then tells the advance to read the bsLBP1 planes too).  Updates are
+// idempotent (Sec. 4.2), so deferring them to the close of the slice leaves
+// the closed state unchanged.
+
+constexpr int kDeferBlock = 1024;
+constexpr int kDeferPer = 32;
+constexpr uint32_t kDeferChunk = kDeferBlock * kDeferPer;
+constexpr uint32_t kDeferWords = kDeferTile / 32;  // bit words per plane of a tile
+static_assert(kDeferTile == kDeferBlock * 32, "one thread advances 32 BDRs of a tile");
+static_assert(kPad % 32 == 0, "tiles of the deferred advance start on whole bit words");
+
+// Exclusive prefix sums of a[0..n) into out[0..n) by one workgroup of
+// kDeferBlock threads, n <= 4 * kDeferBlock; wsum holds kDeferBlock / 64 words.
+__device__ void block_exclusive_scan(const uint32_t* a, uint32_t* out, uint32_t n, uint32_t* wsum) {
+  const uint32_t per = (n + kDeferBlock - 1) / kDeferBlock;
+  const uint32_t lo = threadIdx.x * per;
+  uint32_t v[4] = {0, 0, 0, 0}, sum = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < 4; ++j)
+    if (j < per && lo + j < n) sum += (v[j] = a[lo + j]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = sum;  // inclusive scan over the wave
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(inc, d);
+    if (lane >= d) inc += t;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < kDeferBlock / 64; ++w) {
+      const uint32_t t = wsum[w];
+      wsum[w] = run;
+      run += t;
+    }
+  }
+  __syncthreads();
+  uint32_t off = wsum[wave] + inc - sum;
+#pragma unroll
+  for (uint32_t j = 0; j < 4; ++j)
+    if (j < per && lo + j < n) {
+      out[lo + j] = off;
+      off += v[j];
+    }
+  __syncthreads();
+}
+
+template <bool FAST>
+__device__ __forceinline__ void apply_record(uint32_t rec, uint8_t* dr, uint64_t mstride, uint32_t* seen,
+                                             uint64_t wstride) {
+  const uint32_t pidx = rec >> 5, plane = rec & 31u;
+  if constexpr (FAST)
+    atomicOr(seen + (uint64_t)plane * wstride + (pidx >> 5), 1u << (pidx & 31));
+  else
+    dr[(uint64_t)plane * mstride + pidx] = 0;
+}
+
+// LDS: cnt[tiles], start[tiles], sorted[kDeferChunk], then s1 if staged.
+template <bool FAST>
+__global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restrict__ pairs, uint64_t n,
+                                                            const uint32_t* __restrict__ s1g, uint32_t g, int stage,
+                                                            uint32_t b, uint32_t A1, uint32_t m, uint32_t tiles,
+                                                            uint32_t cap, uint32_t* __restrict__ recs,
+                                                            unsigned long long* __restrict__ fill,
+                                                            uint8_t* __restrict__ dr, uint64_t mstride,
+                                                            uint32_t* __restrict__ seen, uint64_t wstride) {
+  extern __shared__ uint32_t lds[];
+  __shared__ uint32_t wsum[kDeferBlock / 64];
+  uint32_t* cnt = lds;
+  uint32_t* start = lds + tiles;
+  uint32_t* sorted = lds + 2 * tiles;
+  const uint32_t* s1 = s1g;
+  if (stage) {
+    uint32_t* s = sorted + kDeferChunk;
+    for (uint32_t i = threadIdx.x; i < g; i += kDeferBlock) s[i] = s1g[i];
+    s1 = s;
+  }
+  for (uint64_t c0 = (uint64_t)blockIdx.x * kDeferChunk; c0 < n; c0 += (uint64_t)gridDim.x * kDeferChunk) {
+    for (uint32_t t = threadIdx.x; t < tiles; t += kDeferBlock) cnt[t] = 0;
+    __syncthreads();
+    // records and their ranks within the tile (< kDeferChunk, 16 bits each)
+    uint32_t rec[kDeferPer], rank[kDeferPer / 2];
+#pragma unroll
+    for (int u0 = 0; u0 < kDeferPer; u0 += 8) {
+      u32x2 p[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const uint64_t i = c0 + (uint64_t)(u0 + v) * kDeferBlock + threadIdx.x;
+        p[v] = i < n ? __builtin_nontemporal_load(pairs + i) : u32x2{0u, 0u};
+      }
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int u = u0 + v;
+        const uint64_t i = c0 + (uint64_t)u * kDeferBlock + threadIdx.x;
+        uint32_t r = 0;
+        if (i < n) {
+          uint32_t vidx, rho;
+          bip_map(p[v].y, A1, b, vidx, rho);
+          const uint32_t pidx = reduce_m(mm3(p[v].x, s1[vidx]), m);
+          rec[u] = (pidx << 5) | (rho - 1);
+          r = atomicAdd(&cnt[pidx / kDeferTile], 1u);
+        }
+        if (u & 1) rank[u >> 1] |= r << 16;
+        else rank[u >> 1] = r;
+      }
+    }
+    __syncthreads();
+    block_exclusive_scan(cnt, start, tiles, wsum);
+    // one run segment per (chunk, tile); cnt[t] becomes the segment's run offset
+    for (uint32_t t = threadIdx.x; t < tiles; t += kDeferBlock) {
+      const uint32_t c = cnt[t];
+      if (c) {
+        const unsigned long long at = atomicAdd(fill + t, (unsigned long long)c);
+        cnt[t] = at < cap ? (uint32_t)at : cap;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kDeferPer; ++u) {
+      const uint64_t i = c0 + (uint64_t)u * kDeferBlock + threadIdx.x;
+      if (i < n) sorted[start[(rec[u] >> 5) / kDeferTile] + ((rank[u >> 1] >> (16 * (u & 1))) & 0xFFFFu)] = rec[u];
+    }
+    __syncthreads();
+    const uint32_t total = n - c0 < kDeferChunk ? (uint32_t)(n - c0) : kDeferChunk;
+    bool direct = false;
+    for (uint32_t j = threadIdx.x; j < total; j += kDeferBlock) {
+      const uint32_t r = sorted[j];
+      const uint32_t t = (r >> 5) / kDeferTile;
+      const uint32_t pos = cnt[t] + (j - start[t]);
+      if (pos < cap) {
+        recs[(uint64_t)t * cap + pos] = r;
+      } else {
+        apply_record<FAST>(r, dr, mstride, seen, wstride);
+        direct = true;
+      }
+    }
+    if (FAST && direct) fill[tiles] = 1ull;
+    __syncthreads();
+  }
+}
+
+// One workgroup per tile; LDS: L planes of kDeferWords bit words.
+template <bool FAST>
+__global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restrict__ dr, uint64_t mstride,
+                                                               uint32_t* __restrict__ seen, uint64_t wstride,
+                                                               uint8_t* __restrict__ reg, uint8_t* __restrict__ reg4,
+                                                               uint64_t m, uint32_t L, uint32_t thr,
+                                                               unsigned long long* __restrict__ hist,
+                                                               const uint32_t* __restrict__ recs,
+                                                               unsigned long long* __restrict__ fill, uint32_t cap,
+                                                               uint32_t tiles) {
+  extern __shared__ uint32_t pm[];
+  __shared__ uint32_t lh[kDeferBlock / 64][kBins];
+  const uint32_t tile = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint32_t i = threadIdx.x; i < L * kDeferWords; i += kDeferBlock) pm[i] = 0;
+  if (lane < kBins) lh[wave][lane] = 0;
+  const unsigned long long f = fill[tile];
+  const uint32_t n = f < cap ? (uint32_t)f : cap;
+  const bool use_seen = FAST && fill[tiles] != 0;
+  __syncthreads();
+  if (threadIdx.x == 0) fill[tile] = 0;  // every thread has read it
+  const uint32_t* r = recs + (uint64_t)tile * cap;
+  for (uint32_t j = threadIdx.x; j < n; j += kDeferBlock) {
+    const uint32_t rec = r[j];
+    const uint32_t p = (rec >> 5) & (kDeferTile - 1);
+    atomicOr(&pm[(rec & 31u) * kDeferWords + (p >> 5)], 1u << (p & 31));
+  }
+  __syncthreads();
+  const uint64_t base = (uint64_t)tile * kDeferTile + (uint64_t)threadIdx.x * 32;
+  if (base < mstride) {
+    uint32_t R[8];
+    advance_group32<FAST>(dr, mstride, seen, wstride, reg, reg4, base, L, swar_gt_bias(thr), pm + threadIdx.x,
+                          kDeferWords, use_seen, R);
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+      if (base + j < m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBins) {
+    uint32_t c = 0;
+    for (int w = 0; w < kDeferBlock / 64; ++w) c += lh[w][threadIdx.x];
+    if (c) atomicAdd(hist + threadIdx.x, (unsigned long long)c);
+  }
+}
+
+// Apply the pending records of every tile to the pool (before a state export
+// or a switch to direct scans): one workgroup per tile.
+template <bool FAST>
+__global__ __launch_bounds__(256) void k_defer_flush(const uint32_t* __restrict__ recs,
+                                                     unsigned long long* __restrict__ fill, uint32_t cap,
+                                                     uint32_t tiles, uint8_t* __restrict__ dr, uint64_t mstride,
+                                                     uint32_t* __restrict__ seen, uint64_t wstride) {
+  const uint32_t tile = blockIdx.x;
+  const unsigned long long f = fill[tile];
+  const uint32_t n = f < cap ? (uint32_t)f : cap;
+  for (uint32_t j = threadIdx.x; j < n; j += 256) apply_record<FAST>(recs[(uint64_t)tile * cap + j], dr, mstride, seen, wstride);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    fill[tile] = 0;
+    if (FAST && n) fill[tiles] = 1ull;
+  }
+}
+
+// Clear the direct-update flag after the advance (all tiles have read it), or
+// set it when bsLBP1 planes may hold bits the records do not know of.
+__global__ void k_defer_flag(unsigned long long* __restrict__ fill, uint32_t tiles, unsigned long long v) {
+  if (threadIdx.x == 0) fill[tiles] = v;
+}
+
 // ------------------------------------------------------------- estimate
 // One wave per host: each lane hashes g/64 virtual indices (getPhyIdx,
 // Alg. 3), gathers their registers (Alg. 5) and accumulates the exact
@@ -495,61 +718,80 @@ __global__ __launch_bounds__(256) void k_estimate_final(uint32_t nh, uint32_t g,
 
 // ------------------------------------------------ estimate, XCD-binned
 // The partitioned estimate hashes every (host, i) on all 8 XCDs.  Binned
-// instead: pass 1 hashes each (host, i) once and compacts its pidx into the
-// slot run of (range x, host) with wave ballots; pass 2 runs range x on the
-// workgroups of XCD x and gathers from the L2-resident nibble registers.
-// Entries beyond a run's capacity are gathered directly in pass 1 and kept as
-// a per-host overflow sum, so every (host, i) is counted exactly once.
+// instead: pass 1 hashes each (host, i) once and appends its pidx to the run
+// of (host, range x), the slot taken from a per-wave LDS counter; pass 2 runs
+// range x on the workgroups of XCD x and gathers from the L2-resident nibble
+// registers.  Entries beyond a run's capacity are gathered directly in pass 1
+// and kept as a per-host overflow sum, so every (host, i) is counted exactly
+// once.  Runs are written and read with non-temporal accesses so that they do
+// not push the nibble registers out of L2.
+// GUARD: g is not a multiple of 64 * kBinRows.  POW2: m = 2^(32 - mshift), so
+// that H(x, m, A) is a shift of the hash instead of a high multiply.
+constexpr int kBinRows = 4;  // hash rows per wave in flight in pass 1
 
+template <bool GUARD, bool POW2>
 __global__ __launch_bounds__(kEstBlock) void k_est_bin(const uint32_t* __restrict__ hosts, uint32_t nh,
                                                        const uint32_t* __restrict__ s1g, uint32_t g, uint32_t m,
-                                                       const uint8_t* __restrict__ reg, uint32_t cap, uint32_t hc,
-                                                       uint32_t* __restrict__ slots, uint32_t* __restrict__ cnt,
-                                                       unsigned long long* __restrict__ ovf_u,
+                                                       uint32_t mshift, const uint8_t* __restrict__ reg, uint32_t cap,
+                                                       uint32_t hc, uint32_t* __restrict__ slots,
+                                                       uint32_t* __restrict__ cnt, unsigned long long* __restrict__ ovf_u,
                                                        uint32_t* __restrict__ ovf_v) {
   extern __shared__ uint32_t s1_lds[];
+  __shared__ uint32_t run_len[kEstWaves][8];
   for (uint32_t i = threadIdx.x; i < g; i += kEstBlock) s1_lds[i] = s1g[i];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes < this one
+  uint32_t* len = run_len[wave];
   for (uint32_t h = blockIdx.x * kEstWaves + wave; h < nh; h += gridDim.x * kEstWaves) {
     const uint32_t kmix = mm3_key(hosts[h]);
-    uint32_t pos[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint32_t hbase = h * 8u * cap;
+    if (lane < 8) len[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     uint64_t oU = 0;
     uint32_t oV = 0;
-    for (uint32_t i0 = 0; i0 < g; i0 += 64) {
-      const uint32_t i = i0 + lane;
-      const bool valid = i < g;
-      const uint32_t hh = valid ? mm3_seeded(kmix, s1_lds[i]) : 0u;
-      const uint32_t x = hh >> 29, p = reduce_m(hh, m);
-      uint32_t slot = 0;
+    for (uint32_t i0 = lane; i0 < g; i0 += 64 * kBinRows) {
+      uint32_t p[kBinRows], x[kBinRows], slot[kBinRows];
 #pragma unroll
-      for (uint32_t xx = 0; xx < 8; ++xx) {
-        const uint64_t mask = __ballot(valid && x == xx);
-        if (valid && x == xx) slot = pos[xx] + (uint32_t)__popcll(mask & below);
-        pos[xx] += (uint32_t)__popcll(mask);
+      for (int u = 0; u < kBinRows; ++u) {
+        const uint32_t i = i0 + 64u * u;
+        const uint32_t hh = !GUARD || i < g ? mm3_seeded(kmix, s1_lds[i]) : 0u;
+        x[u] = hh >> 29;
+        p[u] = POW2 ? hh >> mshift : reduce_m(hh, m);
       }
-      if (valid) {
-        if (slot < cap) {
-          slots[((uint64_t)x * hc + h) * cap + slot] = p;
-        } else {
-          const uint32_t r = reg[p];
+#pragma unroll
+      for (int u = 0; u < kBinRows; ++u) slot[u] = !GUARD || i0 + 64u * u < g ? atomicAdd(&len[x[u]], 1u) : ~0u;
+#pragma unroll
+      for (int u = 0; u < kBinRows; ++u) {
+        if (slot[u] < cap) {
+          // run (h, x) starts at (8 h + x) cap; byte offsets < 4 * 8 * hc * cap <= 2^29
+          const uint32_t off = (hbase + __umul24(x[u], cap) + slot[u]) * 4u;
+          __builtin_nontemporal_store(p[u], reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(slots) + off));
+        } else if (slot[u] != ~0u) {
+          const uint32_t r = reg[p[u]];
           oU += 1ull << (32 - r);
           oV += r == 0;
         }
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 8) {
+      const uint32_t n = len[lane];
+      cnt[(uint64_t)lane * hc + h] = n < cap ? n : cap;
+    }
+    __builtin_amdgcn_wave_barrier();
     oU = wave_sum_u64(oU);
     oV = (uint32_t)wave_sum_u64(oV);
-#pragma unroll
-    for (uint32_t xx = 0; xx < 8; ++xx)
-      if (lane == (int)xx) cnt[(uint64_t)xx * hc + h] = pos[xx] < cap ? pos[xx] : cap;
     if (lane == 0) {
       ovf_u[h] = oU;
       ovf_v[h] = oV;
     }
   }
 }
+
+// Pass 2: a wave takes four hosts, sixteen lanes each.
+constexpr int kGatherRows = 4;
 
 __global__ __launch_bounds__(kEstBlock) void k_est_gather(uint32_t nh, const uint8_t* __restrict__ reg,
                                                           const uint8_t* __restrict__ reg4, uint32_t cap, uint32_t hc,
@@ -560,27 +802,37 @@ __global__ __launch_bounds__(kEstBlock) void k_est_gather(uint32_t nh, const uin
   const uint32_t x = blockIdx.x & 7u;  // workgroups are dispatched round-robin over the 8 XCDs
   const uint32_t tiles = gridDim.x >> 3;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (uint32_t h = (blockIdx.x >> 3) * kEstWaves + wave; h < nh; h += tiles * kEstWaves) {
-    const uint32_t n = cnt[(uint64_t)x * hc + h];
-    const uint32_t* run = slots + ((uint64_t)x * hc + h) * cap;
+  const uint32_t q = (uint32_t)lane >> 4, ql = (uint32_t)lane & 15u;
+  for (uint32_t h0 = ((blockIdx.x >> 3) * kEstWaves + wave) * 4; h0 < nh; h0 += tiles * kEstWaves * 4) {
+    const uint32_t h = h0 + q;
+    const uint32_t n = h < nh ? cnt[(uint64_t)x * hc + h] : 0u;
+    const uint32_t* run = slots + ((uint64_t)h * 8 + x) * cap;
     uint64_t U = 0;
     uint32_t V = 0;
-    for (uint32_t j0 = lane; j0 < n; j0 += 128) {
-      uint32_t p[2];
+    for (uint32_t j0 = ql; j0 < n; j0 += 16 * kGatherRows) {
+      uint32_t p[kGatherRows], nb[kGatherRows];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) p[u] = j0 + 64u * u < n ? run[j0 + 64u * u] : 0u;
+      for (int u = 0; u < kGatherRows; ++u)
+        p[u] = j0 + 16u * u < n ? __builtin_nontemporal_load(run + j0 + 16u * u) : 0u;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        if (j0 + 64u * u >= n) continue;
-        const uint32_t nib = (reg4[p[u] >> 1] >> ((p[u] & 1u) << 2)) & 15u;
-        const uint32_t r = nib < 15u ? nib : (uint32_t)reg[p[u]];
-        U += 1ull << (32 - r);
-        V += r == 0;
+      for (int u = 0; u < kGatherRows; ++u) nb[u] = j0 + 16u * u < n ? (uint32_t)reg4[p[u] >> 1] : 0u;
+#pragma unroll
+      for (int u = 0; u < kGatherRows; ++u) {
+        if (j0 + 16u * u < n) {
+          const uint32_t nib = (nb[u] >> ((p[u] & 1u) << 2)) & 15u;
+          const uint32_t r = nib < 15u ? nib : (uint32_t)reg[p[u]];
+          U += 1ull << (32 - r);
+          V += r == 0;
+        }
       }
     }
-    U = wave_sum_u64(U);
-    V = (uint32_t)wave_sum_u64(V);
-    if (lane == 0) {
+    // sum over the sixteen lanes of each host
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+      U += __shfl_xor(U, d, 16);
+      V += __shfl_xor(V, d, 16);
+    }
+    if (ql == 0 && h < nh) {
       part_u[(uint64_t)x * kPartChunk + h] = U;
       part_v[(uint64_t)x * kPartChunk + h] = V;
     }
@@ -628,6 +880,21 @@ int init_state(vbdr_sketch* sk, hipStream_t st) {
   }
   hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(64), 0, st, sk->hist, (unsigned long long)sk->m);
   VBDR_LAUNCHED("k_hist_reset");
+  if (sk->def_fill) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(sk->def_fill),
+                       (uint64_t)(sk->def_tiles + 1) * 2, 0u);
+    VBDR_LAUNCHED("k_fill_u32(def_fill)");
+  }
+  return VBDR_OK;
+}
+
+// Apply pending deferred records to the pool (stream-ordered).
+int defer_flush(vbdr_sketch* sk, hipStream_t st) {
+  if (!sk->def_rec) return VBDR_OK;
+  auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_defer_flush<true> : k_defer_flush<false>;
+  hipLaunchKernelGGL(kern, dim3(sk->def_tiles), dim3(256), 0, st, sk->def_rec, sk->def_fill, sk->def_cap,
+                     sk->def_tiles, sk->dr, sk->mstride, sk->seen, sk->wstride);
+  VBDR_LAUNCHED("k_defer_flush");
   return VBDR_OK;
 }
 
@@ -671,7 +938,15 @@ extern "C" {
 
 const char* vbdr_last_error(void) { return g_err.c_str(); }
 
-int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out) {
+}  // extern "C"
+
+namespace {
+
+// Deferred scans need the LDS of k_scan_defer: two words per tile plus the
+// sorted chunk (s1 goes to LDS only if it fits beside them).
+size_t defer_scan_lds(uint32_t tiles) { return (size_t)(2 * tiles + kDeferChunk) * 4; }
+
+int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, bool lean, vbdr_sketch** out) {
   if (!out) return vbdr_fail(VBDR_EINVAL, "out is NULL");
   *out = nullptr;
   if (g < 2 || g > 65536u || (g & (g - 1))) return vbdr_fail(VBDR_EINVAL, "g=%u must be a power of two in [2, 65536]", g);
@@ -688,7 +963,12 @@ int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_
       rc = vbdr_fail(VBDR_EHIP, "hipDeviceGetAttribute failed");
       break;
     }
-    sk->m = m, sk->g = g, sk->k = k, sk->layout = layout;
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, sk->device) != hipSuccess) {
+      rc = vbdr_fail(VBDR_EHIP, "hipDeviceGetAttribute failed");
+      break;
+    }
+    sk->m = m, sk->g = g, sk->k = k, sk->layout = layout, sk->lean = lean;
     sk->tune = default_tuning(layout);
     while ((1u << sk->b) < g) sk->b++;
     sk->L = 33 - sk->b;
@@ -703,10 +983,20 @@ int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_
     sk->parts = (m >= kPartMinM && xcds >= 8) ? 8 : (m >= kPartMinM && xcds >= 4) ? 4 : 1;
     const uint64_t part_bytes = sk->parts > 1 ? (uint64_t)sk->parts * kPartChunk * (8 + 4) : 0;
     // the binned scan needs 8 XCDs and pidx < 2^27 to pack its records
-    const uint64_t bin_bytes = (sk->parts == 8 && m <= kBinMaxM) ? 8ull * kBinCap * 4 : 0;
+    const uint64_t bin_bytes = (!lean && sk->parts == 8 && m <= kBinMaxM) ? 8ull * kBinCap * 4 : 0;
+    // deferred scan records: kDeferSlots per BDR, for 2^22 <= m and 2^26 tile-rounded BDRs at most
+    uint64_t def_bytes = 0;
+    if (!lean && m >= kPartMinM && sk->mstride <= (1ull << 26)) {
+      const uint32_t tiles = (uint32_t)((sk->mstride + kDeferTile - 1) / kDeferTile);
+      if (defer_scan_lds(tiles) + 1024 <= (size_t)lds_max && (size_t)(33 - 1) * kDeferWords * 4 + 4096 <= (size_t)lds_max) {
+        sk->def_tiles = tiles;
+        sk->def_cap = kDeferSlots * kDeferTile;
+        def_bytes = (uint64_t)tiles * sk->def_cap * 4 + (uint64_t)(tiles + 1) * 8;
+      }
+    }
     // binned estimate: runs of g/8 + g/16 + 32 slots per (range, host), <= 512 MiB of runs
     uint64_t est_bytes = 0;
-    if (sk->parts == 8 && g >= 64 && g <= kStageMaxG) {
+    if (!lean && sk->parts == 8 && g >= 64 && g <= kStageMaxG) {
       sk->est_cap = g / 8 + g / 16 + 32;
       uint64_t hc = (512ull << 20) / (8ull * sk->est_cap * 4);
       hc = hc < kPartChunk ? hc : kPartChunk;
@@ -727,14 +1017,17 @@ int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_
         (est_bytes && hipMalloc(&sk->est_slots, 8ull * sk->est_hc * sk->est_cap * 4) != hipSuccess) ||
         (est_bytes && hipMalloc(&sk->est_cnt, 8ull * sk->est_hc * 4) != hipSuccess) ||
         (est_bytes && hipMalloc(&sk->ovf_u, (uint64_t)sk->est_hc * 8) != hipSuccess) ||
-        (est_bytes && hipMalloc(&sk->ovf_v, (uint64_t)sk->est_hc * 4) != hipSuccess)) {
+        (est_bytes && hipMalloc(&sk->ovf_v, (uint64_t)sk->est_hc * 4) != hipSuccess) ||
+        (def_bytes && hipMalloc(&sk->def_rec, (uint64_t)sk->def_tiles * sk->def_cap * 4) != hipSuccess) ||
+        (def_bytes && hipMalloc(&sk->def_fill, (uint64_t)(sk->def_tiles + 1) * 8) != hipSuccess)) {
       (void)hipGetLastError();
       rc = vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed",
                 (unsigned long long)(dr_bytes + seen_bytes + sk->mstride * 3 / 2 + part_bytes));
       break;
     }
     sk->bytes = dr_bytes + seen_bytes + sk->mstride * 3 / 2 + 64 * sizeof(unsigned long long) + (uint64_t)g * 4 +
-                part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + bin_bytes + est_bytes;
+                part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + bin_bytes + est_bytes +
+                def_bytes;
     hipStream_t st = nullptr;
     if ((rc = init_state(sk, st)) != VBDR_OK) break;
     hipLaunchKernelGGL(k_seeds, dim3((g + 255) / 256), dim3(256), 0, st, sk->s1, g, sk->A0);
@@ -749,6 +1042,18 @@ int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_
   }
   *out = sk;
   return VBDR_OK;
+}
+
+}  // namespace
+
+int vbdr_sketch_create_lean(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out) {
+  return create_sketch(m, g, k, hash_seed, layout, true, out);
+}
+
+extern "C" {
+
+int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out) {
+  return create_sketch(m, g, k, hash_seed, layout, false, out);
 }
 
 int vbdr_sketch_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, vbdr_sketch** out) {
@@ -777,6 +1082,8 @@ void vbdr_sketch_destroy(vbdr_sketch* sk) {
   if (sk->est_cnt) (void)hipFree(sk->est_cnt);
   if (sk->ovf_u) (void)hipFree(sk->ovf_u);
   if (sk->ovf_v) (void)hipFree(sk->ovf_v);
+  if (sk->def_rec) (void)hipFree(sk->def_rec);
+  if (sk->def_fill) (void)hipFree(sk->def_fill);
   if (prev >= 0 && prev != sk->device) (void)hipSetDevice(prev);
   delete sk;
 }
@@ -790,6 +1097,8 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
     return vbdr_fail(VBDR_EINVAL, "est_parts must be 0, 4 or 8");
   if (tuning->scan_blocks_per_cu > 64 || tuning->est_blocks_per_cu > 64)
     return vbdr_fail(VBDR_EINVAL, "blocks per CU must be at most 64");
+  if (tuning->scan_defer < 0 || tuning->scan_defer > 2) return vbdr_fail(VBDR_EINVAL, "scan_defer must be 0, 1 or 2");
+  const int old_defer = sk->tune.scan_defer;
   sk->tune = default_tuning(sk->layout);
   if (tuning->scan_test_first) sk->tune.scan_test_first = tuning->scan_test_first;
   if (tuning->scan_blocks_per_cu) sk->tune.scan_blocks_per_cu = tuning->scan_blocks_per_cu;
@@ -797,6 +1106,18 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
   if (tuning->scan_binned) sk->tune.scan_binned = tuning->scan_binned;
   if (tuning->est_binned) sk->tune.est_binned = tuning->est_binned;
   if (tuning->est_parts) sk->tune.est_parts = tuning->est_parts;
+  if (tuning->est_bin_hosts) sk->tune.est_bin_hosts = tuning->est_bin_hosts;
+  if (tuning->est_bin_cap) sk->tune.est_bin_cap = tuning->est_bin_cap;
+  if (tuning->scan_defer) sk->tune.scan_defer = tuning->scan_defer;
+  if (sk->def_rec && sk->tune.scan_defer != old_defer) {
+    // pending records go to the pool; the bsLBP1 planes may now hold bits
+    if (int rc = vbdr_check_device(sk)) return rc;
+    VBDR_HIP(hipDeviceSynchronize());
+    if (int rc = defer_flush(sk, nullptr)) return rc;
+    hipLaunchKernelGGL(k_defer_flag, dim3(1), dim3(64), 0, nullptr, sk->def_fill, sk->def_tiles, 1ull);
+    VBDR_LAUNCHED("k_defer_flag");
+    VBDR_HIP(hipDeviceSynchronize());
+  }
   return VBDR_OK;
 }
 
@@ -811,6 +1132,8 @@ int vbdr_sketch_info(const vbdr_sketch* sk, vbdr_info* out) {
   out->m = sk->m, out->g = sk->g, out->b = sk->b, out->L = sk->L, out->k = sk->k;
   out->layout = sk->layout, out->A0 = sk->A0, out->A1 = sk->A1, out->t = sk->t;
   out->state_bytes = sk->bytes;
+  out->est_parts = sk->parts;
+  out->scan_deferred = sk->def_rec && sk->tune.scan_defer == 1;
   return VBDR_OK;
 }
 
@@ -829,6 +1152,19 @@ int vbdr_scan_slice(vbdr_sketch* sk, const uint32_t* pairs_dev, uint64_t n, void
   const u32x2* p = reinterpret_cast<const u32x2*>(pairs_dev);
   const uint32_t m32 = (uint32_t)sk->m;
   const bool test = sk->tune.scan_test_first == 1;
+  if (sk->def_rec && sk->tune.scan_defer == 1) {
+    const size_t base_lds = defer_scan_lds(sk->def_tiles);
+    int lds_max = 0;
+    VBDR_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, sk->device));
+    const int stage_s1 = base_lds + (size_t)sk->g * 4 + 1024 <= (size_t)lds_max;
+    const uint32_t dgrid = grid_cap(sk, (n + kDeferChunk - 1) / kDeferChunk, 1);
+    auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_scan_defer<true> : k_scan_defer<false>;
+    hipLaunchKernelGGL(kern, dim3(dgrid), dim3(kDeferBlock), base_lds + (stage_s1 ? (size_t)sk->g * 4 : 0), st, p, n,
+                       sk->s1, sk->g, stage_s1, sk->b, sk->A1, m32, sk->def_tiles, sk->def_cap, sk->def_rec,
+                       sk->def_fill, sk->dr, sk->mstride, sk->seen, sk->wstride);
+    VBDR_LAUNCHED("k_scan_defer");
+    return VBDR_OK;
+  }
   if (sk->bins && sk->tune.scan_binned == 1) {
     decltype(&k_scan_bin<true, true, true>) bin;
     decltype(&k_scan_apply<true, true>) apply;
@@ -875,6 +1211,17 @@ int vbdr_advance_slice(vbdr_sketch* sk, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(64), 0, st, sk->hist, 0ull);
   VBDR_LAUNCHED("k_hist_reset");
+  if (sk->def_rec && sk->tune.scan_defer == 1) {
+    auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_advance_defer<true> : k_advance_defer<false>;
+    hipLaunchKernelGGL(kern, dim3(sk->def_tiles), dim3(kDeferBlock), (size_t)sk->L * kDeferWords * 4, st, sk->dr,
+                       sk->mstride, sk->seen, sk->wstride, sk->reg, sk->reg4, sk->m, sk->L, sk->k - 1, sk->hist,
+                       sk->def_rec, sk->def_fill, sk->def_cap, sk->def_tiles);
+    VBDR_LAUNCHED("k_advance_defer");
+    hipLaunchKernelGGL(k_defer_flag, dim3(1), dim3(64), 0, st, sk->def_fill, sk->def_tiles, 0ull);
+    VBDR_LAUNCHED("k_defer_flag");
+    sk->t++;
+    return VBDR_OK;
+  }
   const uint32_t grid = (uint32_t)(sk->mstride / (kAdvBlock * kAdvBpt));
   auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_advance<true> : k_advance<false>;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kAdvBlock), 0, st, sk->dr, sk->mstride, sk->seen, sk->wstride, sk->reg,
@@ -896,14 +1243,21 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
   const bool extra = raw_es_dev || hist_dev;
   const size_t lds = stage ? (size_t)sk->g * 4 : 0;
   if (sk->est_slots && sk->tune.est_binned == 1 && !extra) {
-    const uint32_t hc = sk->est_hc, cap = sk->est_cap;
-    for (uint64_t c = 0; c < n_hosts; c += hc) {
-      const uint32_t nh = (uint32_t)(n_hosts - c < hc ? n_hosts - c : hc);
+    const uint32_t hc = sk->est_hc;
+    const uint32_t cap = sk->tune.est_bin_cap && sk->tune.est_bin_cap < sk->est_cap ? sk->tune.est_bin_cap : sk->est_cap;
+    const uint32_t step = sk->tune.est_bin_hosts && sk->tune.est_bin_hosts < hc ? sk->tune.est_bin_hosts : hc;
+    for (uint64_t c = 0; c < n_hosts; c += step) {
+      const uint32_t nh = (uint32_t)(n_hosts - c < step ? n_hosts - c : step);
       const uint32_t bgrid = grid_cap(sk, (nh + kEstWaves - 1) / kEstWaves, sk->tune.est_blocks_per_cu);
-      hipLaunchKernelGGL(k_est_bin, dim3(bgrid), dim3(kEstBlock), (size_t)sk->g * 4, st, hosts_dev + c, nh, sk->s1,
-                         sk->g, (uint32_t)sk->m, sk->reg, cap, hc, sk->est_slots, sk->est_cnt, sk->ovf_u, sk->ovf_v);
+      const bool guard = sk->g % (64u * kBinRows) != 0, pow2 = (sk->m & (sk->m - 1)) == 0;
+      uint32_t mshift = 32;
+      while (pow2 && (1ull << (32 - mshift)) < sk->m) --mshift;
+      auto bin = guard ? (pow2 ? k_est_bin<true, true> : k_est_bin<true, false>)
+                       : (pow2 ? k_est_bin<false, true> : k_est_bin<false, false>);
+      hipLaunchKernelGGL(bin, dim3(bgrid), dim3(kEstBlock), (size_t)sk->g * 4, st, hosts_dev + c, nh, sk->s1, sk->g,
+                         (uint32_t)sk->m, mshift, sk->reg, cap, hc, sk->est_slots, sk->est_cnt, sk->ovf_u, sk->ovf_v);
       VBDR_LAUNCHED("k_est_bin");
-      const uint64_t want = (nh + kEstWaves - 1) / kEstWaves;
+      const uint64_t want = (nh + 4 * kEstWaves - 1) / (4 * kEstWaves);
       const uint64_t capb = (uint64_t)sk->n_cu * sk->tune.est_blocks_per_cu / 8;
       const uint32_t tiles = (uint32_t)(want < capb ? want : (capb ? capb : 1));
       hipLaunchKernelGGL(k_est_gather, dim3(tiles * 8), dim3(kEstBlock), 0, st, nh, sk->reg, sk->reg4, cap, hc,
@@ -952,6 +1306,7 @@ int vbdr_export_state(vbdr_sketch* sk, uint8_t* dr_host, uint32_t* bs_host, uint
   if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
   if (int rc = vbdr_check_device(sk)) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (int rc = defer_flush(sk, st)) return rc;  // the open slice's deferred records join the state
   VBDR_HIP(hipStreamSynchronize(st));
   const uint64_t m = sk->m, L = sk->L;
   if (dr_host) {
@@ -1018,6 +1373,13 @@ int vbdr_import_state(vbdr_sketch* sk, const uint8_t* dr_host, const uint32_t* b
     VBDR_HIP(hipMemcpy(sk->reg, r.data(), sk->mstride, hipMemcpyHostToDevice));
   }
   VBDR_HIP(hipMemcpy(sk->hist, hist_host, kBins * sizeof(uint64_t), hipMemcpyHostToDevice));
+  if (sk->def_fill) {  // drop pending records; the imported bsLBP1 bits must be read by the advance
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, nullptr, reinterpret_cast<uint32_t*>(sk->def_fill),
+                       (uint64_t)(sk->def_tiles + 1) * 2, 0u);
+    VBDR_LAUNCHED("k_fill_u32(def_fill)");
+    hipLaunchKernelGGL(k_defer_flag, dim3(1), dim3(64), 0, nullptr, sk->def_fill, sk->def_tiles, 1ull);
+    VBDR_LAUNCHED("k_defer_flag");
+  }
   hipLaunchKernelGGL(k_pack_reg4, dim3(grid_cap(sk, (sk->mstride / 2 + 255) / 256, 8)), dim3(256), 0, nullptr, sk->reg,
                      sk->reg4, sk->mstride / 2);
   VBDR_LAUNCHED("k_pack_reg4");

@@ -231,7 +231,7 @@ int vbdr_batch_create(uint32_t n_sketches, const vbdr_batch_params* params, vbdr
     for (uint32_t i = 0; i < n_sketches; ++i) {
       vbdr_sketch* s = nullptr;
       const vbdr_batch_params& p = params[i];
-      if ((rc = vbdr_sketch_create_layout(p.m, p.g, p.k, p.hash_seed, p.layout, &s)) != VBDR_OK) break;
+      if ((rc = vbdr_sketch_create_lean(p.m, p.g, p.k, p.hash_seed, p.layout, &s)) != VBDR_OK) break;
       bt->sk.push_back(s);
     }
     if (rc != VBDR_OK) break;

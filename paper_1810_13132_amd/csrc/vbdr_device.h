@@ -40,7 +40,7 @@ __device__ __forceinline__ uint32_t mm3_key(uint32_t x) {
 __device__ __forceinline__ uint32_t mm3_seeded(uint32_t kmix, uint32_t seed) {
   uint32_t h = seed ^ kmix;
   h = (h << 13) | (h >> 19);
-  h = (h << 2) + h + 0xe6546b64u;  // h * 5 + c
+  h = h * 5u + 0xe6546b64u;
   h ^= 4u;
   h ^= h >> 16;
   h *= 0x85ebca6bu;
@@ -192,6 +192,70 @@ __device__ __forceinline__ void advance_group(uint8_t* dr, uint64_t mstride, uin
 #pragma unroll
   for (int w = 0; w < 4; ++w) nib |= (uint64_t)swar_pack_nibbles(R[w]) << (16 * w);
   *reinterpret_cast<uint64_t*>(reg4 + base / 2) = nib;
+}
+
+// Advance 32 consecutive BDRs starting at `base` (a multiple of 32) as
+// advance_group does, with the slice's LBP1 bits of those BDRs also given as
+// one word per plane, pm[(i - 1) * pm_stride] bit j <-> BDR base + j (the
+// deferred scan records of the tile, gathered in LDS).  Small layout: a set
+// bit means DR[i] was set to 0 during the slice (Alg. 9), so it is zeroed
+// before the slide.  Fast layout: the bits join bsLBP1 (Alg. 7) and the
+// slice's highest LBP1 is set after the slide (Alg. 6).  use_seen: the
+// bsLBP1 bit-planes in memory may hold bits too (fast layout); they are
+// read and cleared.  R receives the 32 registers, byte j of R[w] = BDR
+// base + 4w + j; they are also stored to reg and reg4.
+template <bool FAST>
+__device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, uint32_t* seen, uint64_t wstride,
+                                                uint8_t* reg, uint8_t* reg4, uint64_t base, uint32_t L,
+                                                uint32_t gt_bias, const uint32_t* pm, uint32_t pm_stride,
+                                                bool use_seen, uint32_t R[8]) {
+  uint32_t M[8];
+#pragma unroll
+  for (int w = 0; w < 8; ++w) M[w] = R[w] = 0;
+  uint32_t folded = 0;
+  const uint8_t* top = dr + (uint64_t)(L - 1) * mstride + base;
+  u32x4 dn0 = *reinterpret_cast<const u32x4*>(top), dn1 = *reinterpret_cast<const u32x4*>(top + 16);
+  uint32_t sn = 0;
+  if (FAST && use_seen) sn = seen[(uint64_t)(L - 1) * wstride + (base >> 5)];
+  for (int i = (int)L; i >= 1; --i) {
+    const u32x4 d0 = dn0, d1 = dn1;
+    const uint32_t s = sn;
+    if (i > 1) {
+      const uint8_t* nx = dr + (uint64_t)(i - 2) * mstride + base;
+      dn0 = *reinterpret_cast<const u32x4*>(nx);
+      dn1 = *reinterpret_cast<const u32x4*>(nx + 16);
+      if (FAST && use_seen) sn = seen[(uint64_t)(i - 2) * wstride + (base >> 5)];
+    }
+    const uint32_t bits = s | pm[(uint32_t)(i - 1) * pm_stride];
+    uint32_t fold = 0;
+    if constexpr (FAST) {
+      fold = bits & ~folded;  // only the slice's highest LBP1 is recorded
+      folded |= bits;
+    }
+    u32x4 nd0, nd1;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      uint32_t x = w < 4 ? d0[w] : d1[w - 4];
+      if constexpr (!FAST) x &= ~swar_nibble_to_bytes((bits >> (4 * w)) & 0xFu);  // SetDR of the slice
+      uint32_t y = swar_sat_inc(x);                                                // SlideDR
+      if constexpr (FAST) y &= ~swar_nibble_to_bytes((fold >> (4 * w)) & 0xFu);   // SetDR
+      const uint32_t act = swar_le_mask(FAST ? y : x, gt_bias);                    // IsActiveDR
+      R[w] |= act & ~M[w] & ((uint32_t)i * 0x01010101u);
+      M[w] |= act;
+      if (w < 4) nd0[w] = y; else nd1[w - 4] = y;
+    }
+    uint8_t* out = dr + (uint64_t)(i - 1) * mstride + base;
+    *reinterpret_cast<u32x4*>(out) = nd0;
+    *reinterpret_cast<u32x4*>(out + 16) = nd1;
+  }
+  if (FAST && use_seen)
+    for (uint32_t i = 0; i < L; ++i) seen[(uint64_t)i * wstride + (base >> 5)] = 0;
+  *reinterpret_cast<u32x4*>(reg + base) = u32x4{R[0], R[1], R[2], R[3]};
+  *reinterpret_cast<u32x4*>(reg + base + 16) = u32x4{R[4], R[5], R[6], R[7]};
+  u32x4 nib;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) nib[q] = swar_pack_nibbles(R[2 * q]) | (swar_pack_nibbles(R[2 * q + 1]) << 16);
+  *reinterpret_cast<u32x4*>(reg4 + base / 2) = nib;
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {

@@ -16,6 +16,8 @@ constexpr uint32_t kLearnChunk = 1u << 15;  // hosts per histogram pass of the l
 constexpr uint64_t kBinMaxM = 1ull << 27;   // binned scan records pack (pidx << 5) | (LBP1 - 1)
 constexpr uint32_t kBinChunk = 1u << 24;    // pairs per binned-scan pass (records stay cache resident)
 constexpr uint32_t kBinCap = kBinChunk / 8 + kBinChunk / 32 + 65536;  // records per bin per pass
+constexpr uint32_t kDeferTile = 1u << 15;   // BDRs per deferred-apply tile (one advance workgroup)
+constexpr uint32_t kDeferSlots = 2;         // record slots per BDR per slice before the direct fallback
 
 struct vbdr_sketch {
   int device;
@@ -44,9 +46,16 @@ struct vbdr_sketch {
   unsigned long long* ovf_u;   // [est_hc] overflow partial sums
   uint32_t* ovf_v;             // [est_hc]
   uint32_t est_cap, est_hc;
+  uint32_t* def_rec;              // [def_tiles][def_cap] deferred scan records (pidx << 5 | LBP1-1)
+  unsigned long long* def_fill;   // [def_tiles + 1] records per tile; the last word flags direct updates
+  uint32_t def_tiles, def_cap;
+  bool lean;                      // no optional workspaces (sketches owned by a batch)
   uint64_t bytes;
   vbdr_tuning tune;
 };
+
+// vbdr_sketch_create_layout without the optional large-pool workspaces.
+int vbdr_sketch_create_lean(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out);
 
 // Records the calling thread's error message and returns code.
 int vbdr_fail(int code, const char* fmt, ...);

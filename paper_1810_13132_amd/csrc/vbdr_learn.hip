@@ -30,7 +30,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct MlpDev {
   uint16_t w1[kHid * kInPad];  // bf16, K zero-padded to 96
-  uint16_t w2[kHid * kHid];    // bf16
+  uint16_t w2p[kHid * kHid];   // bf16, W2 with its columns in layer 2's K order (l2_unit)
   float b1[kHid], b2[kHid], w3[kHid], b3;  // w3 holds bf16-rounded values
   float env_lo[kIn], env_hi[kIn];
   int has_env;
@@ -56,6 +56,17 @@ __device__ __forceinline__ float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
+// GELU of the inference kernel: erf by Abramowitz & Stegun 7.1.26 (absolute
+// error <= 1.5e-7, below one fp32 ulp of the GELU's 1 + erf term), without
+// the branches of erff, so that a lane's 16 activations need few registers.
+__device__ __forceinline__ float gelu_inf(float x) {
+  const float z = fabsf(x) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * z);
+  const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float e = 1.0f - poly * __expf(-z * z);  // erf(|x| / sqrt 2)
+  return 0.5f * x * (1.0f + (x < 0.0f ? -e : e));
+}
+
 // ------------------------------------------------------------ features
 // fp32 features of nh hosts from the histogram pass: [h][67].
 __global__ __launch_bounds__(256) void k_features(uint32_t nh, uint32_t parts, const uint32_t* __restrict__ hws,
@@ -74,197 +85,203 @@ __global__ __launch_bounds__(256) void k_features(uint32_t nh, uint32_t parts, c
 }
 
 // ----------------------------------------------------------- inference
+// A wave estimates a tile of 16 hosts.  Both layers run transposed on the
+// matrix cores, hidden units as rows and hosts as columns, so that the
+// accumulator of layer 1 (lane l: units 16 nt + 4 (l/16) + i of host l%16) is
+// already the B operand of layer 2 once the K order of layer 2 is permuted to
+// match (W2's columns are stored permuted, w2p).  Layer 2's outputs meet w3 in
+// the same lanes; three lane exchanges give the tile's 16 sums.  The plain
+// estimate is computed (in parallel over the tile's hosts) only for hosts that
+// fall back.
 constexpr int kInfBlock = 256;
 constexpr int kInfWaves = kInfBlock / 64;
+constexpr int kHistStride = 36;  // words per histogram row (16-byte aligned rows)
+
+// Unit of layer 1 held in K slot (ks, q, i) of layer 2's operands.
+__host__ __device__ inline int l2_unit(int ks, int q, int i) { return 16 * (2 * ks + (i >> 2)) + 4 * q + (i & 3); }
+
+// bf16x8 of eight fp32 values.
+__device__ __forceinline__ bf16x8 pack8(const float* v) {
+  bf16x8 r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = (short)f2bf(v[i]);
+  return r;
+}
 
 // DIRECT: each wave gathers its 16 hosts' registers itself (pools whose
-// registers are cache resident), building each histogram in LDS; otherwise
-// the histograms come from a histogram pass (hws, summed over parts).
+// registers are cache resident) into an LDS histogram per host; otherwise
+// the histograms come from a histogram pass (hws, summed over parts).  Five
+// waves per SIMD (at most 102 registers) keep enough gathers in flight.
 template <bool DIRECT>
-__global__ __launch_bounds__(kInfBlock) void k_learned(uint32_t nh, uint32_t parts, const uint32_t* __restrict__ hws,
+__global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_learned(uint32_t nh, uint32_t parts, const uint32_t* __restrict__ hws,
                                                        const uint32_t* __restrict__ hosts,
                                                        const uint32_t* __restrict__ s1g, const uint8_t* __restrict__ reg,
                                                        const unsigned long long* __restrict__ hist, uint32_t g,
                                                        uint32_t m, const MlpDev* __restrict__ mlp,
                                                        float* __restrict__ out, uint8_t* __restrict__ used_fallback) {
   extern __shared__ uint32_t s1_lds[];
-  __shared__ uint32_t lh[kInfWaves][4][kBins];  // DIRECT: four histogram copies per wave
   __shared__ __attribute__((aligned(16))) uint16_t sw1[kHid * kInPad];
   __shared__ __attribute__((aligned(16))) uint16_t sw2[kHid * kHid];
-  __shared__ __attribute__((aligned(16))) uint16_t sx[kInfWaves][16 * kInPad];
-  __shared__ __attribute__((aligned(16))) uint16_t sh1[kInfWaves][16 * kHid];
-  __shared__ float spool[kInPad];  // fp32 pool features, columns 33..95
-  __shared__ uint16_t spool_bf[kInPad];
+  __shared__ __attribute__((aligned(16))) uint32_t lh[kInfWaves][16 * kHistStride];
+  __shared__ __attribute__((aligned(16))) uint16_t sconst[kInPad];  // bf16 features 33..95 (pool, ln(g/m), 0)
+  __shared__ float sb1[kHid], sb2[kHid], sw3[kHid], senv_lo[kBins], senv_hi[kBins];
   __shared__ int spool_bad;
-  __shared__ float splain[kInfWaves][16];
-  __shared__ int sflag[kInfWaves][16];
   __shared__ double sem;
   for (int i = threadIdx.x; i < kHid * kInPad / 8; i += kInfBlock)
     reinterpret_cast<uint4*>(sw1)[i] = reinterpret_cast<const uint4*>(mlp->w1)[i];
   for (int i = threadIdx.x; i < kHid * kHid / 8; i += kInfBlock)
-    reinterpret_cast<uint4*>(sw2)[i] = reinterpret_cast<const uint4*>(mlp->w2)[i];
+    reinterpret_cast<uint4*>(sw2)[i] = reinterpret_cast<const uint4*>(mlp->w2p)[i];
+  for (int i = threadIdx.x; i < kInfWaves * 16 * kHistStride; i += kInfBlock) (&lh[0][0])[i] = 0;
+  if (threadIdx.x < kHid) {
+    sb1[threadIdx.x] = mlp->b1[threadIdx.x];
+    sb2[threadIdx.x] = mlp->b2[threadIdx.x];
+    sw3[threadIdx.x] = mlp->w3[threadIdx.x];
+  }
+  if (threadIdx.x < kBins) {
+    senv_lo[threadIdx.x] = mlp->has_env ? mlp->env_lo[threadIdx.x] : -INFINITY;
+    senv_hi[threadIdx.x] = mlp->has_env ? mlp->env_hi[threadIdx.x] : INFINITY;
+  }
   if (threadIdx.x == 0) {
     sem = pool_estimate(hist, (double)m);
     spool_bad = 0;
   }
-  if constexpr (DIRECT) {
+  if constexpr (DIRECT)
     for (uint32_t i = threadIdx.x; i < g; i += kInfBlock) s1_lds[i] = s1g[i];
-    for (int i = threadIdx.x; i < kInfWaves * 4 * kBins; i += kInfBlock) (&lh[0][0][0])[i] = 0;
-  }
+  __syncthreads();
   if (threadIdx.x < kInPad) {
     const int c = threadIdx.x;
     float v = 0.0f;
     if (c >= kBins && c < 2 * kBins) v = (float)((double)hist[c - kBins] / (double)m);
     if (c == 2 * kBins) v = (float)log((double)g / (double)m);
-    spool[c] = v;
-    spool_bf[c] = f2bf(v);
-  }
-  __syncthreads();
-  if (threadIdx.x >= kBins && threadIdx.x < kIn && mlp->has_env) {
-    const float v = spool[threadIdx.x];
-    if (!(v >= mlp->env_lo[threadIdx.x] && v <= mlp->env_hi[threadIdx.x])) atomicOr(&spool_bad, 1);
+    sconst[c] = f2bf(v);
+    if (c >= kBins && c < kIn && mlp->has_env && !(v >= mlp->env_lo[c] && v <= mlp->env_hi[c])) atomicOr(&spool_bad, 1);
   }
   __syncthreads();
   const double Em = sem;
+  const int pool_bad = spool_bad;
+  const float inv_g = 1.0f / (float)g;  // g is a power of two: c * inv_g == c / g exactly
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint16_t* X = sx[wave];
-  uint16_t* H1 = sh1[wave];
+  const int col = lane & 15, q = lane >> 4;
+  uint32_t* H = lh[wave];
   const uint32_t ntiles = (nh + 15) / 16;
   for (uint32_t tile = blockIdx.x * kInfWaves + wave; tile < ntiles; tile += gridDim.x * kInfWaves) {
+    // An offset opaque to the compiler: the weights, biases and envelope are
+    // read from LDS per tile instead of being pinned in ~150 registers across
+    // the loop, which would cut the waves available to hide gather latency.
+    uint32_t woff = 0;
+    asm volatile("" : "+v"(woff));
+    // 1. register histograms of the tile's hosts
     if constexpr (DIRECT) {
-      // 1. per host: gathers -> LDS histogram -> features, plain estimate
       for (int row = 0; row < 16; ++row) {
         const uint32_t h = tile * 16 + row;
-        if (h < nh) {
-          const uint32_t kmix = mm3_key(hosts[h]);
-          uint32_t* my = lh[wave][lane & 3];
-          for (uint32_t i0 = lane; i0 < g; i0 += 64 * 8) {
-            uint32_t r[8];
+        if (h >= nh) break;
+        const uint32_t kmix = mm3_key(hosts[h]);
+        uint32_t* my = H + row * kHistStride;
+        for (uint32_t i0 = lane; i0 < g; i0 += 64 * 4) {
+          uint32_t r[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const uint32_t i = i0 + 64u * u;
-              r[u] = i < g ? (uint32_t)reg[reduce_m(mm3_seeded(kmix, s1_lds[i]), m)] : 255u;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (r[u] != 255u) atomicAdd(&my[r[u]], 1u);
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t i = i0 + 64u * u;
+            r[u] = i < g ? (uint32_t)reg[reduce_m(mm3_seeded(kmix, s1_lds[i]), m)] : 255u;
           }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (r[u] != 255u) atomicAdd(&my[r[u]], 1u);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        uint32_t c = 0;
-        if (lane < kBins) {
-          c = lh[wave][0][lane] + lh[wave][1][lane] + lh[wave][2][lane] + lh[wave][3][lane];
-          lh[wave][0][lane] = lh[wave][1][lane] = lh[wave][2][lane] = lh[wave][3][lane] = 0;
-          const float f = (float)((double)c / (double)g);
-          X[row * kInPad + lane] = f2bf(f);
-        } else if (lane < kInPad - kBins + kBins && lane >= kBins) {
-          X[row * kInPad + lane] = spool_bf[lane];  // columns 33..63
-        }
-        if (lane + 64 < kInPad) X[row * kInPad + lane + 64] = spool_bf[lane + 64];  // columns 64..95
-        const bool bad_bin = lane < kBins && mlp->has_env &&
-                             !((float)((double)c / (double)g) >= mlp->env_lo[lane] &&
-                               (float)((double)c / (double)g) <= mlp->env_hi[lane]);
-        const uint64_t Ub = wave_sum_u64(lane < kBins ? (uint64_t)c << (32 - lane) : 0ull);
-        const uint32_t Vb = (uint32_t)__shfl(c, 0);
-        const int bad = __ballot(bad_bin) != 0ull;
-        if (lane == 0) {
-          const double Es = hll_estimate(Ub, Vb, (double)g);
-          const double n = noise_removed(Es, Em, (double)m, (double)g);
-          splain[wave][row] = (float)(n > 0.0 ? n : 0.0);
-          sflag[wave][row] = bad | spool_bad;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
       }
     } else {
-  // 1. features of 16 hosts: lane = 4 * row + quarter
-      const int row = lane >> 2, q = lane & 3;
-      const uint32_t h = tile * 16 + row;
-      const bool live = h < nh;
-      uint64_t U = 0;
-      uint32_t V = 0;
-      int bad = 0;
-      for (int r = q; r < kBins; r += 4) {
+      for (int e = lane; e < 16 * kBins; e += 64) {
+        const int row = e / kBins, r = e - row * kBins;
+        const uint32_t h = tile * 16 + row;
         uint32_t c = 0;
-        if (live)
+        if (h < nh)
           for (uint32_t x = 0; x < parts; ++x) c += hws[((uint64_t)x * kLearnChunk + h) * kBins + r];
-        const float f = (float)((double)c / (double)g);
-        X[row * kInPad + r] = f2bf(f);
-        U += (uint64_t)c << (32 - r);
-        if (r == 0) V = c;
-        if (mlp->has_env && !(f >= mlp->env_lo[r] && f <= mlp->env_hi[r])) bad = 1;
-      }
-      for (int c = kBins + q; c < kInPad; c += 4) X[row * kInPad + c] = spool_bf[c];
-      U += __shfl_xor(U, 1);
-      U += __shfl_xor(U, 2);
-      V += __shfl_xor(V, 1);
-      V += __shfl_xor(V, 2);
-      bad |= __shfl_xor(bad, 1);
-      bad |= __shfl_xor(bad, 2);
-      if (q == 0) {
-        const double Es = hll_estimate(U, V, (double)g);
-        const double n = noise_removed(Es, Em, (double)m, (double)g);
-        splain[wave][row] = (float)(n > 0.0 ? n : 0.0);
-        sflag[wave][row] = bad | spool_bad;
+        H[row * kHistStride + r] = c;
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    // 2. layer 1: Z1 (16 x 64) = X (16 x 96) W1^T, three K steps of 32
-    const int mr = lane & 15, kq = lane >> 4;
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 3; ++ks) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(X + mr * kInPad + ks * 32 + kq * 8);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(sw1 + (nt * 16 + mr) * kInPad + ks * 32 + kq * 8);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-      }
-      const int col = nt * 16 + mr;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) H1[(kq * 4 + i) * kHid + col] = f2bf(gelu(acc[i] + mlp->b1[col]));
+    // 2. features of host `col`: this lane's bins 8q..8q+7 (and bin 32 for q = 0)
+    uint32_t c8[8];
+    {
+      const uint4 lo = *reinterpret_cast<const uint4*>(H + col * kHistStride + 8 * q);
+      const uint4 hi = *reinterpret_cast<const uint4*>(H + col * kHistStride + 8 * q + 4);
+      c8[0] = lo.x, c8[1] = lo.y, c8[2] = lo.z, c8[3] = lo.w, c8[4] = hi.x, c8[5] = hi.y, c8[6] = hi.z, c8[7] = hi.w;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const uint32_t c32 = q == 0 ? H[col * kHistStride + 32] : 0u;
     __builtin_amdgcn_wave_barrier();
-    // 3. layer 2 and the output unit
-    float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) H[col * kHistStride + 8 * q + i] = 0;  // clean for the next tile
+    if (q == 0) H[col * kHistStride + 32] = 0;
+    float f[8];
+    int bad = 0;
+    uint64_t U = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int r = 8 * q + i;
+      f[i] = (float)c8[i] * inv_g;
+      bad |= !(f[i] >= senv_lo[woff + r] && f[i] <= senv_hi[woff + r]);
+      U += (uint64_t)c8[i] << (32 - r);
+    }
+    const float f32 = (float)c32 * inv_g;
+    if (q == 0) {
+      bad |= !(f32 >= senv_lo[woff + 32] && f32 <= senv_hi[woff + 32]);
+      U += (uint64_t)c32;
+    }
+    const bf16x8 x0 = pack8(f);
+    bf16x8 x1 = *reinterpret_cast<const bf16x8*>(sconst + woff + 32 + 8 * q);
+    if (q == 0) x1[0] = (short)f2bf(f32);
+    const bf16x8 x2 = *reinterpret_cast<const bf16x8*>(sconst + woff + 64 + 8 * q);
+    // 3. layer 1, transposed: Z1^T (64 x 16) = W1 (64 x 96) X^T
+    f32x4 z1[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
+      const uint16_t* wr = sw1 + woff + (nt * 16 + col) * kInPad + 8 * q;
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(H1 + mr * kHid + ks * 32 + kq * 8);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(sw2 + (nt * 16 + mr) * kHid + ks * 32 + kq * 8);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-      }
-      const int col = nt * 16 + mr;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) part[i] += gelu(acc[i] + mlp->b2[col]) * mlp->w3[col];
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(wr), x0, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(wr + 32), x1, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(wr + 64), x2, acc, 0, 0, 0);
+      z1[nt] = acc;
     }
+    // 4. H1 = bf16(gelu(Z1 + b1)) in place as layer 2's B operand
+    bf16x8 hb[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      part[i] += __shfl_xor(part[i], 8);
-      part[i] += __shfl_xor(part[i], 4);
-      part[i] += __shfl_xor(part[i], 2);
-      part[i] += __shfl_xor(part[i], 1);
-    }
-    if (mr == 0) {
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hb[nt >> 1][4 * (nt & 1) + i] = (short)f2bf(gelu_inf(z1[nt][i] + sb1[woff + 16 * nt + 4 * q + i]));
+    // 5. layer 2, transposed, and the output unit
+    float part = 0.f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const uint16_t* wr = sw2 + woff + (nt * 16 + col) * kHid + 8 * q;
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(wr), hb[0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(wr + 32), hb[1], acc, 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = kq * 4 + i;
-        const uint32_t hh = tile * 16 + r;
-        if (hh < nh) {
-          const float y = part[i] + mlp->b3;
-          float est = expf(y) - 1.0f;
-          int fb = sflag[wave][r];
-          if (!isfinite(est)) fb = 1;
-          if (fb) est = splain[wave][r];
-          out[hh] = est > 0.0f ? est : 0.0f;
-          if (used_fallback) used_fallback[hh] = (uint8_t)fb;
-        }
+        const int u = woff + 16 * nt + 4 * q + i;
+        part += gelu_inf(acc[i] + sb2[u]) * sw3[u];
       }
+    }
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);
+    U += __shfl_xor(U, 16);
+    U += __shfl_xor(U, 32);
+    bad |= __shfl_xor(bad, 16);
+    bad |= __shfl_xor(bad, 32);
+    // 6. outputs of the tile, lane col of the first row group
+    const uint32_t h = tile * 16 + col;
+    if (q == 0 && h < nh) {
+      float est = expf(part + mlp->b3) - 1.0f;
+      int fb = bad | pool_bad;
+      if (!isfinite(est)) fb = 1;
+      if (fb) {
+        const double Es = hll_estimate(U, c8[0], (double)g);
+        const double n = noise_removed(Es, Em, (double)m, (double)g);
+        est = (float)(n > 0.0 ? n : 0.0);
+      }
+      out[h] = est > 0.0f ? est : 0.0f;
+      if (used_fallback) used_fallback[h] = (uint8_t)fb;
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -387,7 +404,10 @@ int vbdr_mlp_create(const float* params_host, const float* env_lo, const float* 
   MlpDev* h = reinterpret_cast<MlpDev*>(buf.data());
   for (int j = 0; j < kHid; ++j) {
     for (int k = 0; k < kIn; ++k) h->w1[j * kInPad + k] = f2bf(params_host[kOffW1 + j * kIn + k]);
-    for (int k = 0; k < kHid; ++k) h->w2[j * kHid + k] = f2bf(params_host[kOffW2 + j * kHid + k]);
+    for (int ks = 0; ks < 2; ++ks)
+      for (int q = 0; q < 4; ++q)
+        for (int i = 0; i < 8; ++i)
+          h->w2p[j * kHid + 32 * ks + 8 * q + i] = f2bf(params_host[kOffW2 + j * kHid + l2_unit(ks, q, i)]);
     h->b1[j] = params_host[kOffB1 + j];
     h->b2[j] = params_host[kOffB2 + j];
     h->w3[j] = bf2f(f2bf(params_host[kOffW3 + j]));

@@ -32,13 +32,14 @@ class VbdrError(RuntimeError):
 class Info(C.Structure):
     _fields_ = [("m", C.c_uint64), ("g", C.c_uint32), ("b", C.c_uint32), ("L", C.c_uint32), ("k", C.c_uint32),
                 ("layout", C.c_int32), ("A0", C.c_uint32), ("A1", C.c_uint32), ("t", C.c_uint64),
-                ("state_bytes", C.c_uint64)]
+                ("state_bytes", C.c_uint64), ("est_parts", C.c_int32), ("scan_deferred", C.c_int32)]
 
 
 class Tuning(C.Structure):
     _fields_ = [("scan_test_first", C.c_int32), ("scan_blocks_per_cu", C.c_uint32),
                 ("est_blocks_per_cu", C.c_uint32), ("scan_binned", C.c_int32), ("est_binned", C.c_int32),
-                ("est_parts", C.c_int32)]
+                ("est_parts", C.c_int32), ("est_bin_hosts", C.c_uint32),
+                ("est_bin_cap", C.c_uint32), ("scan_defer", C.c_int32)]
 
 
 class BatchParams(C.Structure):
@@ -173,8 +174,10 @@ class Sketch:
         return out
 
     def set_tuning(self, scan_test_first: int = 0, scan_blocks_per_cu: int = 0, est_blocks_per_cu: int = 0,
-                   scan_binned: int = 0, est_binned: int = 0, est_parts: int = 0):
-        t = Tuning(scan_test_first, scan_blocks_per_cu, est_blocks_per_cu, scan_binned, est_binned, est_parts)
+                   scan_binned: int = 0, est_binned: int = 0, est_parts: int = 0, est_bin_hosts: int = 0,
+                   est_bin_cap: int = 0, scan_defer: int = 0):
+        t = Tuning(scan_test_first, scan_blocks_per_cu, est_blocks_per_cu, scan_binned, est_binned, est_parts,
+                   est_bin_hosts, est_bin_cap, scan_defer)
         _check(lib().vbdr_sketch_set_tuning(self._h, C.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -182,7 +185,8 @@ class Sketch:
         _check(lib().vbdr_sketch_get_tuning(self._h, C.byref(t)))
         return {"scan_test_first": t.scan_test_first, "scan_blocks_per_cu": t.scan_blocks_per_cu,
                 "est_blocks_per_cu": t.est_blocks_per_cu, "scan_binned": t.scan_binned, "est_binned": t.est_binned,
-                "est_parts": t.est_parts}
+                "est_parts": t.est_parts, "est_bin_hosts": t.est_bin_hosts,
+                "est_bin_cap": t.est_bin_cap, "scan_defer": t.scan_defer}
 
     @property
     def t(self) -> int:

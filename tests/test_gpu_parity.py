@@ -196,9 +196,38 @@ def test_parity_large_pool_partitioned_estimate(V, O, layout):
     hd = _dev(V, hosts)
     plain = sk.estimate(hd)
     assert torch.equal(b.estimate(hd), plain)
-    # the binned estimate (each (host, i) hashed once) gives the same bits
-    sk.set_tuning(est_binned=1)
-    assert torch.equal(sk.estimate(hd), plain)
+    # the binned estimate (each (host, i) hashed once) gives the same bits,
+    # in one pass, in ragged passes, and with runs too short for most hosts
+    for tune in ({}, {"est_bin_hosts": 40000}, {"est_bin_cap": 20}, {"est_bin_hosts": 999, "est_bin_cap": 33}):
+        sk.set_tuning(est_binned=1, **tune)
+        assert torch.equal(sk.estimate(hd), plain), tune
+
+
+@pytest.mark.parametrize("layout", ["fast", "small"])
+def test_binned_estimate_pow2_pool_ragged_g(V, O, layout):
+    """A power-of-two pool takes the shift form of H(x, m, A) in the binned
+    estimate; g = 128 fills only half a row of hashes per host.  Both
+    estimate variants against the oracle."""
+    m, g, k, seed = 1 << 22, 128, 2, 21
+    rng = np.random.default_rng(seed)
+    aips = rng.integers(0, 2**32, 3000, dtype=np.uint64).astype(np.uint32)
+    sk = V.Sketch(m, g, k, seed, layout)
+    osk = O.Sketch(m, g, k, seed, LAYOUT_CODE[layout])
+    for t in range(2):
+        n = 1 << 18
+        pairs = np.stack([aips[rng.integers(0, len(aips), n)],
+                          rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
+        sk.scan_slice(_dev(V, pairs.reshape(-1)))
+        osk.scan(pairs)
+        sk.advance_slice()
+        osk.advance()
+    hosts = np.concatenate([aips, rng.integers(0, 2**32, 2001, dtype=np.uint64).astype(np.uint32)])
+    assert_estimates_close(V, O, sk, osk, hosts)
+    hd = _dev(V, hosts)
+    plain = sk.estimate(hd)
+    for tune in ({}, {"est_bin_cap": 10}):
+        sk.set_tuning(est_binned=1, **tune)
+        assert torch.equal(sk.estimate(hd), plain), tune
 
 
 @pytest.mark.parametrize("layout", ["fast", "small"])
@@ -213,24 +242,83 @@ def test_binned_scan_matches_direct_and_overflows_safely(V, O, layout):
     rnd = rng.integers(0, 2**32, (n_rand, 2), dtype=np.uint64).astype(np.uint32)
     slices = [np.concatenate([rep, rnd])[rng.permutation(n_rep + n_rand)], rnd[::-1].copy()]
     a = V.Sketch(m, g, k, seed, layout)
-    a.set_tuning(scan_binned=1)  # binned
+    a.set_tuning(scan_binned=1, scan_defer=2)  # binned
     b = V.Sketch(m, g, k, seed, layout)
-    b.set_tuning(scan_binned=2)  # direct
-    assert a.get_tuning()["scan_binned"] == 1
+    b.set_tuning(scan_binned=2, scan_defer=2)  # direct
+    c = V.Sketch(m, g, k, seed, layout)  # deferred (default): one tile's run overflows into direct updates
+    assert a.get_tuning()["scan_binned"] == 1 and c.info().scan_deferred == 1 and b.info().scan_deferred == 0
     osk = O.Sketch(m, g, k, seed, LAYOUT_CODE[layout])
     for pairs in slices:
         pd = _dev(V, pairs.reshape(-1))
         a.scan_slice(pd)
         b.scan_slice(pd)
+        c.scan_slice(pd)
         osk.scan(pairs)
-        sa, sb = a.state(), b.state()
+        sa, sb, sc = a.state(), b.state(), c.state()
         assert_state_equal(sa, osk.state(), layout, "binned scan vs oracle (open slice)")
         for key in ("dr", "bs", "reg", "hist"):
             assert np.array_equal(sa[key], sb[key]), key
+            assert np.array_equal(sc[key], sb[key]), key
         a.advance_slice()
         b.advance_slice()
+        c.advance_slice()
         osk.advance()
     assert_state_equal(a.state(), osk.state(), layout, "binned scan vs oracle (closed)")
+    assert_state_equal(c.state(), osk.state(), layout, "deferred scan vs oracle (closed)")
+
+
+@pytest.mark.parametrize("layout", ["fast", "small"])
+def test_deferred_scan_parity(V, O, layout):
+    """Large pools defer the scan's updates to the advance (records sorted by
+    tile of 2^15 BDRs).  A ragged pool (last tile partial), several scan
+    calls per slice, a state export in the middle of a slice (pending records
+    applied first), an empty slice, and switches of the mode in the middle of
+    a slice; the state after every advance and the estimates against the
+    oracle."""
+    m, g, k, seed = (1 << 22) + 77, 512, 3, 23
+    rng = np.random.default_rng(seed)
+    aips = rng.integers(0, 2**32, 4000, dtype=np.uint64).astype(np.uint32)
+    sk = V.Sketch(m, g, k, seed, layout)
+    assert sk.get_tuning()["scan_defer"] == 1 and sk.info().scan_deferred == 1
+    osk = O.Sketch(m, g, k, seed, LAYOUT_CODE[layout])
+    hosts = aips[:700]
+    for t in range(6):
+        n = 0 if t == 3 else int(rng.integers(1 << 18, 1 << 19))
+        pairs = np.stack([aips[rng.integers(0, len(aips), n)],
+                          rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
+        pd = _dev(V, pairs.reshape(-1))
+        cuts = [0, n // 3, n // 2, n]
+        for i, (a, b) in enumerate(zip(cuts[:-1], cuts[1:])):
+            if t == 4 and i == 1:
+                sk.set_tuning(scan_defer=2)  # pending records go to the pool
+            if t == 5 and i == 1:
+                sk.set_tuning(scan_defer=1)  # back, with bsLBP1 bits already set
+            sk.scan_slice(pd[2 * a: 2 * b])
+            if t == 1 and i == 0:
+                osk.scan(pairs[:b])
+                assert_state_equal(sk.state(), osk.state(), layout, "mid-slice export")
+                osk.scan(pairs[b:])
+        if t != 1:
+            osk.scan(pairs)
+        sk.advance_slice()
+        osk.advance()
+        assert_state_equal(sk.state(), osk.state(), layout, f"after advance of slice {t}")
+        assert_estimates_close(V, O, sk, osk, hosts)
+    # resume in the middle of a slice: the export applies the pending records,
+    # the import hands them to the next advance as pool state
+    n = 1 << 18
+    pairs = np.stack([aips[rng.integers(0, len(aips), n)],
+                      rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
+    sk.scan_slice(_dev(V, pairs.reshape(-1)))
+    mid = sk.state()
+    b = V.Sketch(m, g, k, seed, layout)
+    b.load_state(mid)
+    sk.advance_slice()
+    b.advance_slice()
+    osk.scan(pairs)
+    osk.advance()
+    assert_state_equal(b.state(), osk.state(), layout, "resumed")
+    assert_state_equal(sk.state(), osk.state(), layout, "continued")
 
 
 def test_resume_from_exported_state(V, O):
@@ -261,6 +349,8 @@ def test_bad_arguments_on_device(V):
     pairs = torch.zeros(8, dtype=torch.int32, device="cuda")
     with pytest.raises(V.VbdrError):
         sk.scan_slice(pairs[1:7])  # misaligned pointer
+    with pytest.raises(V.VbdrError):
+        sk.set_tuning(scan_defer=3)
     with pytest.raises(ValueError):
         sk.scan_slice(pairs.cpu())
     with pytest.raises(V.VbdrError):
