@@ -50,9 +50,15 @@ def algorithmic_bytes(kind, w, layout, L, n_hosts):
     raise ValueError(kind)
 
 
+# gfx950 L2: 8 XCDs x 16 channels, one tag lookup per channel per clock at 2.4 GHz.
+# A random 1-byte register gather that misses L1 costs one such request.
+L2_REQ_PEAK = 8 * 16 * 2.4e9
+
+
 def traffic_from_counters(kernel_name, n_launch_units):
-    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs,
-    if they were taken on the current kernel sources; else None."""
+    """HBM bytes per call of a hot-path stage (all kernels it launches) from
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs, if they were taken on the
+    current kernel sources; else None."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
@@ -195,6 +201,13 @@ def run_stress(args):
         del pd
     truth = learn.window_truth(seen_keys[-w.k:], host_keys)
     est = out.to(torch.float64)
+    # super-point detection at a threshold between the planted (>= 10^6) and background (<= 10^4) populations
+    thr = 1e5
+    found, _, n_found = vbdr.select_hosts(out, hosts, thr)
+    found = set(found.cpu().numpy().view(np.uint32).tolist())
+    real = set(st.aip[sel][(truth >= thr).cpu().numpy()].tolist())
+    detect = {"threshold": thr, "selected": n_found, "true_positives": len(found & real),
+              "precision": len(found & real) / max(len(found), 1), "recall": len(found & real) / max(len(real), 1)}
     ms = float(np.mean(times))
     res = {"metric": METRIC, "value": w.pairs_per_slice / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": K,
            "warmup": W, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -203,6 +216,7 @@ def run_stress(args):
                       "g": w.g, "k": w.k, "layout": args.layout, "estimated_hosts": len(sel)},
            "rms_rel_superspreaders": learn.rms_rel(est[:w.n_heavy], truth[:w.n_heavy]),
            "rms_rel_background": learn.rms_rel(est[w.n_heavy:], truth[w.n_heavy:]),
+           "detection": detect,
            "superspreader_truth": [int(v) for v in truth[:w.n_heavy].cpu()],
            "superspreader_estimate": [float(v) for v in est[:w.n_heavy].cpu()],
            "slices_in_window": min(W + K, w.k)}
@@ -308,11 +322,19 @@ def main():
     units = float(np.mean(timed_active))
     alg = algorithmic_bytes(dom, w, args.layout, L, units)
     achieved = alg / (avg[dom] * 1e-3) / 1e9
-    kernel_names = {"scan": "k_scan", "advance": "k_advance", "estimate": "k_estimate"}
-    traffic = traffic_from_counters(f"{kernel_names[dom]}:{args.layout}:{w.name}", units)
+    info = sk.info()
+    kernels = {"scan": "k_scan_defer" if info.scan_deferred else "k_scan",
+               "advance": ("k_advance_defer" if info.scan_deferred else "k_advance") + " + k_hist_reset",
+               "estimate": ("k_estimate_part + k_estimate_final" if info.est_parts > 1 else "k_estimate")}
+    traffic = traffic_from_counters(f"{dom}:{args.layout}:{w.name}", units)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel_names[dom],
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernels[dom],
                 "algorithmic_bytes_per_launch": alg}
+    if dom == "estimate":
+        # the estimate moves few bytes; its limit is the L2 request rate of g random gathers per host
+        gathers = units * w.g / (avg["estimate"] * 1e-3)
+        roofline["l2_requests"] = {"achieved": gathers, "peak": L2_REQ_PEAK, "unit": "requests/s",
+                                   "frac": round(gathers / L2_REQ_PEAK, 4)}
 
     res = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": K, "warmup": W,

@@ -131,7 +131,43 @@ int vbdr_estimate(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_hosts, 
 int vbdr_estimate_ex(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_hosts, float *out_dev,
                      double *raw_es_dev, uint32_t *hist_dev, void *stream);
 
-/* Parameters and slice counter of a sketch.  Host only, no device work. */
+/*
+ * Super-point (superspreader) detection over the sliding window, the use the
+ * paper motivates for per-host cardinalities (Sec. 1, Sec. 2.3): the hosts
+ * whose estimate is at least `threshold`.  est_dev and hosts_dev are device
+ * arrays of n entries (the output and input of an estimate call), n < 2^32.
+ * The selected hosts and their estimates go to out_hosts_dev and out_est_dev
+ * (device arrays of cap entries) in unspecified order; *count_dev (one device
+ * uint32) receives the number of hosts selected, which may exceed cap: then
+ * only cap of them are written.  Stream-ordered, no synchronisation.  NaN
+ * estimates are never selected.
+ */
+int vbdr_select_hosts(const float *est_dev, const uint32_t *hosts_dev, uint64_t n, float threshold,
+                      uint32_t *out_hosts_dev, float *out_est_dev, uint64_t cap, uint32_t *count_dev, void *stream);
+
+/*
+ * Per-slice max-LBP1 map, for data parallelism over one slice's pairs (fast
+ * layout).  The fast layout keeps of a slice only the highest LBP1 seen per
+ * BDR (Alg. 6), i.e. the serial layout's nowLBP1 (Alg. 1, Alg. 4).  Sketches
+ * with identical state (replicas) that scan disjoint shares of a slice can
+ * therefore export their maps, combine them with an element-wise MAX (on
+ * several GPUs: an all-reduce of m bytes), import the combined map, and
+ * advance: every replica then holds the state one sketch would after
+ * scanning all the pairs.
+ *   vbdr_export_now: now_dev[p] (m bytes, device) = highest LBP1 of the open
+ *     slice at BDR p, 0 if none.  The open slice is unchanged.
+ *   vbdr_import_now: the open slice's LBP1 record becomes exactly now_dev
+ *     (entries 0..L); earlier scans of the slice are replaced.
+ *   vbdr_now_max: out_dev[i] = max(a_dev[i], b_dev[i]) for n bytes (out may
+ *     alias a or b); the reduction operator of the exchange.
+ * VBDR_EINVAL for a small-layout sketch (it records every LBP1 of a slice,
+ * which a MAX does not combine).  Stream-ordered.
+ */
+int vbdr_export_now(vbdr_sketch *sk, uint8_t *now_dev, void *stream);
+int vbdr_import_now(vbdr_sketch *sk, const uint8_t *now_dev, void *stream);
+int vbdr_now_max(const uint8_t *a_dev, const uint8_t *b_dev, uint8_t *out_dev, uint64_t n, void *stream);
+
+/* Parameters and slice counter of a sketch.  Host only, no device work. *//* Parameters and slice counter of a sketch.  Host only, no device work. */
 int vbdr_sketch_info(const vbdr_sketch *sk, vbdr_info *out);
 
 /*

@@ -183,3 +183,15 @@ class Sketch:
         hist = np.zeros(NBINS, dtype=np.uint64)
         lib().vbdro_get_state(self._h, _ptr(dr), _ptr(bs), _ptr(now), _ptr(reg), _ptr(hist))
         return {"dr": dr, "bs": bs, "now": now, "reg": reg, "hist": hist, "t": self.t}
+
+
+def select_hosts(est, hosts, threshold: float):
+    """Super points over the window (Sec. 1 and Sec. 2.3 motivate per-host
+    cardinalities for superspreader detection): every host whose estimate is
+    at least the threshold, as a sorted array of (host, estimate) rows.  The
+    definition written out; NaN compares false and is never selected."""
+    est = np.asarray(est, dtype=np.float32).reshape(-1)
+    hosts = np.asarray(hosts, dtype=np.uint32).reshape(-1)
+    keep = [i for i in range(len(est)) if est[i] >= np.float32(threshold)]
+    rows = sorted((int(hosts[i]), float(est[i])) for i in keep)
+    return rows

@@ -467,6 +467,15 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
   const unsigned long long f = fill[tile];
   const uint32_t n = f < cap ? (uint32_t)f : cap;
   const bool use_seen = FAST && fill[tiles] != 0;
+  // the top plane's load goes out before the record phase
+  const uint64_t base = (uint64_t)tile * kDeferTile + (uint64_t)threadIdx.x * 32;
+  const bool live = base < mstride;
+  u32x4 top0 = {0u, 0u, 0u, 0u}, top1 = {0u, 0u, 0u, 0u};
+  if (live) {
+    const uint8_t* top = dr + (uint64_t)(L - 1) * mstride + base;
+    top0 = *reinterpret_cast<const u32x4*>(top);
+    top1 = *reinterpret_cast<const u32x4*>(top + 16);
+  }
   __syncthreads();
   if (threadIdx.x == 0) fill[tile] = 0;  // every thread has read it
   const uint32_t* r = recs + (uint64_t)tile * cap;
@@ -476,11 +485,10 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
     atomicOr(&pm[(rec & 31u) * kDeferWords + (p >> 5)], 1u << (p & 31));
   }
   __syncthreads();
-  const uint64_t base = (uint64_t)tile * kDeferTile + (uint64_t)threadIdx.x * 32;
-  if (base < mstride) {
+  if (live) {
     uint32_t R[8];
     advance_group32<FAST>(dr, mstride, seen, wstride, reg, reg4, base, L, swar_gt_bias(thr), pm + threadIdx.x,
-                          kDeferWords, use_seen, R);
+                          kDeferWords, use_seen, top0, top1, R);
 #pragma unroll
     for (int j = 0; j < 32; ++j)
       if (base + j < m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
@@ -723,8 +731,8 @@ __global__ __launch_bounds__(256) void k_estimate_final(uint32_t nh, uint32_t g,
 // range x on the workgroups of XCD x and gathers from the L2-resident nibble
 // registers.  Entries beyond a run's capacity are gathered directly in pass 1
 // and kept as a per-host overflow sum, so every (host, i) is counted exactly
-// once.  Runs are written and read with non-temporal accesses so that they do
-// not push the nibble registers out of L2.
+// once.  (Non-temporal stores and loads of the runs were measured 1.5x slower:
+// the runs' partial lines then leave L2 before they are complete.)
 // GUARD: g is not a multiple of 64 * kBinRows.  POW2: m = 2^(32 - mshift), so
 // that H(x, m, A) is a shift of the hash instead of a high multiply.
 constexpr int kBinRows = 4;  // hash rows per wave in flight in pass 1
@@ -766,7 +774,7 @@ __global__ __launch_bounds__(kEstBlock) void k_est_bin(const uint32_t* __restric
         if (slot[u] < cap) {
           // run (h, x) starts at (8 h + x) cap; byte offsets < 4 * 8 * hc * cap <= 2^29
           const uint32_t off = (hbase + __umul24(x[u], cap) + slot[u]) * 4u;
-          __builtin_nontemporal_store(p[u], reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(slots) + off));
+          *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(slots) + off) = p[u];
         } else if (slot[u] != ~0u) {
           const uint32_t r = reg[p[u]];
           oU += 1ull << (32 - r);
@@ -813,7 +821,7 @@ __global__ __launch_bounds__(kEstBlock) void k_est_gather(uint32_t nh, const uin
       uint32_t p[kGatherRows], nb[kGatherRows];
 #pragma unroll
       for (int u = 0; u < kGatherRows; ++u)
-        p[u] = j0 + 16u * u < n ? __builtin_nontemporal_load(run + j0 + 16u * u) : 0u;
+        p[u] = j0 + 16u * u < n ? run[j0 + 16u * u] : 0u;
 #pragma unroll
       for (int u = 0; u < kGatherRows; ++u) nb[u] = j0 + 16u * u < n ? (uint32_t)reg4[p[u] >> 1] : 0u;
 #pragma unroll
@@ -835,6 +843,103 @@ __global__ __launch_bounds__(kEstBlock) void k_est_gather(uint32_t nh, const uin
     if (ql == 0 && h < nh) {
       part_u[(uint64_t)x * kPartChunk + h] = U;
       part_v[(uint64_t)x * kPartChunk + h] = V;
+    }
+  }
+}
+
+// ------------------------------------------------- per-slice max-LBP1 map
+// Fast layout only.  The open slice's LBP1 record is split between the
+// bsLBP1 bit-planes and, with deferred scans, the pending records of each
+// tile; export folds both into one byte per BDR (the highest LBP1), one
+// workgroup per tile of kDeferTile BDRs, 32 BDRs per thread.
+__global__ __launch_bounds__(kDeferBlock) void k_now_export(const uint32_t* __restrict__ seen, uint64_t wstride,
+                                                            uint64_t mstride, uint64_t m, uint32_t L,
+                                                            const uint32_t* __restrict__ recs,
+                                                            const unsigned long long* __restrict__ fill, uint32_t cap,
+                                                            uint8_t* __restrict__ now) {
+  extern __shared__ uint32_t pm[];
+  const uint32_t tile = blockIdx.x;
+  for (uint32_t i = threadIdx.x; i < L * kDeferWords; i += kDeferBlock) pm[i] = 0;
+  __syncthreads();
+  if (recs) {
+    const unsigned long long f = fill[tile];
+    const uint32_t n = f < cap ? (uint32_t)f : cap;
+    for (uint32_t j = threadIdx.x; j < n; j += kDeferBlock) {
+      const uint32_t rec = recs[(uint64_t)tile * cap + j];
+      const uint32_t p = (rec >> 5) & (kDeferTile - 1);
+      atomicOr(&pm[(rec & 31u) * kDeferWords + (p >> 5)], 1u << (p & 31));
+    }
+  }
+  __syncthreads();
+  const uint64_t base = (uint64_t)tile * kDeferTile + (uint64_t)threadIdx.x * 32;
+  if (base >= m) return;
+  uint32_t R[8] = {0, 0, 0, 0, 0, 0, 0, 0}, done = 0;
+  for (int i = (int)L; i >= 1; --i) {
+    const uint32_t bits = pm[(uint32_t)(i - 1) * kDeferWords + threadIdx.x] | seen[(uint64_t)(i - 1) * wstride + (base >> 5)];
+    const uint32_t fold = bits & ~done;
+    done |= bits;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) R[w] |= swar_nibble_to_bytes((fold >> (4 * w)) & 0xFu) & ((uint32_t)i * 0x01010101u);
+  }
+  if (base + 32 <= m) {
+    *reinterpret_cast<u32x4*>(now + base) = u32x4{R[0], R[1], R[2], R[3]};
+    *reinterpret_cast<u32x4*>(now + base + 16) = u32x4{R[4], R[5], R[6], R[7]};
+  } else {
+    for (uint32_t j = 0; base + j < m; ++j) now[base + j] = (uint8_t)(R[j >> 2] >> (8 * (j & 3)));
+  }
+}
+
+// The open slice's record becomes `now`: bit-plane word w of plane r-1 gets
+// bit j set exactly when now[32 w + j] == r (values outside 1..L set nothing).
+__global__ __launch_bounds__(256) void k_now_import(const uint8_t* __restrict__ now, uint64_t m, uint32_t L,
+                                                    uint32_t* __restrict__ seen, uint64_t wstride) {
+  const uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (w >= wstride) return;
+  uint32_t v[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) v[j] = 32 * w + j < m ? now[32 * w + j] : 0u;
+  for (uint32_t r = 1; r <= L; ++r) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) word |= (uint32_t)(v[j] == r) << j;
+    seen[(uint64_t)(r - 1) * wstride + w] = word;
+  }
+}
+
+__global__ void k_now_max(const uint8_t* __restrict__ a, const uint8_t* __restrict__ b, uint8_t* __restrict__ out,
+                          uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint8_t x = a[i], y = b[i];
+    out[i] = x > y ? x : y;
+  }
+}
+
+// ------------------------------------------------ super-point selection
+// Hosts whose estimate reaches the threshold, compacted per wave: a ballot
+// gives each selected lane its rank, one atomic per wave reserves the run.
+__global__ void k_select_reset(uint32_t* __restrict__ count) {
+  if (threadIdx.x == 0) *count = 0;
+}
+
+__global__ __launch_bounds__(256) void k_select(const float* __restrict__ est, const uint32_t* __restrict__ hosts,
+                                                uint32_t n, float thr, uint32_t* __restrict__ out_hosts,
+                                                float* __restrict__ out_est, uint32_t cap,
+                                                uint32_t* __restrict__ count) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (uint32_t i0 = blockIdx.x * 256 + (threadIdx.x & ~63u); i0 < n; i0 += gridDim.x * 256) {
+    const uint32_t i = i0 + lane;
+    const float e = i < n ? est[i] : 0.0f;
+    const bool take = i < n && e >= thr;
+    const uint64_t mask = __ballot(take);
+    if (!mask) continue;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(count, (uint32_t)__popcll(mask));
+    base = __shfl(base, 0);
+    const uint32_t at = base + (uint32_t)__popcll(mask & below);
+    if (take && at < cap) {
+      out_hosts[at] = hosts[i];
+      out_est[at] = e;
     }
   }
 }
@@ -1299,6 +1404,67 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
 
 int vbdr_estimate(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, float* out_dev, void* stream) {
   return vbdr_estimate_ex(sk, hosts_dev, n_hosts, out_dev, nullptr, nullptr, stream);
+}
+
+int vbdr_export_now(vbdr_sketch* sk, uint8_t* now_dev, void* stream) {
+  if (!sk || !now_dev) return vbdr_fail(VBDR_EINVAL, "NULL argument");
+  if (sk->layout != VBDR_LAYOUT_FAST) return vbdr_fail(VBDR_EINVAL, "max-LBP1 maps need the fast layout");
+  if (int rc = vbdr_check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const uint32_t tiles = (uint32_t)((sk->mstride + kDeferTile - 1) / kDeferTile);
+  hipLaunchKernelGGL(k_now_export, dim3(tiles), dim3(kDeferBlock), (size_t)sk->L * kDeferWords * 4, st, sk->seen,
+                     sk->wstride, sk->mstride, sk->m, sk->L, sk->def_rec, sk->def_fill, sk->def_cap, now_dev);
+  VBDR_LAUNCHED("k_now_export");
+  return VBDR_OK;
+}
+
+int vbdr_import_now(vbdr_sketch* sk, const uint8_t* now_dev, void* stream) {
+  if (!sk || !now_dev) return vbdr_fail(VBDR_EINVAL, "NULL argument");
+  if (sk->layout != VBDR_LAYOUT_FAST) return vbdr_fail(VBDR_EINVAL, "max-LBP1 maps need the fast layout");
+  if (int rc = vbdr_check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (sk->def_fill) {  // pending records are replaced; the advance must read the bit-planes
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(sk->def_fill),
+                       (uint64_t)sk->def_tiles * 2, 0u);
+    VBDR_LAUNCHED("k_fill_u32(def_fill)");
+    hipLaunchKernelGGL(k_defer_flag, dim3(1), dim3(64), 0, st, sk->def_fill, sk->def_tiles, 1ull);
+    VBDR_LAUNCHED("k_defer_flag");
+  }
+  hipLaunchKernelGGL(k_now_import, dim3((uint32_t)((sk->wstride + 255) / 256)), dim3(256), 0, st, now_dev, sk->m,
+                     sk->L, sk->seen, sk->wstride);
+  VBDR_LAUNCHED("k_now_import");
+  return VBDR_OK;
+}
+
+int vbdr_now_max(const uint8_t* a_dev, const uint8_t* b_dev, uint8_t* out_dev, uint64_t n, void* stream) {
+  if (n == 0) return VBDR_OK;
+  if (!a_dev || !b_dev || !out_dev) return vbdr_fail(VBDR_EINVAL, "NULL argument");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const uint64_t want = (n + 255) / 256;
+  hipLaunchKernelGGL(k_now_max, dim3((uint32_t)(want < 8192 ? want : 8192)), dim3(256), 0, st, a_dev, b_dev, out_dev, n);
+  VBDR_LAUNCHED("k_now_max");
+  return VBDR_OK;
+}
+
+int vbdr_select_hosts(const float* est_dev, const uint32_t* hosts_dev, uint64_t n, float threshold,
+                      uint32_t* out_hosts_dev, float* out_est_dev, uint64_t cap, uint32_t* count_dev, void* stream) {
+  if (!count_dev) return vbdr_fail(VBDR_EINVAL, "count_dev is NULL");
+  if (n >= (1ull << 32)) return vbdr_fail(VBDR_EINVAL, "n=%llu must be below 2^32", (unsigned long long)n);
+  if (n && (!est_dev || !hosts_dev)) return vbdr_fail(VBDR_EINVAL, "est_dev and hosts_dev must not be NULL");
+  if (cap && (!out_hosts_dev || !out_est_dev)) return vbdr_fail(VBDR_EINVAL, "output arrays must not be NULL");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_select_reset, dim3(1), dim3(64), 0, st, count_dev);
+  VBDR_LAUNCHED("k_select_reset");
+  if (n == 0) return VBDR_OK;
+  int dev = 0, n_cu = 0;
+  VBDR_HIP(hipGetDevice(&dev));
+  VBDR_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  const uint64_t want = (n + 255) / 256, capb = (uint64_t)n_cu * 8;
+  const uint32_t c32 = cap < 0xFFFFFFFFull ? (uint32_t)cap : 0xFFFFFFFFu;
+  hipLaunchKernelGGL(k_select, dim3((uint32_t)(want < capb ? want : capb)), dim3(256), 0, st, est_dev, hosts_dev,
+                     (uint32_t)n, threshold, out_hosts_dev, out_est_dev, c32, count_dev);
+  VBDR_LAUNCHED("k_select");
+  return VBDR_OK;
 }
 
 int vbdr_export_state(vbdr_sketch* sk, uint8_t* dr_host, uint32_t* bs_host, uint8_t* reg_host, uint64_t* hist_host,

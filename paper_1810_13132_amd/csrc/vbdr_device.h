@@ -202,19 +202,18 @@ __device__ __forceinline__ void advance_group(uint8_t* dr, uint64_t mstride, uin
 // before the slide.  Fast layout: the bits join bsLBP1 (Alg. 7) and the
 // slice's highest LBP1 is set after the slide (Alg. 6).  use_seen: the
 // bsLBP1 bit-planes in memory may hold bits too (fast layout); they are
-// read and cleared.  R receives the 32 registers, byte j of R[w] = BDR
-// base + 4w + j; they are also stored to reg and reg4.
+// read and cleared.  dn0, dn1: the 32 DRs of plane L, loaded by the caller
+// (so that the load can be issued early).  R receives the 32 registers, byte j
+// of R[w] = BDR base + 4w + j; they are also stored to reg and reg4.
 template <bool FAST>
 __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, uint32_t* seen, uint64_t wstride,
                                                 uint8_t* reg, uint8_t* reg4, uint64_t base, uint32_t L,
                                                 uint32_t gt_bias, const uint32_t* pm, uint32_t pm_stride,
-                                                bool use_seen, uint32_t R[8]) {
+                                                bool use_seen, u32x4 dn0, u32x4 dn1, uint32_t R[8]) {
   uint32_t M[8];
 #pragma unroll
   for (int w = 0; w < 8; ++w) M[w] = R[w] = 0;
   uint32_t folded = 0;
-  const uint8_t* top = dr + (uint64_t)(L - 1) * mstride + base;
-  u32x4 dn0 = *reinterpret_cast<const u32x4*>(top), dn1 = *reinterpret_cast<const u32x4*>(top + 16);
   uint32_t sn = 0;
   if (FAST && use_seen) sn = seen[(uint64_t)(L - 1) * wstride + (base >> 5)];
   for (int i = (int)L; i >= 1; --i) {

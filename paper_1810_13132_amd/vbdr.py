@@ -58,7 +58,8 @@ EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_destr
            "vbdr_mlp_create", "vbdr_mlp_destroy", "vbdr_features", "vbdr_estimate_learned", "vbdr_trainer_create",
            "vbdr_trainer_destroy", "vbdr_trainer_set_lr", "vbdr_trainer_step", "vbdr_trainer_grad",
            "vbdr_trainer_params", "vbdr_batch_create", "vbdr_batch_destroy", "vbdr_batch_sketch",
-           "vbdr_batch_set_tuning", "vbdr_batch_get_tuning", "vbdr_batch_step"]
+           "vbdr_batch_set_tuning", "vbdr_batch_get_tuning", "vbdr_batch_step", "vbdr_select_hosts",
+           "vbdr_export_now", "vbdr_import_now", "vbdr_now_max"]
 VOID_EXPORTS = ("vbdr_sketch_destroy", "vbdr_last_error", "vbdr_mlp_destroy", "vbdr_trainer_destroy",
                 "vbdr_batch_destroy", "vbdr_batch_sketch")
 MLP_IN, MLP_PARAMS = 67, 8577
@@ -102,6 +103,10 @@ def lib():
         L.vbdr_batch_sketch.argtypes = [vp, u32]
         L.vbdr_batch_set_tuning.argtypes = [vp, C.POINTER(BatchTuning)]
         L.vbdr_batch_get_tuning.argtypes = [vp, C.POINTER(BatchTuning)]
+        L.vbdr_select_hosts.argtypes = [vp, vp, u64, C.c_float, vp, vp, u64, vp, vp]
+        L.vbdr_export_now.argtypes = [vp, vp, vp]
+        L.vbdr_import_now.argtypes = [vp, vp, vp]
+        L.vbdr_now_max.argtypes = [vp, vp, vp, u64, vp]
         L.vbdr_batch_step.argtypes = [vp, C.POINTER(vp), C.POINTER(u64), C.POINTER(vp), C.POINTER(u64),
                                       C.POINTER(vp), vp]
         L.vbdr_last_error.restype = C.c_char_p
@@ -179,6 +184,20 @@ class Sketch:
         t = Tuning(scan_test_first, scan_blocks_per_cu, est_blocks_per_cu, scan_binned, est_binned, est_parts,
                    est_bin_hosts, est_bin_cap, scan_defer)
         _check(lib().vbdr_sketch_set_tuning(self._h, C.byref(t)))
+
+    def export_now(self, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        """(m,) uint8 device map of the open slice's highest LBP1 per BDR (fast layout)."""
+        m = int(self.info().m)
+        if out is None:
+            out = torch.empty(m, dtype=torch.uint8, device="cuda")
+        _check(lib().vbdr_export_now(self._h, _dev_ptr(out, (torch.uint8,), "now"), _stream(stream)))
+        return out
+
+    def import_now(self, now: torch.Tensor, stream=None):
+        """Make `now` ((m,) uint8 device) the open slice's LBP1 record (fast layout)."""
+        if now.numel() != int(self.info().m):
+            raise ValueError("now must hold m bytes")
+        _check(lib().vbdr_import_now(self._h, _dev_ptr(now, (torch.uint8,), "now"), _stream(stream)))
 
     def get_tuning(self) -> dict:
         t = Tuning()
@@ -267,6 +286,37 @@ class Sketch:
             raise ValueError("state shapes do not match the sketch")
         _check(lib().vbdr_import_state(self._h, dr.ctypes.data, None if bs is None else bs.ctypes.data,
                                        reg.ctypes.data, hist.ctypes.data, int(state["t"]), _stream(stream)))
+
+
+def now_max(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """Element-wise MAX of two uint8 device maps (the exchange's reduction)."""
+    if a.numel() != b.numel():
+        raise ValueError("maps differ in length")
+    out = torch.empty_like(a) if out is None else out
+    _check(lib().vbdr_now_max(_dev_ptr(a, (torch.uint8,), "a"), _dev_ptr(b, (torch.uint8,), "b"),
+                              _dev_ptr(out, (torch.uint8,), "out"), a.numel(), _stream(stream)))
+    return out
+
+
+def select_hosts(est: torch.Tensor, hosts: torch.Tensor, threshold: float, cap: int = None, stream=None):
+    """Super points: the hosts whose estimate is at least `threshold`.
+    Returns (hosts, estimates, count) with hosts/estimates on the device in
+    unspecified order; count is the number selected (only min(count, cap)
+    are returned)."""
+    n = est.numel()
+    if hosts.numel() != n:
+        raise ValueError("est and hosts must have the same length")
+    cap = n if cap is None else cap
+    oh = torch.empty(max(cap, 1), dtype=torch.int32, device=est.device)
+    oe = torch.empty(max(cap, 1), dtype=torch.float32, device=est.device)
+    cnt = torch.empty(1, dtype=torch.int32, device=est.device)
+    _check(lib().vbdr_select_hosts(_dev_ptr(est, (torch.float32,), "est") if n else None,
+                                   _dev_ptr(hosts, _U32, "hosts") if n else None, n, float(threshold),
+                                   _dev_ptr(oh, _U32, "out_hosts"), _dev_ptr(oe, (torch.float32,), "out_est"), cap,
+                                   _dev_ptr(cnt, _U32, "count"), _stream(stream)))
+    c = int(cnt.item())
+    k = min(c, cap)
+    return oh[:k], oe[:k], c
 
 
 def to_device_u32(a: np.ndarray, device="cuda") -> torch.Tensor:
