@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle_vbdr.so")
 
 SERIAL, GFAST, GSMALL = 0, 1, 2
+HLL, LOGLOG, PCSA = 0, 1, 2  # estimators over the pool
 NBINS = 33
 
 _lib = None
@@ -57,6 +58,12 @@ def lib():
         L.vbdro_estimate.argtypes = [vp, vp, u64, vp, vp, vp]
         L.vbdro_sum_lbp1.restype = u64
         L.vbdro_sum_lbp1.argtypes = [vp, u32]
+        L.vbdro_loglog_alpha.restype = C.c_double
+        L.vbdro_loglog_alpha.argtypes = [C.c_double]
+        L.vbdro_estimate_kind.restype = C.c_int
+        L.vbdro_estimate_kind.argtypes = [vp, vp, u64, C.c_int, vp, vp]
+        L.vbdro_get_preg.restype = C.c_int
+        L.vbdro_get_preg.argtypes = [vp, vp]
         L.vbdro_params.restype = None
         L.vbdro_params.argtypes = [vp, vp]
         L.vbdro_get_state.restype = None
@@ -90,6 +97,10 @@ def lbp1(w: int, b: int) -> int:
 
 def alpha(q: float) -> float:
     return float(lib().vbdro_alpha(q))
+
+
+def loglog_alpha(q: float) -> float:
+    return float(lib().vbdro_loglog_alpha(float(q)))
 
 
 def hll_from_hist(hist, q: float) -> float:
@@ -172,6 +183,25 @@ class Sketch:
 
     def sum_lbp1(self, aip: int) -> int:
         return int(lib().vbdro_sum_lbp1(self._h, aip))
+
+    def estimate_kind(self, hosts, kind: int, with_raw: bool = False):
+        """Noise-removed LogLog (kind LOGLOG) or PCSA (kind PCSA, small layout) estimates."""
+        if kind == HLL:
+            return self.estimate(hosts, with_raw=with_raw)
+        hosts = np.ascontiguousarray(hosts, dtype=np.uint32).reshape(-1)
+        n = hosts.shape[0]
+        out = np.zeros(n, dtype=np.float32)
+        raw = np.zeros(n, dtype=np.float64)
+        if lib().vbdro_estimate_kind(self._h, _ptr(hosts), n, kind, _ptr(out), _ptr(raw)) != 0:
+            raise ValueError("estimator not available for this sketch")
+        return (out, raw) if with_raw else out
+
+    def pcsa_registers(self):
+        """(m,) PCSA runs of the last closed window (small layout)."""
+        out = np.zeros(self.m, dtype=np.uint8)
+        if lib().vbdro_get_preg(self._h, _ptr(out)) != 0:
+            raise ValueError("PCSA registers need the small layout")
+        return out
 
     def state(self):
         """Canonical state: dict of dr (m, L), bs (m,), now (m,), reg (m,), hist (33,)."""

@@ -39,6 +39,16 @@
  *    correction apply; the noise of pool sharing is removed with
  *    n = (m*E_s - g*E_m)/(m - g), E_m being the same estimator over the whole
  *    pool.  The result is clamped at 0 and rounded to FP32.
+ *  - Other estimators on the same pool (the text after Alg. 5 in Sec. 4.1,
+ *    and Sec. 5, name PCSA and LogLog as users of the pool): LogLog
+ *    (Durand and Flajolet 2003) takes
+ *    the same registers, E = alpha_q q 2^(S/q) with S the literal sum of
+ *    Alg. 5 and alpha_q = (Gamma(-1/q) (1 - 2^(1/q)) / ln 2)^-q; PCSA
+ *    (Flajolet and Martin 1985) reads each recorder vector as the bitmap of
+ *    the LBP1 values seen in the window (a DR per bit: only the small layout
+ *    records every LBP1 of a slice), R = the number of consecutive active
+ *    DRs from LBP1 1, E = (q / 0.77351) 2^(S/q) with S the sum of R.  Both
+ *    remove the sharing noise with the same (m*E_s - g*E_m)/(m - g).
  */
 #include <math.h>
 #include <stdint.h>
@@ -146,6 +156,7 @@ typedef struct {
     uint8_t *now;     /* serial: nowLBP1 per BDR */
     uint32_t *bs;     /* fast GPU layout: bsLBP1 per BDR, bit r-1 <-> LBP1 r */
     uint8_t *reg;     /* register of each BDR over the last closed window */
+    uint8_t *preg;    /* small layout: PCSA run of each BDR over the last closed window */
     uint64_t pool_hist[NBINS];
     uint64_t t;       /* closed slices */
 } vbdro_sketch;
@@ -178,8 +189,11 @@ vbdro_sketch *vbdro_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_see
         s->now = (uint8_t *)calloc(m, 1);
     if (layout == VBDRO_GFAST)
         s->bs = (uint32_t *)calloc(m, sizeof(uint32_t));
-    if (!s->drv || !s->reg || (layout == VBDRO_SERIAL && !s->now) || (layout == VBDRO_GFAST && !s->bs)) {
-        free(s->drv), free(s->reg), free(s->now), free(s->bs), free(s);
+    if (layout == VBDRO_GSMALL)
+        s->preg = (uint8_t *)calloc(m, 1);
+    if (!s->drv || !s->reg || (layout == VBDRO_SERIAL && !s->now) || (layout == VBDRO_GFAST && !s->bs) ||
+        (layout == VBDRO_GSMALL && !s->preg)) {
+        free(s->drv), free(s->reg), free(s->now), free(s->bs), free(s->preg), free(s);
         return NULL;
     }
     for (uint64_t p = 0; p < m; p++)
@@ -194,7 +208,7 @@ void vbdro_destroy(vbdro_sketch *s)
 {
     if (!s)
         return;
-    free(s->drv), free(s->reg), free(s->now), free(s->bs), free(s);
+    free(s->drv), free(s->reg), free(s->now), free(s->bs), free(s->preg), free(s);
 }
 
 /* DR operations of Sec. 3. */
@@ -281,6 +295,17 @@ static uint32_t GetLBP1BDR(vbdro_sketch *s, uint64_t p)
     return 0;
 }
 
+/* PCSA reading of a recorder vector: the number of consecutive active DRs
+ * from LBP1 1 upwards, i.e. the index of the lowest unset bitmap bit. */
+static uint32_t PcsaRun(vbdro_sketch *s, uint64_t p)
+{
+    uint8_t *v = DRV(s, p);
+    uint32_t r = 0;
+    while (r < s->L && IsActiveDR(v[r + 1], s->k))
+        r++;
+    return r;
+}
+
 /* Close the open slice. */
 void vbdro_advance(vbdro_sketch *s)
 {
@@ -311,6 +336,7 @@ void vbdro_advance(vbdro_sketch *s)
             /* Small layout: read the closed window first (Alg. 2), then
              * Alg. 8 BeginSliceUpdateDRV for the next slice. */
             s->reg[p] = (uint8_t)GetLBP1BDR(s, p);
+            s->preg[p] = (uint8_t)PcsaRun(s, p);
             for (uint32_t i = 1; i <= s->L; i++)
                 SlideDR(&v[i]);
         }
@@ -372,6 +398,65 @@ void vbdro_estimate(vbdro_sketch *s, const uint32_t *hosts, uint64_t n, float *o
             for (uint32_t r = 0; r < NBINS; r++)
                 hist_out[h * NBINS + r] = (uint32_t)hist[r];
     }
+}
+
+/* LogLog constant alpha_q of Durand and Flajolet (2003),
+ * (Gamma(-1/q) (1 - 2^(1/q)) / ln 2)^-q.  With x = 1/q and y = x ln 2,
+ * |Gamma(-x)| = Gamma(1-x)/x and 2^x - 1 = y (1 + z), z = sum_k>=1 y^k/(k+1)!,
+ * so alpha_q = exp(-q (ln Gamma(1-x) + ln(1+z))): no term cancels, which a
+ * pool of 2^24 and more registers needs.  q >= 16 (y < 0.05: ten terms of z
+ * leave an error below 1e-20). */
+double vbdro_loglog_alpha(double q)
+{
+    double x = 1.0 / q, y = x * log(2.0), z = 0.0, term = 1.0;
+    for (int k = 1; k <= 10; k++) {
+        term *= y / (double)(k + 1);
+        z += term;
+    }
+    return exp(-q * (lgamma(1.0 - x) + log1p(z)));
+}
+
+/* Estimators on the sum S of q per-recorder values: LogLog over registers
+ * (kind 1), PCSA over PCSA runs (kind 2). */
+static double sum_estimate(int kind, double S, double q)
+{
+    if (kind == 1)
+        return vbdro_loglog_alpha(q) * q * pow(2.0, S / q);
+    return q / 0.77351 * pow(2.0, S / q);
+}
+
+/* Noise-removed LogLog (kind 1) or PCSA (kind 2) estimates of n hosts;
+ * raw_es (nullable) receives each E_s.  -1 for PCSA without a small-layout
+ * pool or for an unknown kind. */
+int vbdro_estimate_kind(vbdro_sketch *s, const uint32_t *hosts, uint64_t n, int kind, float *out, double *raw_es)
+{
+    if (kind != 1 && !(kind == 2 && s->layout == VBDRO_GSMALL))
+        return -1;
+    const uint8_t *val = kind == 1 ? s->reg : s->preg;
+    uint64_t pool = 0;
+    for (uint64_t p = 0; p < s->m; p++)
+        pool += val[p];
+    double Em = sum_estimate(kind, (double)pool, (double)s->m);
+    for (uint64_t h = 0; h < n; h++) {
+        uint64_t S = 0;
+        for (uint32_t i = 0; i < s->g; i++)
+            S += val[vbdro_phy_idx(s, hosts[h], i)];
+        double Es = sum_estimate(kind, (double)S, (double)s->g);
+        double nh = ((double)s->m * Es - (double)s->g * Em) / ((double)s->m - (double)s->g);
+        out[h] = (float)(nh > 0.0 ? nh : 0.0);
+        if (raw_es)
+            raw_es[h] = Es;
+    }
+    return 0;
+}
+
+/* PCSA runs of the last closed window (small layout), else -1. */
+int vbdro_get_preg(const vbdro_sketch *s, uint8_t *out)
+{
+    if (!s->preg)
+        return -1;
+    memcpy(out, s->preg, s->m);
+    return 0;
 }
 
 /* Literal Alg. 5: the sum of the g LBP1 values of a host. */

@@ -93,6 +93,24 @@ def fresh_registers(slices, m, g, k, hash_seed):
     return reg.astype(np.uint8)
 
 
+def fresh_pcsa_runs(slices, m, g, k, hash_seed):
+    """PCSA reading of the pool over the last k closed slices: the bitmap of
+    BDR p holds every LBP1 seen there; the run is the number of consecutive
+    set bits from LBP1 1."""
+    b = int(g).bit_length() - 1
+    L = 33 - b
+    seen = np.zeros((m, L + 2), dtype=bool)
+    for pairs in slices[max(0, len(slices) - k):]:
+        p, r = pair_map(pairs, m, g, hash_seed)
+        seen[p, r] = True
+    run = np.zeros(m, dtype=np.int64)
+    alive = np.ones(m, dtype=bool)
+    for r in range(1, L + 1):
+        alive &= seen[:, r]
+        run += alive
+    return run.astype(np.uint8)
+
+
 def closed_form_dr(slices, m, g, hash_seed, layout: str):
     """Distance recorders after closing every slice in ``slices``.
 

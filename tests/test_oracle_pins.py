@@ -332,3 +332,108 @@ def test_exact_counts_helper():
     got = synth.exact_counts(slices[1:], hosts)
     ref = [B.exact_cardinality(slices[1:], h) for h in hosts.tolist()]
     assert got.tolist() == ref
+
+
+# ---- LogLog and PCSA on the same pool (the pool serves them too: text after Alg. 5, Sec. 5)
+
+def test_loglog_alpha(oracle_mod):
+    """alpha_q of Durand and Flajolet: the oracle's cancellation-free form
+    against the defining Gamma expression where that one is still accurate
+    (small q), and against the limit exp(-gamma - ln2/2) = 0.39701 for large q."""
+    import math
+    for q in (16, 32, 64, 128, 256):
+        # the direct form loses digits to 1 - 2^(1/q), then the power -q amplifies them
+        direct = (math.gamma(-1.0 / q) * (1.0 - 2.0 ** (1.0 / q)) / math.log(2.0)) ** (-q)
+        assert abs(oracle_mod.loglog_alpha(q) - direct) <= q * 2e-14 * direct
+    limit = math.exp(-0.5772156649015329 - math.log(2.0) / 2)
+    assert abs(oracle_mod.loglog_alpha(2.0 ** 31) - limit) < 1e-9
+    assert abs(oracle_mod.loglog_alpha(2.0 ** 31) - 0.39701) < 5e-6  # the published constant
+    assert oracle_mod.loglog_alpha(1024) < oracle_mod.loglog_alpha(2 ** 20) < limit
+
+
+def _single_host_maxima_and_bitmaps(aip, bips, g, hash_seed):
+    """Textbook LogLog / PCSA inputs of one host, straight from the hashes."""
+    b = int(g).bit_length() - 1
+    _, A1 = B.seeds(hash_seed)
+    h = B.murmur3_u32(bips, A1).astype(np.uint64)
+    vidx = (h >> np.uint64(32 - b)).astype(np.int64)
+    rho = B.rho_of((h << np.uint64(b)) & np.uint64(B.M32), b)
+    M = np.zeros(g, dtype=np.int64)
+    np.maximum.at(M, vidx, rho)
+    bits = np.zeros((g, 34), dtype=bool)
+    bits[vidx, rho] = True
+    R = np.zeros(g, dtype=np.int64)
+    alive = np.ones(g, dtype=bool)
+    for r in range(1, 34):
+        alive &= bits[:, r]
+        R += alive
+    return M, R
+
+
+@pytest.mark.parametrize("g", [64, 256])
+def test_loglog_pcsa_single_host_textbook(oracle_mod, g):
+    """With one host and no collision among its g physical BDRs, E_s is the
+    textbook LogLog (Durand-Flajolet) and PCSA (Flajolet-Martin, phi =
+    0.77351) estimate of the host's stream on the same hash."""
+    import math
+    O = oracle_mod
+    m, k, seed, aip = 1 << 20, 2, 7, 0xC0A80001
+    assert len(set(B.host_pidx(aip, m, g, seed).tolist())) == g
+    rng = np.random.default_rng(g)
+    bips = rng.choice(2**32, 5000, replace=False).astype(np.uint32)
+    sk = O.Sketch(m, g, k, seed, O.GSMALL)
+    sk.scan(np.stack([np.full(len(bips), aip, np.uint32), bips], 1))
+    sk.advance()
+    M, R = _single_host_maxima_and_bitmaps(aip, bips, g, seed)
+    alpha = (math.gamma(-1.0 / g) * (1.0 - 2.0 ** (1.0 / g)) / math.log(2.0)) ** (-g)
+    ll = alpha * g * 2.0 ** (M.sum() / g)
+    pc = g / 0.77351 * 2.0 ** (R.sum() / g)
+    _, raw_ll = sk.estimate_kind([aip], O.LOGLOG, with_raw=True)
+    _, raw_pc = sk.estimate_kind([aip], O.PCSA, with_raw=True)
+    assert abs(raw_ll[0] - ll) <= g * 2e-14 * ll  # alpha's direct form, as above
+    assert abs(raw_pc[0] - pc) <= 1e-12 * pc
+    assert sk.sum_lbp1(aip) == M.sum()  # Alg. 5 as written is LogLog's sum
+
+
+def test_pcsa_runs_are_fresh_bitmaps(oracle_mod):
+    """The oracle's PCSA runs equal those of fresh bitmaps over the last k
+    closed slices (small layout), after every slice of a random history."""
+    O = oracle_mod
+    m, g, k, seed = 3000, 16, 3, 5
+    rng = np.random.default_rng(3)
+    aips = rng.integers(0, 2**32, 40, dtype=np.uint64).astype(np.uint32)
+    sk = O.Sketch(m, g, k, seed, O.GSMALL)
+    slices = []
+    for t in range(8):
+        n = 0 if t == 4 else 4000
+        pairs = np.stack([aips[rng.integers(0, 40, n)], rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)],
+                         1).astype(np.uint32)
+        slices.append(pairs)
+        sk.scan(pairs)
+        sk.advance()
+        assert np.array_equal(sk.pcsa_registers(), B.fresh_pcsa_runs(slices, m, g, k, seed)), t
+    with pytest.raises(ValueError):
+        O.Sketch(m, g, k, seed, O.GFAST).estimate_kind(aips, O.PCSA)
+
+
+def test_loglog_pcsa_accuracy(oracle_mod):
+    """Many hosts of 20000 distinct peers in a large pool: the noise-removed
+    LogLog and PCSA estimates are unbiased to a few percent and their
+    relative error is near the published 1.30/sqrt(g) and 0.78/sqrt(g)."""
+    O = oracle_mod
+    m, g, k, seed = 1 << 22, 64, 1, 9
+    rng = np.random.default_rng(12)
+    hosts = rng.choice(2**32, 60, replace=False).astype(np.uint32)
+    n = 20000
+    a = np.repeat(hosts, n)
+    bb = rng.integers(0, 2**32, len(a), dtype=np.uint64).astype(np.uint32)
+    sk = O.Sketch(m, g, k, seed, O.GSMALL)
+    sk.scan(np.stack([a, bb], 1))
+    sk.advance()
+    truth = np.array([len(set(bb[i * n:(i + 1) * n].tolist())) for i in range(len(hosts))], dtype=np.float64)
+    for kind, sigma in ((O.LOGLOG, 1.30), (O.PCSA, 0.78)):
+        est = sk.estimate_kind(hosts, kind).astype(np.float64)
+        rel = est / truth - 1.0
+        assert abs(rel.mean()) < 0.06, (kind, rel.mean())
+        rms = float(np.sqrt(np.mean(rel ** 2)))
+        assert 0.5 * sigma / np.sqrt(g) < rms < 1.6 * sigma / np.sqrt(g), (kind, rms)
