@@ -132,6 +132,35 @@ int vbdr_estimate_ex(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_host
                      double *raw_es_dev, uint32_t *hist_dev, void *stream);
 
 /*
+ * Other estimators on the same pool: the text after Alg. 5 (Sec. 4.1) and
+ * Sec. 5 name PCSA and LogLog as users of the recorder pool.
+ *   VBDR_EST_HLL     the HyperLogLog estimate of vbdr_estimate;
+ *   VBDR_EST_LOGLOG  LogLog (Durand and Flajolet 2003) over the same
+ *                    registers: E_s = alpha_g g 2^(S/g), S the host's
+ *                    literal sum of Alg. 5, alpha_q = (Gamma(-1/q)
+ *                    (1 - 2^(1/q)) / ln 2)^-q;
+ *   VBDR_EST_PCSA    PCSA (Flajolet and Martin 1985): a recorder vector read
+ *                    as the bitmap of the LBP1 values active in the window,
+ *                    R = the number of consecutive active DRs from LBP1 1,
+ *                    E_s = g / 0.77351 2^(S/g) with S the host's sum of R.
+ *                    Small layout only (it records every LBP1 of a slice);
+ *                    the runs are kept from the advance after
+ *                    vbdr_enable_pcsa(sk, 1) on, at m more bytes of state.
+ * E_m is the same estimator over the pool; the sharing noise is removed
+ * with (m E_s - g E_m)/(m - g), clamped at 0, FP64 then FP32, as for
+ * HyperLogLog.  raw_es_dev (n_hosts double, nullable) receives E_s.
+ * vbdr_estimate_kind reads the pool's sums on the host (it synchronises
+ * with `stream`).  VBDR_ESTATE for PCSA before runs exist.
+ * vbdr_export_pcsa copies the m PCSA runs of the last closed window to host
+ * memory (synchronous).  vbdr_enable_pcsa(sk, 0) frees the runs.
+ */
+enum vbdr_estimator { VBDR_EST_HLL = 0, VBDR_EST_LOGLOG = 1, VBDR_EST_PCSA = 2 };
+int vbdr_enable_pcsa(vbdr_sketch *sk, int on);
+int vbdr_estimate_kind(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_hosts, int kind, float *out_dev,
+                       double *raw_es_dev, void *stream);
+int vbdr_export_pcsa(vbdr_sketch *sk, uint8_t *preg_host, void *stream);
+
+/*
  * Super-point (superspreader) detection over the sliding window, the use the
  * paper motivates for per-host cardinalities (Sec. 1, Sec. 2.3): the hosts
  * whose estimate is at least `threshold`.  est_dev and hosts_dev are device

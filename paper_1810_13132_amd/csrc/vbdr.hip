@@ -16,6 +16,7 @@
 // scanned (pidx < m), keep DR = 255 and register 0, and are not counted.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -68,8 +69,20 @@ __global__ void k_seeds(uint32_t* __restrict__ s1, uint32_t g, uint32_t A0) {
   if (i < g) s1[i] = mm3(i, A0);
 }
 
-__global__ void k_hist_reset(unsigned long long* __restrict__ hist, unsigned long long first) {
+__global__ void k_hist_reset(unsigned long long* __restrict__ hist, unsigned long long first,
+                             unsigned long long* __restrict__ psum) {
   if (threadIdx.x < kBins) hist[threadIdx.x] = threadIdx.x == 0 ? first : 0ull;
+  if (psum && threadIdx.x == 0) *psum = 0;
+}
+
+// Adds the PCSA runs P[0..n) (four per word) of a thread to the pool's sum.
+template <int N>
+__device__ __forceinline__ void add_pcsa_sum(const uint32_t* P, unsigned long long* psum) {
+  uint32_t t = 0;
+#pragma unroll
+  for (int w = 0; w < N; ++w) t += byte_sum(P[w]);
+  const uint64_t s = wave_sum_u64(t);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(psum, (unsigned long long)s);
 }
 
 // ----------------------------------------------------------------- scan
@@ -278,14 +291,17 @@ __global__ __launch_bounds__(kAdvBlock) void k_advance(uint8_t* __restrict__ dr,
                                                        uint32_t* __restrict__ seen, uint64_t wstride,
                                                        uint8_t* __restrict__ reg, uint8_t* __restrict__ reg4,
                                                        uint64_t m, uint32_t L, uint32_t thr,
-                                                       unsigned long long* __restrict__ hist) {
+                                                       unsigned long long* __restrict__ hist,
+                                                       uint8_t* __restrict__ preg,
+                                                       unsigned long long* __restrict__ psum) {
   __shared__ uint32_t lh[kAdvBlock / 64][kBins];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane < kBins) lh[wave][lane] = 0;
   __syncthreads();
   const uint64_t base = ((uint64_t)blockIdx.x * kAdvBlock + threadIdx.x) * kAdvBpt;
-  uint32_t R[4];
-  advance_group<FAST>(dr, mstride, seen, wstride, reg, reg4, base, L, swar_gt_bias(thr), R);
+  uint32_t R[4], P[4];
+  advance_group<FAST>(dr, mstride, seen, wstride, reg, reg4, base, L, swar_gt_bias(thr), R, preg, P);
+  if (!FAST && preg) add_pcsa_sum<4>(P, psum);  // padding BDRs have run 0
 #pragma unroll
   for (int j = 0; j < kAdvBpt; ++j)
     if (base + j < m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
@@ -457,7 +473,8 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
                                                                unsigned long long* __restrict__ hist,
                                                                const uint32_t* __restrict__ recs,
                                                                unsigned long long* __restrict__ fill, uint32_t cap,
-                                                               uint32_t tiles) {
+                                                               uint32_t tiles, uint8_t* __restrict__ preg,
+                                                               unsigned long long* __restrict__ psum) {
   extern __shared__ uint32_t pm[];
   __shared__ uint32_t lh[kDeferBlock / 64][kBins];
   const uint32_t tile = blockIdx.x;
@@ -485,14 +502,16 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
     atomicOr(&pm[(rec & 31u) * kDeferWords + (p >> 5)], 1u << (p & 31));
   }
   __syncthreads();
+  uint32_t P[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (live) {
     uint32_t R[8];
     advance_group32<FAST>(dr, mstride, seen, wstride, reg, reg4, base, L, swar_gt_bias(thr), pm + threadIdx.x,
-                          kDeferWords, use_seen, top0, top1, R);
+                          kDeferWords, use_seen, top0, top1, R, preg, P);
 #pragma unroll
     for (int j = 0; j < 32; ++j)
       if (base + j < m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
   }
+  if (!FAST && preg) add_pcsa_sum<8>(P, psum);  // every lane of the wave takes part
   __syncthreads();
   if (threadIdx.x < kBins) {
     uint32_t c = 0;
@@ -847,6 +866,40 @@ __global__ __launch_bounds__(kEstBlock) void k_est_gather(uint32_t nh, const uin
   }
 }
 
+// ------------------------------------------- LogLog and PCSA on the pool
+// The pool serves other estimators than HyperLogLog (the text after Alg. 5,
+// Sec. 5).  One wave per host gathers the host's g values -- registers for
+// LogLog (Alg. 5's literal sum), PCSA runs for PCSA -- and sums them; E_s =
+// c_g * g * 2^(S/g) with c = alpha_g (LogLog) or 1/0.77351 (PCSA), E_m the
+// same over the pool, then the noise removal of the HyperLogLog path.
+__global__ __launch_bounds__(kEstBlock) void k_estimate_sum(const uint32_t* __restrict__ hosts, uint64_t nh,
+                                                            const uint32_t* __restrict__ s1, uint32_t g, uint32_t m,
+                                                            const uint8_t* __restrict__ val, double cg, double Em,
+                                                            float* __restrict__ out, double* __restrict__ raw) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint64_t h = (uint64_t)blockIdx.x * kEstWaves + wave; h < nh; h += (uint64_t)gridDim.x * kEstWaves) {
+    const uint32_t kmix = mm3_key(hosts[h]);
+    uint32_t S = 0;
+    for (uint32_t i0 = lane; i0 < g; i0 += 64 * 4) {
+      uint32_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t i = i0 + 64u * u;
+        v[u] = i < g ? (uint32_t)val[reduce_m(mm3_seeded(kmix, s1[i]), m)] : 0u;
+      }
+      S += v[0] + v[1] + v[2] + v[3];
+    }
+    S = (uint32_t)wave_sum_u64(S);
+    if (lane == 0) {
+#pragma clang fp contract(off)
+      const double Es = cg * (double)g * exp2((double)S / (double)g);
+      const double n = noise_removed(Es, Em, (double)m, (double)g);
+      out[h] = (float)(n > 0.0 ? n : 0.0);
+      if (raw) raw[h] = Es;
+    }
+  }
+}
+
 // ------------------------------------------------- per-slice max-LBP1 map
 // Fast layout only.  The open slice's LBP1 record is split between the
 // bsLBP1 bit-planes and, with deferred scans, the pending records of each
@@ -961,6 +1014,21 @@ uint32_t grid_cap(const vbdr_sketch* sk, uint64_t want, uint32_t per_cu) {
   return (uint32_t)(want < cap ? want : cap);
 }
 
+// LogLog constant alpha_q of Durand and Flajolet (2003),
+// (Gamma(-1/q) (1 - 2^(1/q)) / ln 2)^-q.  With x = 1/q, y = x ln 2,
+// |Gamma(-x)| = Gamma(1-x)/x and 2^x - 1 = y (1 + z), z = sum_k>=1 y^k/(k+1)!:
+// alpha_q = exp(-q (ln Gamma(1-x) + ln(1+z))), free of cancellation for the
+// large q of a pool.  q >= 16.
+double loglog_alpha(double q) {
+  const double x = 1.0 / q, y = x * std::log(2.0);
+  double z = 0.0, term = 1.0;
+  for (int k = 1; k <= 10; ++k) {
+    term *= y / (double)(k + 1);
+    z += term;
+  }
+  return std::exp(-q * (std::lgamma(1.0 - x) + std::log1p(z)));
+}
+
 uint64_t splitmix64_first(uint64_t state) {
   uint64_t z = state + 0x9e3779b97f4a7c15ull;
   z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -983,7 +1051,8 @@ int init_state(vbdr_sketch* sk, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, sk->seen, (uint64_t)sk->L * sk->wstride, 0u);
     VBDR_LAUNCHED("k_fill_u32(seen)");
   }
-  hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(64), 0, st, sk->hist, (unsigned long long)sk->m);
+  hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(64), 0, st, sk->hist, (unsigned long long)sk->m,
+                     (unsigned long long*)nullptr);
   VBDR_LAUNCHED("k_hist_reset");
   if (sk->def_fill) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(sk->def_fill),
@@ -1189,6 +1258,8 @@ void vbdr_sketch_destroy(vbdr_sketch* sk) {
   if (sk->ovf_v) (void)hipFree(sk->ovf_v);
   if (sk->def_rec) (void)hipFree(sk->def_rec);
   if (sk->def_fill) (void)hipFree(sk->def_fill);
+  if (sk->preg) (void)hipFree(sk->preg);
+  if (sk->psum) (void)hipFree(sk->psum);
   if (prev >= 0 && prev != sk->device) (void)hipSetDevice(prev);
   delete sk;
 }
@@ -1314,13 +1385,14 @@ int vbdr_advance_slice(vbdr_sketch* sk, void* stream) {
   if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
   if (int rc = vbdr_check_device(sk)) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(64), 0, st, sk->hist, 0ull);
+  hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(64), 0, st, sk->hist, 0ull, sk->psum);
   VBDR_LAUNCHED("k_hist_reset");
+  if (sk->preg) sk->pcsa_valid = true;  // written by the launch below
   if (sk->def_rec && sk->tune.scan_defer == 1) {
     auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_advance_defer<true> : k_advance_defer<false>;
     hipLaunchKernelGGL(kern, dim3(sk->def_tiles), dim3(kDeferBlock), (size_t)sk->L * kDeferWords * 4, st, sk->dr,
                        sk->mstride, sk->seen, sk->wstride, sk->reg, sk->reg4, sk->m, sk->L, sk->k - 1, sk->hist,
-                       sk->def_rec, sk->def_fill, sk->def_cap, sk->def_tiles);
+                       sk->def_rec, sk->def_fill, sk->def_cap, sk->def_tiles, sk->preg, sk->psum);
     VBDR_LAUNCHED("k_advance_defer");
     hipLaunchKernelGGL(k_defer_flag, dim3(1), dim3(64), 0, st, sk->def_fill, sk->def_tiles, 0ull);
     VBDR_LAUNCHED("k_defer_flag");
@@ -1330,7 +1402,7 @@ int vbdr_advance_slice(vbdr_sketch* sk, void* stream) {
   const uint32_t grid = (uint32_t)(sk->mstride / (kAdvBlock * kAdvBpt));
   auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_advance<true> : k_advance<false>;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kAdvBlock), 0, st, sk->dr, sk->mstride, sk->seen, sk->wstride, sk->reg,
-                     sk->reg4, sk->m, sk->L, sk->k - 1, sk->hist);
+                     sk->reg4, sk->m, sk->L, sk->k - 1, sk->hist, sk->preg, sk->psum);
   VBDR_LAUNCHED("k_advance");
   sk->t++;
   return VBDR_OK;
@@ -1404,6 +1476,76 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
 
 int vbdr_estimate(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, float* out_dev, void* stream) {
   return vbdr_estimate_ex(sk, hosts_dev, n_hosts, out_dev, nullptr, nullptr, stream);
+}
+
+int vbdr_enable_pcsa(vbdr_sketch* sk, int on) {
+  if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
+  if (sk->layout != VBDR_LAYOUT_SMALL) return vbdr_fail(VBDR_EINVAL, "PCSA runs need the small layout");
+  if (int rc = vbdr_check_device(sk)) return rc;
+  VBDR_HIP(hipDeviceSynchronize());
+  if (on && !sk->preg) {
+    if (hipMalloc(&sk->preg, sk->mstride) != hipSuccess || hipMalloc(&sk->psum, 8) != hipSuccess) {
+      (void)hipGetLastError();
+      if (sk->preg) (void)hipFree(sk->preg);
+      sk->preg = nullptr;
+      return vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed", (unsigned long long)sk->mstride);
+    }
+    sk->bytes += sk->mstride + 8;
+  } else if (!on && sk->preg) {
+    (void)hipFree(sk->preg);
+    (void)hipFree(sk->psum);
+    sk->preg = nullptr, sk->psum = nullptr;
+    sk->bytes -= sk->mstride + 8;
+  }
+  sk->pcsa_valid = false;
+  return VBDR_OK;
+}
+
+int vbdr_estimate_kind(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, int kind, float* out_dev,
+                       double* raw_es_dev, void* stream) {
+  if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
+  if (kind == VBDR_EST_HLL) return vbdr_estimate_ex(sk, hosts_dev, n_hosts, out_dev, raw_es_dev, nullptr, stream);
+  if (kind != VBDR_EST_LOGLOG && kind != VBDR_EST_PCSA) return vbdr_fail(VBDR_EINVAL, "unknown estimator %d", kind);
+  if (kind == VBDR_EST_PCSA && !sk->pcsa_valid)
+    return vbdr_fail(VBDR_ESTATE, "no PCSA runs: enable them (small layout), then advance a slice");
+  if (n_hosts == 0) return VBDR_OK;
+  if (!hosts_dev || !out_dev) return vbdr_fail(VBDR_EINVAL, "hosts_dev and out_dev must not be NULL");
+  if (int rc = vbdr_check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // the pool's sum of values: registers from the histogram, PCSA runs from the advance's sum
+  double pool_sum = 0.0;
+  if (kind == VBDR_EST_LOGLOG) {
+    uint64_t hist[kBins];
+    VBDR_HIP(hipMemcpyAsync(hist, sk->hist, sizeof(hist), hipMemcpyDeviceToHost, st));
+    VBDR_HIP(hipStreamSynchronize(st));
+    uint64_t s = 0;
+    for (int r = 0; r < kBins; ++r) s += hist[r] * (uint64_t)r;
+    pool_sum = (double)s;
+  } else {
+    unsigned long long s = 0;
+    VBDR_HIP(hipMemcpyAsync(&s, sk->psum, sizeof(s), hipMemcpyDeviceToHost, st));
+    VBDR_HIP(hipStreamSynchronize(st));
+    pool_sum = (double)s;
+  }
+  const double q = (double)sk->m, g = (double)sk->g;
+  const double cg = kind == VBDR_EST_LOGLOG ? loglog_alpha(g) : 1.0 / 0.77351;
+  const double cm = kind == VBDR_EST_LOGLOG ? loglog_alpha(q) : 1.0 / 0.77351;
+  const double Em = cm * q * std::exp2(pool_sum / q);
+  const uint32_t grid = grid_cap(sk, (n_hosts + kEstWaves - 1) / kEstWaves, sk->tune.est_blocks_per_cu);
+  hipLaunchKernelGGL(k_estimate_sum, dim3(grid), dim3(kEstBlock), 0, st, hosts_dev, n_hosts, sk->s1, sk->g,
+                     (uint32_t)sk->m, kind == VBDR_EST_LOGLOG ? sk->reg : sk->preg, cg, Em, out_dev, raw_es_dev);
+  VBDR_LAUNCHED("k_estimate_sum");
+  return VBDR_OK;
+}
+
+int vbdr_export_pcsa(vbdr_sketch* sk, uint8_t* preg_host, void* stream) {
+  if (!sk || !preg_host) return vbdr_fail(VBDR_EINVAL, "NULL argument");
+  if (!sk->pcsa_valid) return vbdr_fail(VBDR_ESTATE, "no PCSA runs: enable them (small layout), then advance a slice");
+  if (int rc = vbdr_check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  VBDR_HIP(hipStreamSynchronize(st));
+  VBDR_HIP(hipMemcpy(preg_host, sk->preg, sk->m, hipMemcpyDeviceToHost));
+  return VBDR_OK;
 }
 
 int vbdr_export_now(vbdr_sketch* sk, uint8_t* now_dev, void* stream) {
@@ -1551,6 +1693,7 @@ int vbdr_import_state(vbdr_sketch* sk, const uint8_t* dr_host, const uint32_t* b
   VBDR_LAUNCHED("k_pack_reg4");
   VBDR_HIP(hipStreamSynchronize(nullptr));
   sk->t = t;
+  sk->pcsa_valid = false;  // PCSA runs are not part of the canonical state: valid again after an advance
   return VBDR_OK;
 }
 

@@ -147,12 +147,17 @@ __device__ __forceinline__ void scan_pair(uint32_t aip, uint32_t bip, const uint
 // (byte j of R[w] = BDR base + 4w + j); they are also stored to reg and reg4.
 // With 16 BDRs per thread, the two threads sharing a bsLBP1 word are
 // adjacent lanes of one wave and both consume it before the even one clears it.
+// With `preg` (small layout), also the PCSA run of each BDR, the number of
+// consecutive active DRs from LBP1 1 (the lowest inactive LBP1 minus 1),
+// stored to preg; P receives the 16 runs like R.
 template <bool FAST>
 __device__ __forceinline__ void advance_group(uint8_t* dr, uint64_t mstride, uint32_t* seen, uint64_t wstride,
                                               uint8_t* reg, uint8_t* reg4, uint64_t base, uint32_t L,
-                                              uint32_t gt_bias, uint32_t R[4]) {
-  uint32_t M[4] = {0, 0, 0, 0};
+                                              uint32_t gt_bias, uint32_t R[4], uint8_t* preg = nullptr,
+                                              uint32_t* P = nullptr) {
+  uint32_t M[4] = {0, 0, 0, 0}, Q[4];
   R[0] = R[1] = R[2] = R[3] = 0;
+  Q[0] = Q[1] = Q[2] = Q[3] = L * 0x01010101u;
   uint32_t folded = 0;
   u32x4 dn = *reinterpret_cast<const u32x4*>(dr + (uint64_t)(L - 1) * mstride + base);
   uint32_t sn = 0;
@@ -179,9 +184,15 @@ __device__ __forceinline__ void advance_group(uint8_t* dr, uint64_t mstride, uin
       const uint32_t act = swar_le_mask(FAST ? y : x, gt_bias);                   // IsActiveDR
       R[w] |= act & ~M[w] & ((uint32_t)i * 0x01010101u);
       M[w] |= act;
+      if (!FAST && preg) Q[w] = (Q[w] & act) | (~act & ((uint32_t)(i - 1) * 0x01010101u));
       nd[w] = y;
     }
     *reinterpret_cast<u32x4*>(dr + (uint64_t)(i - 1) * mstride + base) = nd;
+  }
+  if (!FAST && preg) {
+    *reinterpret_cast<u32x4*>(preg + base) = u32x4{Q[0], Q[1], Q[2], Q[3]};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) P[w] = Q[w];
   }
   if constexpr (FAST) {
     if ((base & 31) == 0)
@@ -209,10 +220,14 @@ template <bool FAST>
 __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, uint32_t* seen, uint64_t wstride,
                                                 uint8_t* reg, uint8_t* reg4, uint64_t base, uint32_t L,
                                                 uint32_t gt_bias, const uint32_t* pm, uint32_t pm_stride,
-                                                bool use_seen, u32x4 dn0, u32x4 dn1, uint32_t R[8]) {
-  uint32_t M[8];
+                                                bool use_seen, u32x4 dn0, u32x4 dn1, uint32_t R[8],
+                                                uint8_t* preg = nullptr, uint32_t* P = nullptr) {
+  uint32_t M[8], Q[8];
 #pragma unroll
-  for (int w = 0; w < 8; ++w) M[w] = R[w] = 0;
+  for (int w = 0; w < 8; ++w) {
+    M[w] = R[w] = 0;
+    Q[w] = L * 0x01010101u;
+  }
   uint32_t folded = 0;
   uint32_t sn = 0;
   if (FAST && use_seen) sn = seen[(uint64_t)(L - 1) * wstride + (base >> 5)];
@@ -241,6 +256,7 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
       const uint32_t act = swar_le_mask(FAST ? y : x, gt_bias);                    // IsActiveDR
       R[w] |= act & ~M[w] & ((uint32_t)i * 0x01010101u);
       M[w] |= act;
+      if (!FAST && preg) Q[w] = (Q[w] & act) | (~act & ((uint32_t)(i - 1) * 0x01010101u));
       if (w < 4) nd0[w] = y; else nd1[w - 4] = y;
     }
     uint8_t* out = dr + (uint64_t)(i - 1) * mstride + base;
@@ -251,11 +267,20 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
     for (uint32_t i = 0; i < L; ++i) seen[(uint64_t)i * wstride + (base >> 5)] = 0;
   *reinterpret_cast<u32x4*>(reg + base) = u32x4{R[0], R[1], R[2], R[3]};
   *reinterpret_cast<u32x4*>(reg + base + 16) = u32x4{R[4], R[5], R[6], R[7]};
+  if (!FAST && preg) {
+    *reinterpret_cast<u32x4*>(preg + base) = u32x4{Q[0], Q[1], Q[2], Q[3]};
+    *reinterpret_cast<u32x4*>(preg + base + 16) = u32x4{Q[4], Q[5], Q[6], Q[7]};
+#pragma unroll
+    for (int w = 0; w < 8; ++w) P[w] = Q[w];
+  }
   u32x4 nib;
 #pragma unroll
   for (int q = 0; q < 4; ++q) nib[q] = swar_pack_nibbles(R[2 * q]) | (swar_pack_nibbles(R[2 * q + 1]) << 16);
   *reinterpret_cast<u32x4*>(reg4 + base / 2) = nib;
 }
+
+// Sum of the four bytes of x when it is below 256.
+__device__ __forceinline__ uint32_t byte_sum(uint32_t x) { return (x * 0x01010101u) >> 24; }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);

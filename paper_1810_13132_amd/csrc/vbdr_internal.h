@@ -50,6 +50,9 @@ struct vbdr_sketch {
   unsigned long long* def_fill;   // [def_tiles + 1] records per tile; the last word flags direct updates
   uint32_t def_tiles, def_cap;
   bool lean;                      // no optional workspaces (sketches owned by a batch)
+  uint8_t* preg;                  // small layout, on request: PCSA run of each BDR, last closed window
+  unsigned long long* psum;       // sum of preg over the pool
+  bool pcsa_valid;                // preg was written by an advance since it was enabled
   uint64_t bytes;
   vbdr_tuning tune;
 };

@@ -19,6 +19,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libvbdr.so")
 
 LAYOUTS = {"fast": 0, "small": 1}
+ESTIMATORS = {"hll": 0, "loglog": 1, "pcsa": 2}
 NBINS = 33
 STATUS = {0: "VBDR_OK", -1: "VBDR_EINVAL", -2: "VBDR_ENOMEM", -3: "VBDR_EHIP", -4: "VBDR_ESTATE"}
 
@@ -59,7 +60,8 @@ EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_destr
            "vbdr_trainer_destroy", "vbdr_trainer_set_lr", "vbdr_trainer_step", "vbdr_trainer_grad",
            "vbdr_trainer_params", "vbdr_batch_create", "vbdr_batch_destroy", "vbdr_batch_sketch",
            "vbdr_batch_set_tuning", "vbdr_batch_get_tuning", "vbdr_batch_step", "vbdr_select_hosts",
-           "vbdr_export_now", "vbdr_import_now", "vbdr_now_max"]
+           "vbdr_export_now", "vbdr_import_now", "vbdr_now_max", "vbdr_enable_pcsa", "vbdr_estimate_kind",
+           "vbdr_export_pcsa"]
 VOID_EXPORTS = ("vbdr_sketch_destroy", "vbdr_last_error", "vbdr_mlp_destroy", "vbdr_trainer_destroy",
                 "vbdr_batch_destroy", "vbdr_batch_sketch")
 MLP_IN, MLP_PARAMS = 67, 8577
@@ -105,6 +107,9 @@ def lib():
         L.vbdr_batch_get_tuning.argtypes = [vp, C.POINTER(BatchTuning)]
         L.vbdr_select_hosts.argtypes = [vp, vp, u64, C.c_float, vp, vp, u64, vp, vp]
         L.vbdr_export_now.argtypes = [vp, vp, vp]
+        L.vbdr_enable_pcsa.argtypes = [vp, i32]
+        L.vbdr_estimate_kind.argtypes = [vp, vp, u64, i32, vp, vp, vp]
+        L.vbdr_export_pcsa.argtypes = [vp, vp, vp]
         L.vbdr_import_now.argtypes = [vp, vp, vp]
         L.vbdr_now_max.argtypes = [vp, vp, vp, u64, vp]
         L.vbdr_batch_step.argtypes = [vp, C.POINTER(vp), C.POINTER(u64), C.POINTER(vp), C.POINTER(u64),
@@ -184,6 +189,28 @@ class Sketch:
         t = Tuning(scan_test_first, scan_blocks_per_cu, est_blocks_per_cu, scan_binned, est_binned, est_parts,
                    est_bin_hosts, est_bin_cap, scan_defer)
         _check(lib().vbdr_sketch_set_tuning(self._h, C.byref(t)))
+
+    def enable_pcsa(self, on: bool = True):
+        """Keep PCSA runs from the next advance on (small layout)."""
+        _check(lib().vbdr_enable_pcsa(self._h, 1 if on else 0))
+
+    def estimate_kind(self, hosts: torch.Tensor, kind: str, with_raw: bool = False, stream=None):
+        """Noise-removed estimates by `kind` in ("hll", "loglog", "pcsa")."""
+        n = hosts.numel()
+        out = torch.empty(n, dtype=torch.float32, device=hosts.device)
+        raw = torch.empty(n, dtype=torch.float64, device=hosts.device) if with_raw else None
+        if n:
+            _check(lib().vbdr_estimate_kind(self._h, _dev_ptr(hosts, _U32, "hosts"), n, ESTIMATORS[kind],
+                                            _dev_ptr(out, (torch.float32,), "out"),
+                                            _dev_ptr(raw, (torch.float64,), "raw") if with_raw else None,
+                                            _stream(stream)))
+        return (out, raw) if with_raw else out
+
+    def pcsa_registers(self, stream=None) -> np.ndarray:
+        """(m,) PCSA runs of the last closed window (host copy)."""
+        out = np.zeros(int(self.info().m), dtype=np.uint8)
+        _check(lib().vbdr_export_pcsa(self._h, out.ctypes.data_as(C.c_void_p), _stream(stream)))
+        return out
 
     def export_now(self, out: torch.Tensor = None, stream=None) -> torch.Tensor:
         """(m,) uint8 device map of the open slice's highest LBP1 per BDR (fast layout)."""
