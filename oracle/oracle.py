@@ -13,7 +13,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle_vbdr.so")
 
-SERIAL, GFAST, GSMALL = 0, 1, 2
+SERIAL, GFAST, GSMALL, GPACKED = 0, 1, 2, 3
 HLL, LOGLOG, PCSA = 0, 1, 2  # estimators over the pool
 NBINS = 33
 
@@ -38,6 +38,8 @@ def lib():
         L.vbdro_lbp1.argtypes = [u32, u32]
         L.vbdro_create.restype = vp
         L.vbdro_create.argtypes = [u64, u32, u32, u64, C.c_int]
+        L.vbdro_create_packed.restype = vp
+        L.vbdro_create_packed.argtypes = [u64, u32, u32, u64, u32]
         L.vbdro_destroy.restype = None
         L.vbdro_destroy.argtypes = [vp]
         L.vbdro_phy_idx.restype = u32
@@ -123,13 +125,17 @@ def map_pairs(m: int, g: int, hash_seed: int, pairs: np.ndarray):
 class Sketch:
     """One VBDR sketch held by the oracle."""
 
-    def __init__(self, m: int, g: int, k: int, hash_seed: int, layout: int = GFAST):
-        self._h = lib().vbdro_create(m, g, k, hash_seed, layout)
+    def __init__(self, m: int, g: int, k: int, hash_seed: int, layout: int = GFAST, Lc: int = 0):
+        if layout == GPACKED:
+            self._h = lib().vbdro_create_packed(m, g, k, hash_seed, Lc)
+        else:
+            self._h = lib().vbdro_create(m, g, k, hash_seed, layout)
         if not self._h:
-            raise ValueError(f"oracle rejects m={m} g={g} k={k} layout={layout}")
+            raise ValueError(f"oracle rejects m={m} g={g} k={k} layout={layout} Lc={Lc}")
         p = self.params()
         self.m, self.g, self.b, self.L, self.k = p[0], p[1], p[2], p[3], p[4]
         self.layout, self.A0, self.A1 = p[5], p[6], p[7]
+        self.Lc, self.sat = p[9], p[10]
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -138,7 +144,7 @@ class Sketch:
             self._h = None
 
     def params(self):
-        out = np.zeros(9, dtype=np.uint64)
+        out = np.zeros(11, dtype=np.uint64)
         lib().vbdro_params(self._h, _ptr(out))
         return [int(v) for v in out]
 
@@ -197,7 +203,7 @@ class Sketch:
         return (out, raw) if with_raw else out
 
     def pcsa_registers(self):
-        """(m,) PCSA runs of the last closed window (small layout)."""
+        """(m,) PCSA runs of the last closed window (small and packed layouts)."""
         out = np.zeros(self.m, dtype=np.uint8)
         if lib().vbdro_get_preg(self._h, _ptr(out)) != 0:
             raise ValueError("PCSA registers need the small layout")

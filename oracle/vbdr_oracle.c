@@ -49,6 +49,11 @@
  *    records every LBP1 of a slice), R = the number of consecutive active
  *    DRs from LBP1 1, E = (q / 0.77351) 2^(S/q) with S the sum of R.  Both
  *    remove the sharing noise with the same (m*E_s - g*E_m)/(m - g).
+ *  - Packed layout (Table 1's gsmall: log2(n/g) DRs of log2(k+1) bits): the
+ *    small layout with z = ceil(log2(k+1))-bit DRs, InitDR and saturation at
+ *    2^z - 1 (>= k, so a DR that left the window stays inactive), and Lc
+ *    recorders per BDR with LBP1 values above Lc recorded at Lc, so that a
+ *    register is min(register, Lc) of the full layout.
  */
 #include <math.h>
 #include <stdint.h>
@@ -58,6 +63,7 @@
 #define VBDRO_SERIAL 0
 #define VBDRO_GFAST 1
 #define VBDRO_GSMALL 2
+#define VBDRO_GPACKED 3 /* small layout with z-bit DRs and Lc recorders (Table 1's gsmall) */
 
 #define DR_BITS 8u
 #define DR_INIT 255u /* InitDR: 2^z - 1 with z = 8 */
@@ -150,6 +156,8 @@ typedef struct {
     uint64_t m;       /* BDRs in the pool BDRP */
     uint32_t g, b, L; /* g = 2^b recorders per host; L = 33-b LBP1 values */
     uint32_t k;       /* window length in slices */
+    uint32_t Lc;      /* recorders kept per BDR: L, or the packed layout's cap (LBP1 clamped to it) */
+    uint32_t sat;     /* InitDR value and saturation bound: 255, or 2^z - 1 for z-bit DRs */
     int layout;
     uint32_t A0, A1;
     uint8_t *drv;     /* DRV of BDR p at drv[p*(L+1) + i], i = 1..L */
@@ -163,10 +171,10 @@ typedef struct {
 
 static int is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
-vbdro_sketch *vbdro_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout)
+static vbdro_sketch *create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, uint32_t Lc)
 {
     if (!is_pow2(g) || g < 2 || g > 65536u || m <= g || m >= (1ull << 32) || k < 1 || k > 254 ||
-        layout < VBDRO_SERIAL || layout > VBDRO_GSMALL)
+        layout < VBDRO_SERIAL || layout > VBDRO_GPACKED)
         return NULL;
     vbdro_sketch *s = (vbdro_sketch *)calloc(1, sizeof(*s));
     if (!s)
@@ -179,6 +187,21 @@ vbdro_sketch *vbdro_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_see
     s->L = 33 - s->b;
     s->k = k;
     s->layout = layout;
+    s->Lc = s->L;
+    s->sat = DR_INIT;
+    if (layout == VBDRO_GPACKED) {
+        /* z = ceil(log2(k+1)) bits: 2^z - 1 >= k, so a DR that left the
+         * window stays inactive at the saturation value */
+        uint32_t z = 1;
+        while (((1u << z) - 1) < k)
+            z++;
+        if (Lc < 1 || Lc > s->L) {
+            free(s);
+            return NULL;
+        }
+        s->Lc = Lc;
+        s->sat = (1u << z) - 1;
+    }
     uint64_t st = hash_seed;
     uint64_t x = vbdro_splitmix64(&st);
     s->A0 = (uint32_t)x;
@@ -189,19 +212,33 @@ vbdro_sketch *vbdro_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_see
         s->now = (uint8_t *)calloc(m, 1);
     if (layout == VBDRO_GFAST)
         s->bs = (uint32_t *)calloc(m, sizeof(uint32_t));
-    if (layout == VBDRO_GSMALL)
+    if (layout >= VBDRO_GSMALL)
         s->preg = (uint8_t *)calloc(m, 1);
     if (!s->drv || !s->reg || (layout == VBDRO_SERIAL && !s->now) || (layout == VBDRO_GFAST && !s->bs) ||
-        (layout == VBDRO_GSMALL && !s->preg)) {
+        (layout >= VBDRO_GSMALL && !s->preg)) {
         free(s->drv), free(s->reg), free(s->now), free(s->bs), free(s->preg), free(s);
         return NULL;
     }
     for (uint64_t p = 0; p < m; p++)
         for (uint32_t i = 0; i <= s->L; i++)
-            s->drv[p * (s->L + 1) + i] = (uint8_t)DR_INIT; /* InitDR */
+            s->drv[p * (s->L + 1) + i] = (uint8_t)s->sat; /* InitDR */
     s->pool_hist[0] = m;
     s->t = 0;
     return s;
+}
+
+vbdro_sketch *vbdro_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout)
+{
+    if (layout == VBDRO_GPACKED)
+        return NULL;
+    return create(m, g, k, hash_seed, layout, 0);
+}
+
+/* The packed layout: the small layout's algorithms (Alg. 8, 9) on z-bit DRs
+ * and Lc recorders per BDR, LBP1 values above Lc recorded at Lc. */
+vbdro_sketch *vbdro_create_packed(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, uint32_t Lc)
+{
+    return create(m, g, k, hash_seed, VBDRO_GPACKED, Lc);
 }
 
 void vbdro_destroy(vbdro_sketch *s)
@@ -213,9 +250,9 @@ void vbdro_destroy(vbdro_sketch *s)
 
 /* DR operations of Sec. 3. */
 static void SetDR(uint8_t *dr) { *dr = 0; }
-static void SlideDR(uint8_t *dr)
+static void SlideDR(const vbdro_sketch *s, uint8_t *dr)
 {
-    if (*dr < DR_INIT)
+    if (*dr < s->sat)
         (*dr)++;
 }
 static int IsActiveDR(uint8_t dr, uint32_t k) { return dr < k; }
@@ -280,7 +317,7 @@ void vbdro_scan(vbdro_sketch *s, const uint32_t *pairs, uint64_t n)
         } else if (s->layout == VBDRO_GFAST) {
             s->bs[p] |= 1u << (r - 1);
         } else {
-            SetDR(&DRV(s, p)[r]);
+            SetDR(&DRV(s, p)[r < s->Lc ? r : s->Lc]);
         }
     }
 }
@@ -289,7 +326,7 @@ void vbdro_scan(vbdro_sketch *s, const uint32_t *pairs, uint64_t n)
 static uint32_t GetLBP1BDR(vbdro_sketch *s, uint64_t p)
 {
     uint8_t *v = DRV(s, p);
-    for (uint32_t lbp1 = s->L; lbp1 >= 1; lbp1--)
+    for (uint32_t lbp1 = s->Lc; lbp1 >= 1; lbp1--)
         if (IsActiveDR(v[lbp1], s->k))
             return lbp1;
     return 0;
@@ -301,7 +338,7 @@ static uint32_t PcsaRun(vbdro_sketch *s, uint64_t p)
 {
     uint8_t *v = DRV(s, p);
     uint32_t r = 0;
-    while (r < s->L && IsActiveDR(v[r + 1], s->k))
+    while (r < s->Lc && IsActiveDR(v[r + 1], s->k))
         r++;
     return r;
 }
@@ -314,7 +351,7 @@ void vbdro_advance(vbdro_sketch *s)
         if (s->layout == VBDRO_SERIAL) {
             /* Alg. 1 EndSliceUpdateBDR, then nowLBP1 starts the next slice at 0. */
             for (uint32_t i = 1; i <= s->L; i++)
-                SlideDR(&v[i]);
+                SlideDR(s, &v[i]);
             if (s->now[p] > 0)
                 SetDR(&v[s->now[p]]);
             s->now[p] = 0;
@@ -323,7 +360,7 @@ void vbdro_advance(vbdro_sketch *s)
             /* Alg. 6 EndSliceUpdateBDRGpu: the slice's LBP1 is the highest
              * set bit of bsLBP1; bsLBP1 is reset for the next slice. */
             for (uint32_t i = 1; i <= s->L; i++)
-                SlideDR(&v[i]);
+                SlideDR(s, &v[i]);
             uint32_t lbp1 = 0;
             for (uint32_t i = 1; i <= s->L; i++)
                 if ((s->bs[p] >> (i - 1)) & 1u)
@@ -338,7 +375,7 @@ void vbdro_advance(vbdro_sketch *s)
             s->reg[p] = (uint8_t)GetLBP1BDR(s, p);
             s->preg[p] = (uint8_t)PcsaRun(s, p);
             for (uint32_t i = 1; i <= s->L; i++)
-                SlideDR(&v[i]);
+                SlideDR(s, &v[i]);
         }
     }
     memset(s->pool_hist, 0, sizeof(s->pool_hist));
@@ -430,7 +467,7 @@ static double sum_estimate(int kind, double S, double q)
  * pool or for an unknown kind. */
 int vbdro_estimate_kind(vbdro_sketch *s, const uint32_t *hosts, uint64_t n, int kind, float *out, double *raw_es)
 {
-    if (kind != 1 && !(kind == 2 && s->layout == VBDRO_GSMALL))
+    if (kind != 1 && !(kind == 2 && s->layout >= VBDRO_GSMALL))
         return -1;
     const uint8_t *val = kind == 1 ? s->reg : s->preg;
     uint64_t pool = 0;
@@ -472,11 +509,12 @@ uint64_t vbdro_sum_lbp1(vbdro_sketch *s, uint32_t aip)
 /* Introspection for tests                                             */
 /* ------------------------------------------------------------------ */
 
-/* out[0..8] = m, g, b, L, k, layout, A0, A1, t */
+/* out[0..10] = m, g, b, L, k, layout, A0, A1, t, Lc, saturation value */
 void vbdro_params(const vbdro_sketch *s, uint64_t *out)
 {
     out[0] = s->m, out[1] = s->g, out[2] = s->b, out[3] = s->L, out[4] = s->k;
     out[5] = (uint64_t)s->layout, out[6] = s->A0, out[7] = s->A1, out[8] = s->t;
+    out[9] = s->Lc, out[10] = s->sat;
 }
 
 /* Canonical state: dr[p*L + (i-1)] = DRV[i] of BDR p; bs[p] (fast layout)

@@ -437,3 +437,42 @@ def test_loglog_pcsa_accuracy(oracle_mod):
         assert abs(rel.mean()) < 0.06, (kind, rel.mean())
         rms = float(np.sqrt(np.mean(rel ** 2)))
         assert 0.5 * sigma / np.sqrt(g) < rms < 1.6 * sigma / np.sqrt(g), (kind, rms)
+
+
+# ---- packed layout (Table 1's gsmall sizes): z-bit DRs, Lc recorders
+
+@pytest.mark.parametrize("k,Lc_off", [(1, 0), (3, 20), (4, 0), (7, 17), (60, 12), (254, 25)])
+def test_packed_layout_relates_to_small(oracle_mod, k, Lc_off):
+    """The packed layout is the small one with z = ceil(log2(k+1))-bit DRs
+    saturating at 2^z - 1 and LBP1 values above Lc recorded at Lc.  After
+    every slice of a random history: registers are min(small register, Lc);
+    DR r < Lc is min(small DR, 2^z - 1); DR Lc is the most recent of the small
+    DRs Lc..L, capped; DRs above Lc stay at 2^z - 1; the histogram follows."""
+    O = oracle_mod
+    m, g, seed = 2500, 8, 13
+    rng = np.random.default_rng(k * 31 + Lc_off)
+    small = O.Sketch(m, g, k, seed, O.GSMALL)
+    L = small.L
+    Lc = L - Lc_off if Lc_off else L
+    packed = O.Sketch(m, g, k, seed, O.GPACKED, Lc=Lc)
+    z = int(np.ceil(np.log2(k + 1)))
+    sat = (1 << z) - 1
+    assert (packed.Lc, packed.sat) == (Lc, sat) and sat >= k
+    aips = rng.integers(0, 2**32, 30, dtype=np.uint64).astype(np.uint32)
+    for t in range(k + 6):
+        n = 0 if t % 5 == 3 else 3000
+        pairs = np.stack([aips[rng.integers(0, 30, n)], rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)],
+                         1).astype(np.uint32)
+        small.scan(pairs)
+        packed.scan(pairs)
+        small.advance()
+        packed.advance()
+        a, b = small.state(), packed.state()
+        assert np.array_equal(b["reg"], np.minimum(a["reg"], Lc)), t
+        exp = np.minimum(a["dr"].astype(np.int64), sat)
+        exp[:, Lc - 1] = np.minimum(a["dr"][:, Lc - 1:].min(axis=1), sat)
+        exp[:, Lc:] = sat
+        assert np.array_equal(b["dr"], exp.astype(np.uint8)), t
+        assert np.array_equal(b["hist"], np.bincount(b["reg"], minlength=33).astype(np.uint64))
+    with pytest.raises(ValueError):
+        O.Sketch(m, g, k, seed, O.GPACKED, Lc=L + 1)
