@@ -38,12 +38,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kind, w, layout, L, n_hosts):
-    """Bytes a launch must move at minimum (per unit x units)."""
-    if kind == "scan":  # pair read + one state update (fast: 4 B word read-modify-write; small: 1 B store)
+def algorithmic_bytes(kind, w, layout, L, n_hosts, dr_bits=8):
+    """Bytes a launch must move at minimum (per unit x units).  For the packed
+    layout L is its recorder count Lc and dr_bits its DR width z."""
+    if kind == "scan":  # pair read + one state update (fast: 4 B word read-modify-write; small/packed: 1 B store)
         return w.pairs_per_slice * (16 if layout == "fast" else 9)
     if kind == "advance":  # every DR read and written, register written; fast: bsLBP1 bits read and cleared
-        per = 2 * L + 1 + (2 * L / 8 if layout == "fast" else 0)
+        per = 2 * L * dr_bits / 8 + 1 + (2 * L / 8 if layout == "fast" else 0)
         return w.m * per
     if kind == "estimate":  # g register gathers + host id + estimate
         return n_hosts * (w.g + 8)
@@ -72,14 +73,14 @@ def traffic_from_counters(kernel_name, n_launch_units):
     return (k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"]) * 1024.0
 
 
-def cpu_baseline(w, layout, slice0, hosts_sample, n_active):
+def cpu_baseline(w, layout, slice0, hosts_sample, n_active, Lc=0):
     """Time the CPU oracle (single thread, as it stands) on a bounded sample."""
     import numpy as np
     from oracle import oracle
-    code = oracle.GFAST if layout == "fast" else oracle.GSMALL
+    code = {"fast": oracle.GFAST, "small": oracle.GSMALL, "packed": oracle.GPACKED}[layout]
     S = min(len(slice0), 1 << 22)
     t0 = time.perf_counter()
-    osk = oracle.Sketch(w.m, w.g, w.k, w.seed, code)
+    osk = oracle.Sketch(w.m, w.g, w.k, w.seed, code, Lc=Lc)
     t_create = time.perf_counter() - t0
     t0 = time.perf_counter()
     osk.scan(slice0[:S])
@@ -228,7 +229,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--layout", default="small", choices=["small", "fast"])
+    ap.add_argument("--layout", default="small", choices=["small", "fast", "packed"])
+    ap.add_argument("--packed-lc", type=int, default=16,
+                    help="recorders per BDR of the packed layout (LBP1 values above it are recorded at it)")
     ap.add_argument("--workload", default="line_rate", choices=["line_rate", "tiny", "batched", "stress"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -278,8 +281,9 @@ def main():
         log(f"slice {t}: generated and copied ({time.time() - t0:.1f}s), {len(act)} active hosts")
     outs = [torch.empty(n, dtype=torch.float32, device=dev) for n in n_active]
 
-    sk = vbdr.Sketch(w.m, w.g, w.k, w.seed, args.layout)
-    L = sk.L
+    Lc = args.packed_lc if args.layout == "packed" else 0
+    sk = vbdr.Sketch(w.m, w.g, w.k, w.seed, args.layout, Lc=Lc)
+    L = sk.Lc
 
     def step(i):
         sk.scan_slice(slices_dev[i])
@@ -320,11 +324,12 @@ def main():
 
     dom = max(avg, key=avg.get)
     units = float(np.mean(timed_active))
-    alg = algorithmic_bytes(dom, w, args.layout, L, units)
+    alg = algorithmic_bytes(dom, w, args.layout, L, units, sk.dr_bits)
     achieved = alg / (avg[dom] * 1e-3) / 1e9
     info = sk.info()
+    adv = "k_advance_packed" if args.layout == "packed" else "k_advance_defer" if info.scan_deferred else "k_advance"
     kernels = {"scan": "k_scan_defer" if info.scan_deferred else "k_scan",
-               "advance": ("k_advance_defer" if info.scan_deferred else "k_advance") + " + k_hist_reset",
+               "advance": adv + " + k_hist_reset",
                "estimate": ("k_estimate_part + k_estimate_final" if info.est_parts > 1 else "k_estimate")}
     traffic = traffic_from_counters(f"{dom}:{args.layout}:{w.name}", units)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -341,7 +346,9 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": w.name, "pairs_per_slice": w.pairs_per_slice, "hosts": w.hosts, "m": w.m,
-                   "g": w.g, "k": w.k, "layout": args.layout, "active_hosts_per_step": int(units)},
+                   "g": w.g, "k": w.k, "layout": args.layout, "active_hosts_per_step": int(units),
+                   **({"Lc": sk.Lc, "dr_bits": sk.dr_bits} if args.layout == "packed" else {}),
+                   "state_bytes": int(info.state_bytes)},
         "hosts_per_s": float(np.sum(timed_active) / (np.sum(kms["estimate"]) * 1e-3)),
         "scan_pairs_per_s": w.pairs_per_slice / (avg["scan"] * 1e-3),
         "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
@@ -363,7 +370,7 @@ def main():
         act_last = hosts_all[np.nonzero(np.logical_or.reduce(window))[0]]
         sample = rng.choice(act_last, size=min(2048, len(act_last)), replace=False)
         log("timing the CPU oracle on a sample")
-        res["cpu_baseline"] = cpu_baseline(w, args.layout, slice0, sample, int(units))
+        res["cpu_baseline"] = cpu_baseline(w, args.layout, slice0, sample, int(units), Lc)
     print(json.dumps(res), flush=True)
 
 

@@ -16,15 +16,22 @@
  * ->  vbdr_estimate().  Scans of one slice may be split over any number of
  * calls; their result does not depend on pair order or on repeated pairs.
  *
- * Two layouts (Sec. 4.2, Table 1):
+ * Three layouts (Sec. 4.2, Table 1):
  *   VBDR_LAYOUT_FAST  -- the scan records each pair's LBP1 as one bit of a
  *                        per-slice bit string (bsLBP1, Alg. 7) with an
  *                        atomic OR; the advance folds the highest bit into
  *                        the DRs (Alg. 6).  More memory, fastest scan.
  *   VBDR_LAYOUT_SMALL -- the scan zeroes the DR of the pair's LBP1 directly
  *                        (Alg. 9, a plain byte store); the advance slides
- *                        every DR (Alg. 8).  Least memory.
- * Both give identical registers and estimates.
+ *                        every DR (Alg. 8).
+ *   VBDR_LAYOUT_PACKED -- the small layout with Table 1's recorder sizes:
+ *                        z = ceil(log2(k+1))-bit DRs (bit-sliced, saturating
+ *                        at 2^z - 1 >= k) and Lc recorders per BDR, LBP1
+ *                        values above Lc recorded at Lc, so its registers
+ *                        are min(register, Lc).  Least memory.  Pools of at
+ *                        most 2^26 BDRs; scans always go through records.
+ * The fast and small layouts give identical registers and estimates; the
+ * packed layout gives identical ones when Lc = L = 33 - b.
  *
  * Hashing (the paper leaves H(x, N, A) open): H(x, N, A) is
  * MurmurHash3_x86_32 of the 4-byte little-endian x with seed A, mapped to
@@ -59,7 +66,7 @@ extern "C" {
 
 typedef struct vbdr_sketch vbdr_sketch;
 
-enum vbdr_layout { VBDR_LAYOUT_FAST = 0, VBDR_LAYOUT_SMALL = 1 };
+enum vbdr_layout { VBDR_LAYOUT_FAST = 0, VBDR_LAYOUT_SMALL = 1, VBDR_LAYOUT_PACKED = 2 };
 
 enum vbdr_status {
     VBDR_OK = 0,
@@ -78,6 +85,8 @@ typedef struct vbdr_info {
     uint64_t state_bytes; /* device bytes held by the sketch */
     int32_t est_parts;    /* pool ranges of the estimate's XCD-partitioned gathers (1 = direct) */
     int32_t scan_deferred; /* 1 when scans defer their updates to the advance (scan_defer = 1) */
+    uint32_t Lc;          /* recorders per BDR (L except for the packed layout) */
+    uint32_t dr_bits;     /* bits per DR: 8, or z for the packed layout */
 } vbdr_info;
 
 /*
@@ -90,6 +99,9 @@ typedef struct vbdr_info {
  */
 int vbdr_sketch_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, vbdr_sketch **out);
 int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout,
+                              vbdr_sketch **out);
+/* The packed layout with Lc recorders per BDR (1 <= Lc <= 33 - b), m <= 2^26. */
+int vbdr_sketch_create_packed(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, uint32_t Lc,
                               vbdr_sketch **out);
 
 /* Free a sketch and its device memory after synchronising the device.  NULL is a no-op. */
@@ -255,6 +267,8 @@ int vbdr_sketch_get_tuning(const vbdr_sketch *sk, vbdr_tuning *tuning);
  *             (all zero for the small layout);
  *   reg_host  m bytes, register of BDR p for the last closed window;
  *   hist_host 33 uint64, histogram of reg over the pool.
+ * Packed layout: DR values are 0..2^z - 1 and recorders above Lc read
+ * 2^z - 1 (they are never set).
  */
 int vbdr_export_state(vbdr_sketch *sk, uint8_t *dr_host, uint32_t *bs_host, uint8_t *reg_host,
                       uint64_t *hist_host, void *stream);
@@ -263,7 +277,8 @@ int vbdr_export_state(vbdr_sketch *sk, uint8_t *dr_host, uint32_t *bs_host, uint
  * Load a canonical state (same layout as vbdr_export_state; dr_host, reg_host
  * and hist_host required, bs_host may be NULL = all zero) and the slice
  * counter t into a sketch with the same parameters, for checkpoint/resume.
- * Synchronous.
+ * Packed layout: DR values are capped at 2^z - 1 (every value >= k is
+ * inactive alike) and recorders above Lc are ignored.  Synchronous.
  */
 int vbdr_import_state(vbdr_sketch *sk, const uint8_t *dr_host, const uint32_t *bs_host, const uint8_t *reg_host,
                       const uint64_t *hist_host, uint64_t t, void *stream);

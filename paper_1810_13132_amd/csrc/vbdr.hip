@@ -371,14 +371,20 @@ __device__ void block_exclusive_scan(const uint32_t* a, uint32_t* out, uint32_t 
   __syncthreads();
 }
 
+// Apply one record to the pool: fast layout, set the bsLBP1 bit; small
+// layout, SetDR; packed layout (bits != nullptr), clear the DR's z bits.
 template <bool FAST>
 __device__ __forceinline__ void apply_record(uint32_t rec, uint8_t* dr, uint64_t mstride, uint32_t* seen,
-                                             uint64_t wstride) {
+                                             uint64_t wstride, uint32_t* bits, uint32_t z) {
   const uint32_t pidx = rec >> 5, plane = rec & 31u;
-  if constexpr (FAST)
+  if constexpr (FAST) {
     atomicOr(seen + (uint64_t)plane * wstride + (pidx >> 5), 1u << (pidx & 31));
-  else
+  } else if (bits) {
+    for (uint32_t b = 0; b < z; ++b)
+      atomicAnd(bits + ((uint64_t)plane * z + b) * wstride + (pidx >> 5), ~(1u << (pidx & 31)));
+  } else {
     dr[(uint64_t)plane * mstride + pidx] = 0;
+  }
 }
 
 // LDS: cnt[tiles], start[tiles], sorted[kDeferChunk], then s1 if staged.
@@ -389,7 +395,8 @@ __global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restr
                                                             uint32_t cap, uint32_t* __restrict__ recs,
                                                             unsigned long long* __restrict__ fill,
                                                             uint8_t* __restrict__ dr, uint64_t mstride,
-                                                            uint32_t* __restrict__ seen, uint64_t wstride) {
+                                                            uint32_t* __restrict__ seen, uint64_t wstride,
+                                                            uint32_t Lc, uint32_t* __restrict__ bits, uint32_t z) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t wsum[kDeferBlock / 64];
   uint32_t* cnt = lds;
@@ -423,7 +430,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restr
           uint32_t vidx, rho;
           bip_map(p[v].y, A1, b, vidx, rho);
           const uint32_t pidx = reduce_m(mm3(p[v].x, s1[vidx]), m);
-          rec[u] = (pidx << 5) | (rho - 1);
+          rec[u] = (pidx << 5) | ((rho < Lc ? rho : Lc) - 1);  // LBP1 above Lc is recorded at Lc
           r = atomicAdd(&cnt[pidx / kDeferTile], 1u);
         }
         if (u & 1) rank[u >> 1] |= r << 16;
@@ -455,7 +462,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restr
       if (pos < cap) {
         recs[(uint64_t)t * cap + pos] = r;
       } else {
-        apply_record<FAST>(r, dr, mstride, seen, wstride);
+        apply_record<FAST>(r, dr, mstride, seen, wstride, bits, z);
         direct = true;
       }
     }
@@ -520,17 +527,110 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
   }
 }
 
+// Packed layout (Table 1's recorder sizes): DR r of BDR p is a z-bit counter
+// stored bit-sliced, bit b in bit-plane (r - 1) z + b at word p / 32, so one
+// 32-bit word holds one bit of 32 BDRs and every DR operation is a handful of
+// bitwise operations on z words.  One workgroup per tile, as k_advance_defer:
+// the tile's records become per-plane bit words in LDS, then thread t sweeps
+// word t of every plane from LBP1 Lc down to 1: SetDR of the slice's records
+// (clear z bits), the window read (value < k, compared from the top bit down;
+// Alg. 2 takes the highest active LBP1), SlideDR (saturating increment by a
+// ripple carry; all-ones saturates).
+__global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __restrict__ bits, uint64_t wstride,
+                                                                uint32_t z, uint32_t Lc, uint32_t k,
+                                                                uint8_t* __restrict__ reg, uint8_t* __restrict__ reg4,
+                                                                uint64_t m, unsigned long long* __restrict__ hist,
+                                                                const uint32_t* __restrict__ recs,
+                                                                unsigned long long* __restrict__ fill, uint32_t cap) {
+  extern __shared__ uint32_t pm[];
+  __shared__ uint32_t lh[kDeferBlock / 64][kBins];
+  const uint32_t tile = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint32_t i = threadIdx.x; i < Lc * kDeferWords; i += kDeferBlock) pm[i] = 0;
+  if (lane < kBins) lh[wave][lane] = 0;
+  const unsigned long long f = fill[tile];
+  const uint32_t n = f < cap ? (uint32_t)f : cap;
+  __syncthreads();
+  if (threadIdx.x == 0) fill[tile] = 0;  // every thread has read it
+  const uint32_t* r = recs + (uint64_t)tile * cap;
+  for (uint32_t j = threadIdx.x; j < n; j += kDeferBlock) {
+    const uint32_t rec = r[j];
+    const uint32_t p = (rec >> 5) & (kDeferTile - 1);
+    atomicOr(&pm[(rec & 31u) * kDeferWords + (p >> 5)], 1u << (p & 31));
+  }
+  __syncthreads();
+  const uint64_t w = (uint64_t)tile * kDeferWords + threadIdx.x;
+  if (w < wstride) {
+    uint32_t R[8] = {0, 0, 0, 0, 0, 0, 0, 0}, done = 0;
+    for (int rr = (int)Lc; rr >= 1; --rr) {
+      const uint64_t pb = (uint64_t)(rr - 1) * z;
+      uint32_t d[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) d[b] = (uint32_t)b < z ? bits[(pb + b) * wstride + w] : 0u;
+      const uint32_t set = pm[(uint32_t)(rr - 1) * kDeferWords + threadIdx.x];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) d[b] &= ~set;  // SetDR (Alg. 9) of the slice
+      uint32_t lt = 0, eq = ~0u;                   // IsActiveDR: value < k
+#pragma unroll
+      for (int b = 7; b >= 0; --b) {
+        if ((uint32_t)b >= z) continue;
+        if ((k >> b) & 1u) {
+          lt |= eq & ~d[b];
+          eq &= d[b];
+        } else {
+          eq &= ~d[b];
+        }
+      }
+      const uint32_t newly = lt & ~done;  // Alg. 2: the highest active LBP1
+      done |= lt;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) R[q] |= swar_nibble_to_bytes((newly >> (4 * q)) & 0xFu) & ((uint32_t)rr * 0x01010101u);
+      uint32_t full = ~0u;  // SlideDR: saturating increment
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        if ((uint32_t)b < z) full &= d[b];
+      uint32_t carry = ~full;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        if ((uint32_t)b >= z) continue;
+        const uint32_t t = d[b] & carry;
+        d[b] ^= carry;
+        carry = t;
+        bits[(pb + b) * wstride + w] = d[b];
+      }
+    }
+    const uint64_t base = w * 32;
+    *reinterpret_cast<u32x4*>(reg + base) = u32x4{R[0], R[1], R[2], R[3]};
+    *reinterpret_cast<u32x4*>(reg + base + 16) = u32x4{R[4], R[5], R[6], R[7]};
+    u32x4 nib;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nib[q] = swar_pack_nibbles(R[2 * q]) | (swar_pack_nibbles(R[2 * q + 1]) << 16);
+    *reinterpret_cast<u32x4*>(reg4 + base / 2) = nib;
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+      if (base + j < m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBins) {
+    uint32_t c = 0;
+    for (int v = 0; v < kDeferBlock / 64; ++v) c += lh[v][threadIdx.x];
+    if (c) atomicAdd(hist + threadIdx.x, (unsigned long long)c);
+  }
+}
+
 // Apply the pending records of every tile to the pool (before a state export
 // or a switch to direct scans): one workgroup per tile.
 template <bool FAST>
 __global__ __launch_bounds__(256) void k_defer_flush(const uint32_t* __restrict__ recs,
                                                      unsigned long long* __restrict__ fill, uint32_t cap,
                                                      uint32_t tiles, uint8_t* __restrict__ dr, uint64_t mstride,
-                                                     uint32_t* __restrict__ seen, uint64_t wstride) {
+                                                     uint32_t* __restrict__ seen, uint64_t wstride,
+                                                     uint32_t* __restrict__ bits, uint32_t z) {
   const uint32_t tile = blockIdx.x;
   const unsigned long long f = fill[tile];
   const uint32_t n = f < cap ? (uint32_t)f : cap;
-  for (uint32_t j = threadIdx.x; j < n; j += 256) apply_record<FAST>(recs[(uint64_t)tile * cap + j], dr, mstride, seen, wstride);
+  for (uint32_t j = threadIdx.x; j < n; j += 256)
+    apply_record<FAST>(recs[(uint64_t)tile * cap + j], dr, mstride, seen, wstride, bits, z);
   __syncthreads();
   if (threadIdx.x == 0) {
     fill[tile] = 0;
@@ -1038,9 +1138,15 @@ uint64_t splitmix64_first(uint64_t state) {
 
 int init_state(vbdr_sketch* sk, hipStream_t st) {
   const uint32_t fill_grid = grid_cap(sk, (sk->L * sk->mstride / 4 + 255) / 256, 32);
-  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, reinterpret_cast<uint32_t*>(sk->dr),
-                     (uint64_t)sk->L * sk->mstride / 4, 0xFFFFFFFFu);  // InitDR: 255 in every byte
-  VBDR_LAUNCHED("k_fill_u32(dr)");
+  if (sk->dr) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, reinterpret_cast<uint32_t*>(sk->dr),
+                       (uint64_t)sk->L * sk->mstride / 4, 0xFFFFFFFFu);  // InitDR: 255 in every byte
+    VBDR_LAUNCHED("k_fill_u32(dr)");
+  } else {
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, sk->bits,
+                       (uint64_t)sk->Lc * sk->z * sk->wstride, 0xFFFFFFFFu);  // InitDR: 2^z - 1 in every DR
+    VBDR_LAUNCHED("k_fill_u32(bits)");
+  }
   hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, reinterpret_cast<uint32_t*>(sk->reg),
                      sk->mstride / 4, 0u);
   VBDR_LAUNCHED("k_fill_u32(reg)");
@@ -1067,7 +1173,7 @@ int defer_flush(vbdr_sketch* sk, hipStream_t st) {
   if (!sk->def_rec) return VBDR_OK;
   auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_defer_flush<true> : k_defer_flush<false>;
   hipLaunchKernelGGL(kern, dim3(sk->def_tiles), dim3(256), 0, st, sk->def_rec, sk->def_fill, sk->def_cap,
-                     sk->def_tiles, sk->dr, sk->mstride, sk->seen, sk->wstride);
+                     sk->def_tiles, sk->dr, sk->mstride, sk->seen, sk->wstride, sk->bits, sk->z);
   VBDR_LAUNCHED("k_defer_flush");
   return VBDR_OK;
 }
@@ -1120,13 +1226,22 @@ namespace {
 // sorted chunk (s1 goes to LDS only if it fits beside them).
 size_t defer_scan_lds(uint32_t tiles) { return (size_t)(2 * tiles + kDeferChunk) * 4; }
 
-int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, bool lean, vbdr_sketch** out) {
+int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, bool lean, uint32_t Lc,
+                  vbdr_sketch** out) {
   if (!out) return vbdr_fail(VBDR_EINVAL, "out is NULL");
   *out = nullptr;
   if (g < 2 || g > 65536u || (g & (g - 1))) return vbdr_fail(VBDR_EINVAL, "g=%u must be a power of two in [2, 65536]", g);
   if (m <= g || m >= (1ull << 32)) return vbdr_fail(VBDR_EINVAL, "m=%llu must satisfy g < m < 2^32", (unsigned long long)m);
   if (k < 1 || k > 254) return vbdr_fail(VBDR_EINVAL, "k=%u must be in [1, 254]", k);
-  if (layout != VBDR_LAYOUT_FAST && layout != VBDR_LAYOUT_SMALL) return vbdr_fail(VBDR_EINVAL, "unknown layout %d", layout);
+  if (layout != VBDR_LAYOUT_FAST && layout != VBDR_LAYOUT_SMALL && layout != VBDR_LAYOUT_PACKED)
+    return vbdr_fail(VBDR_EINVAL, "unknown layout %d", layout);
+  uint32_t b0 = 0;
+  while ((1u << b0) < g) b0++;
+  if (layout == VBDR_LAYOUT_PACKED) {
+    if (lean) return vbdr_fail(VBDR_EINVAL, "the packed layout needs deferred scans");
+    if (Lc < 1 || Lc > 33 - b0) return vbdr_fail(VBDR_EINVAL, "Lc=%u must be in [1, %u]", Lc, 33 - b0);
+    if (m > kPackedMaxM) return vbdr_fail(VBDR_EINVAL, "the packed layout holds at most 2^26 BDRs");
+  }
   vbdr_sketch* sk = new (std::nothrow) vbdr_sketch();
   if (!sk) return vbdr_fail(VBDR_ENOMEM, "host allocation failed");
   std::memset(sk, 0, sizeof(*sk));
@@ -1150,23 +1265,35 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
     sk->A0 = (uint32_t)x, sk->A1 = (uint32_t)(x >> 32);
     sk->mstride = (m + kPad - 1) / kPad * kPad;
     sk->wstride = sk->mstride / 32;
-    const uint64_t dr_bytes = (uint64_t)sk->L * sk->mstride;
+    sk->Lc = sk->L, sk->z = 8;
+    if (layout == VBDR_LAYOUT_PACKED) {
+      sk->Lc = Lc;
+      sk->z = 1;
+      while (((1u << sk->z) - 1) < k) sk->z++;  // 2^z - 1 >= k: a DR that left the window stays inactive
+    }
+    const uint64_t dr_bytes = layout == VBDR_LAYOUT_PACKED ? 0 : (uint64_t)sk->L * sk->mstride;
+    const uint64_t bits_bytes = layout == VBDR_LAYOUT_PACKED ? (uint64_t)sk->Lc * sk->z * sk->wstride * 4 : 0;
     const uint64_t seen_bytes = layout == VBDR_LAYOUT_FAST ? (uint64_t)sk->L * sk->wstride * 4 : 0;
     // The partitioned estimate pays off once the registers outgrow one XCD's L2.
     const int xcds = sk->n_cu / (int)kCusPerXcd;
     sk->parts = (m >= kPartMinM && xcds >= 8) ? 8 : (m >= kPartMinM && xcds >= 4) ? 4 : 1;
     const uint64_t part_bytes = sk->parts > 1 ? (uint64_t)sk->parts * kPartChunk * (8 + 4) : 0;
     // the binned scan needs 8 XCDs and pidx < 2^27 to pack its records
-    const uint64_t bin_bytes = (!lean && sk->parts == 8 && m <= kBinMaxM) ? 8ull * kBinCap * 4 : 0;
+    const uint64_t bin_bytes =
+        (!lean && layout != VBDR_LAYOUT_PACKED && sk->parts == 8 && m <= kBinMaxM) ? 8ull * kBinCap * 4 : 0;
     // deferred scan records: kDeferSlots per BDR, for 2^22 <= m and 2^26 tile-rounded BDRs at most
     uint64_t def_bytes = 0;
-    if (!lean && m >= kPartMinM && sk->mstride <= (1ull << 26)) {
+    if (!lean && (m >= kPartMinM || layout == VBDR_LAYOUT_PACKED) && sk->mstride <= (1ull << 26)) {
       const uint32_t tiles = (uint32_t)((sk->mstride + kDeferTile - 1) / kDeferTile);
       if (defer_scan_lds(tiles) + 1024 <= (size_t)lds_max && (size_t)(33 - 1) * kDeferWords * 4 + 4096 <= (size_t)lds_max) {
         sk->def_tiles = tiles;
         sk->def_cap = kDeferSlots * kDeferTile;
         def_bytes = (uint64_t)tiles * sk->def_cap * 4 + (uint64_t)(tiles + 1) * 8;
       }
+    }
+    if (layout == VBDR_LAYOUT_PACKED && !def_bytes) {
+      rc = vbdr_fail(VBDR_EINVAL, "the packed layout needs %zu bytes of LDS per workgroup", defer_scan_lds(1));
+      break;
     }
     // binned estimate: runs of g/8 + g/16 + 32 slots per (range, host), <= 512 MiB of runs
     uint64_t est_bytes = 0;
@@ -1177,7 +1304,8 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
       sk->est_hc = (uint32_t)(hc / 64 * 64);
       est_bytes = 8ull * sk->est_hc * sk->est_cap * 4 + 8ull * sk->est_hc * 4 + (uint64_t)sk->est_hc * 12;
     }
-    if (hipMalloc(&sk->dr, dr_bytes) != hipSuccess || hipMalloc(&sk->reg, sk->mstride) != hipSuccess ||
+    if ((dr_bytes && hipMalloc(&sk->dr, dr_bytes) != hipSuccess) ||
+        (bits_bytes && hipMalloc(&sk->bits, bits_bytes) != hipSuccess) || hipMalloc(&sk->reg, sk->mstride) != hipSuccess ||
         hipMalloc(&sk->reg4, sk->mstride / 2) != hipSuccess ||
         hipMalloc(&sk->hist, 64 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&sk->s1, (uint64_t)g * 4) != hipSuccess ||
@@ -1186,12 +1314,7 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
         (part_bytes && hipMalloc(&sk->part_v, (uint64_t)sk->parts * kPartChunk * 4) != hipSuccess) ||
         hipMalloc(&sk->hist_ws, (uint64_t)sk->parts * kLearnChunk * kBins * 4) != hipSuccess ||
         hipMalloc(&sk->est_ws, (uint64_t)kLearnChunk * 4) != hipSuccess ||
-        (bin_bytes && hipMalloc(&sk->bins, bin_bytes) != hipSuccess) ||
-        (bin_bytes && hipMalloc(&sk->bin_fill, 64) != hipSuccess) ||
-        (est_bytes && hipMalloc(&sk->est_slots, 8ull * sk->est_hc * sk->est_cap * 4) != hipSuccess) ||
-        (est_bytes && hipMalloc(&sk->est_cnt, 8ull * sk->est_hc * 4) != hipSuccess) ||
-        (est_bytes && hipMalloc(&sk->ovf_u, (uint64_t)sk->est_hc * 8) != hipSuccess) ||
-        (est_bytes && hipMalloc(&sk->ovf_v, (uint64_t)sk->est_hc * 4) != hipSuccess) ||
+
         (def_bytes && hipMalloc(&sk->def_rec, (uint64_t)sk->def_tiles * sk->def_cap * 4) != hipSuccess) ||
         (def_bytes && hipMalloc(&sk->def_fill, (uint64_t)(sk->def_tiles + 1) * 8) != hipSuccess)) {
       (void)hipGetLastError();
@@ -1199,9 +1322,10 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
                 (unsigned long long)(dr_bytes + seen_bytes + sk->mstride * 3 / 2 + part_bytes));
       break;
     }
-    sk->bytes = dr_bytes + seen_bytes + sk->mstride * 3 / 2 + 64 * sizeof(unsigned long long) + (uint64_t)g * 4 +
-                part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + bin_bytes + est_bytes +
-                def_bytes;
+    sk->bytes = dr_bytes + bits_bytes + seen_bytes + sk->mstride * 3 / 2 + 64 * sizeof(unsigned long long) + (uint64_t)g * 4 +
+                part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + def_bytes;
+    sk->bin_ok = bin_bytes != 0;  // allocated when the variant is selected (vbdr_sketch_set_tuning)
+    sk->est_ok = est_bytes != 0;
     hipStream_t st = nullptr;
     if ((rc = init_state(sk, st)) != VBDR_OK) break;
     hipLaunchKernelGGL(k_seeds, dim3((g + 255) / 256), dim3(256), 0, st, sk->s1, g, sk->A0);
@@ -1221,13 +1345,19 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
 }  // namespace
 
 int vbdr_sketch_create_lean(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out) {
-  return create_sketch(m, g, k, hash_seed, layout, true, out);
+  if (layout == VBDR_LAYOUT_PACKED) return vbdr_fail(VBDR_EINVAL, "batches hold fast and small layouts only");
+  return create_sketch(m, g, k, hash_seed, layout, true, 0, out);
 }
 
 extern "C" {
 
 int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out) {
-  return create_sketch(m, g, k, hash_seed, layout, false, out);
+  if (layout == VBDR_LAYOUT_PACKED) return vbdr_fail(VBDR_EINVAL, "create a packed sketch with vbdr_sketch_create_packed");
+  return create_sketch(m, g, k, hash_seed, layout, false, 0, out);
+}
+
+int vbdr_sketch_create_packed(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, uint32_t Lc, vbdr_sketch** out) {
+  return create_sketch(m, g, k, hash_seed, VBDR_LAYOUT_PACKED, false, Lc, out);
 }
 
 int vbdr_sketch_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, vbdr_sketch** out) {
@@ -1241,6 +1371,7 @@ void vbdr_sketch_destroy(vbdr_sketch* sk) {
   if (prev != sk->device) (void)hipSetDevice(sk->device);
   (void)hipDeviceSynchronize();
   if (sk->dr) (void)hipFree(sk->dr);
+  if (sk->bits) (void)hipFree(sk->bits);
   if (sk->seen) (void)hipFree(sk->seen);
   if (sk->reg) (void)hipFree(sk->reg);
   if (sk->hist) (void)hipFree(sk->hist);
@@ -1274,6 +1405,8 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
   if (tuning->scan_blocks_per_cu > 64 || tuning->est_blocks_per_cu > 64)
     return vbdr_fail(VBDR_EINVAL, "blocks per CU must be at most 64");
   if (tuning->scan_defer < 0 || tuning->scan_defer > 2) return vbdr_fail(VBDR_EINVAL, "scan_defer must be 0, 1 or 2");
+  if (sk->layout == VBDR_LAYOUT_PACKED && tuning->scan_defer == 2)
+    return vbdr_fail(VBDR_EINVAL, "the packed layout always defers its scans");
   const int old_defer = sk->tune.scan_defer;
   sk->tune = default_tuning(sk->layout);
   if (tuning->scan_test_first) sk->tune.scan_test_first = tuning->scan_test_first;
@@ -1285,6 +1418,29 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
   if (tuning->est_bin_hosts) sk->tune.est_bin_hosts = tuning->est_bin_hosts;
   if (tuning->est_bin_cap) sk->tune.est_bin_cap = tuning->est_bin_cap;
   if (tuning->scan_defer) sk->tune.scan_defer = tuning->scan_defer;
+  // workspaces of the binned variants, on first selection
+  if (sk->tune.scan_binned == 1 && sk->bin_ok && !sk->bins) {
+    if (hipMalloc(&sk->bins, 8ull * kBinCap * 4) != hipSuccess || hipMalloc(&sk->bin_fill, 64) != hipSuccess) {
+      (void)hipGetLastError();
+      if (sk->bins) (void)hipFree(sk->bins);
+      sk->bins = nullptr;
+      return vbdr_fail(VBDR_ENOMEM, "allocation of the binned-scan workspace failed");
+    }
+    sk->bytes += 8ull * kBinCap * 4 + 64;
+  }
+  if (sk->tune.est_binned == 1 && sk->est_ok && !sk->est_slots) {
+    const uint64_t slots = 8ull * sk->est_hc * sk->est_cap * 4, cnt = 8ull * sk->est_hc * 4;
+    if (hipMalloc(&sk->est_slots, slots) != hipSuccess || hipMalloc(&sk->est_cnt, cnt) != hipSuccess ||
+        hipMalloc(&sk->ovf_u, (uint64_t)sk->est_hc * 8) != hipSuccess ||
+        hipMalloc(&sk->ovf_v, (uint64_t)sk->est_hc * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      for (void* q : {(void*)sk->est_slots, (void*)sk->est_cnt, (void*)sk->ovf_u, (void*)sk->ovf_v})
+        if (q) (void)hipFree(q);
+      sk->est_slots = nullptr, sk->est_cnt = nullptr, sk->ovf_u = nullptr, sk->ovf_v = nullptr;
+      return vbdr_fail(VBDR_ENOMEM, "allocation of the binned-estimate workspace failed");
+    }
+    sk->bytes += slots + cnt + (uint64_t)sk->est_hc * 12;
+  }
   if (sk->def_rec && sk->tune.scan_defer != old_defer) {
     // pending records go to the pool; the bsLBP1 planes may now hold bits
     if (int rc = vbdr_check_device(sk)) return rc;
@@ -1309,7 +1465,9 @@ int vbdr_sketch_info(const vbdr_sketch* sk, vbdr_info* out) {
   out->layout = sk->layout, out->A0 = sk->A0, out->A1 = sk->A1, out->t = sk->t;
   out->state_bytes = sk->bytes;
   out->est_parts = sk->parts;
-  out->scan_deferred = sk->def_rec && sk->tune.scan_defer == 1;
+  out->scan_deferred = sk->def_rec && (sk->tune.scan_defer == 1 || sk->layout == VBDR_LAYOUT_PACKED);
+  out->Lc = sk->Lc;
+  out->dr_bits = sk->z;
   return VBDR_OK;
 }
 
@@ -1328,7 +1486,7 @@ int vbdr_scan_slice(vbdr_sketch* sk, const uint32_t* pairs_dev, uint64_t n, void
   const u32x2* p = reinterpret_cast<const u32x2*>(pairs_dev);
   const uint32_t m32 = (uint32_t)sk->m;
   const bool test = sk->tune.scan_test_first == 1;
-  if (sk->def_rec && sk->tune.scan_defer == 1) {
+  if (sk->def_rec && (sk->tune.scan_defer == 1 || sk->layout == VBDR_LAYOUT_PACKED)) {
     const size_t base_lds = defer_scan_lds(sk->def_tiles);
     int lds_max = 0;
     VBDR_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, sk->device));
@@ -1337,7 +1495,7 @@ int vbdr_scan_slice(vbdr_sketch* sk, const uint32_t* pairs_dev, uint64_t n, void
     auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_scan_defer<true> : k_scan_defer<false>;
     hipLaunchKernelGGL(kern, dim3(dgrid), dim3(kDeferBlock), base_lds + (stage_s1 ? (size_t)sk->g * 4 : 0), st, p, n,
                        sk->s1, sk->g, stage_s1, sk->b, sk->A1, m32, sk->def_tiles, sk->def_cap, sk->def_rec,
-                       sk->def_fill, sk->dr, sk->mstride, sk->seen, sk->wstride);
+                       sk->def_fill, sk->dr, sk->mstride, sk->seen, sk->wstride, sk->Lc, sk->bits, sk->z);
     VBDR_LAUNCHED("k_scan_defer");
     return VBDR_OK;
   }
@@ -1388,6 +1546,14 @@ int vbdr_advance_slice(vbdr_sketch* sk, void* stream) {
   hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(64), 0, st, sk->hist, 0ull, sk->psum);
   VBDR_LAUNCHED("k_hist_reset");
   if (sk->preg) sk->pcsa_valid = true;  // written by the launch below
+  if (sk->layout == VBDR_LAYOUT_PACKED) {
+    hipLaunchKernelGGL(k_advance_packed, dim3(sk->def_tiles), dim3(kDeferBlock), (size_t)sk->Lc * kDeferWords * 4, st,
+                       sk->bits, sk->wstride, sk->z, sk->Lc, sk->k, sk->reg, sk->reg4, sk->m, sk->hist, sk->def_rec,
+                       sk->def_fill, sk->def_cap);
+    VBDR_LAUNCHED("k_advance_packed");
+    sk->t++;
+    return VBDR_OK;
+  }
   if (sk->def_rec && sk->tune.scan_defer == 1) {
     auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_advance_defer<true> : k_advance_defer<false>;
     hipLaunchKernelGGL(kern, dim3(sk->def_tiles), dim3(kDeferBlock), (size_t)sk->L * kDeferWords * 4, st, sk->dr,
@@ -1617,11 +1783,26 @@ int vbdr_export_state(vbdr_sketch* sk, uint8_t* dr_host, uint32_t* bs_host, uint
   if (int rc = defer_flush(sk, st)) return rc;  // the open slice's deferred records join the state
   VBDR_HIP(hipStreamSynchronize(st));
   const uint64_t m = sk->m, L = sk->L;
-  if (dr_host) {
+  if (dr_host && sk->dr) {
     std::vector<uint8_t> plane(m);
     for (uint64_t i = 0; i < L; ++i) {
       VBDR_HIP(hipMemcpy(plane.data(), sk->dr + i * sk->mstride, m, hipMemcpyDeviceToHost));
       for (uint64_t p = 0; p < m; ++p) dr_host[p * L + i] = plane[p];
+    }
+  } else if (dr_host) {  // packed: z bit-planes per recorder, recorders above Lc never set
+    const uint8_t sat = (uint8_t)((1u << sk->z) - 1);
+    std::vector<uint32_t> bp((uint64_t)sk->z * sk->wstride);
+    for (uint64_t i = 0; i < L; ++i) {
+      if (i >= sk->Lc) {
+        for (uint64_t p = 0; p < m; ++p) dr_host[p * L + i] = sat;
+        continue;
+      }
+      VBDR_HIP(hipMemcpy(bp.data(), sk->bits + i * sk->z * sk->wstride, bp.size() * 4, hipMemcpyDeviceToHost));
+      for (uint64_t p = 0; p < m; ++p) {
+        uint32_t v = 0;
+        for (uint32_t b = 0; b < sk->z; ++b) v |= ((bp[b * sk->wstride + (p >> 5)] >> (p & 31)) & 1u) << b;
+        dr_host[p * L + i] = (uint8_t)v;
+      }
     }
   }
   if (bs_host) {
@@ -1652,18 +1833,31 @@ int vbdr_import_state(vbdr_sketch* sk, const uint8_t* dr_host, const uint32_t* b
   if (total != sk->m) return vbdr_fail(VBDR_EINVAL, "histogram does not sum to m");
   const uint64_t m = sk->m, L = sk->L;
   for (uint64_t p = 0; p < m; ++p)
-    if (reg_host[p] > L) return vbdr_fail(VBDR_EINVAL, "register %u of BDR %llu exceeds L", reg_host[p], (unsigned long long)p);
+    if (reg_host[p] > sk->Lc)
+      return vbdr_fail(VBDR_EINVAL, "register %u of BDR %llu exceeds %u", reg_host[p], (unsigned long long)p, sk->Lc);
   if (bs_host)
     for (uint64_t p = 0; p < m; ++p)
       if (L < 32 && (bs_host[p] >> L)) return vbdr_fail(VBDR_EINVAL, "bsLBP1 of BDR %llu has bits above L", (unsigned long long)p);
   if (int rc = vbdr_check_device(sk)) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   VBDR_HIP(hipStreamSynchronize(st));
-  {
+  if (sk->dr) {
     std::vector<uint8_t> plane(sk->mstride, (uint8_t)kSat);
     for (uint64_t i = 0; i < L; ++i) {
       for (uint64_t p = 0; p < m; ++p) plane[p] = dr_host[p * L + i];
       VBDR_HIP(hipMemcpy(sk->dr + i * sk->mstride, plane.data(), sk->mstride, hipMemcpyHostToDevice));
+    }
+  } else {  // packed: values capped at 2^z - 1, recorders above Lc dropped, padding at 2^z - 1
+    const uint32_t sat = (1u << sk->z) - 1;
+    std::vector<uint32_t> bp((uint64_t)sk->z * sk->wstride);
+    for (uint64_t i = 0; i < sk->Lc; ++i) {
+      std::fill(bp.begin(), bp.end(), ~0u);
+      for (uint64_t p = 0; p < m; ++p) {
+        const uint32_t v = dr_host[p * L + i] < sat ? dr_host[p * L + i] : sat;
+        for (uint32_t b = 0; b < sk->z; ++b)
+          if (!((v >> b) & 1u)) bp[b * sk->wstride + (p >> 5)] &= ~(1u << (p & 31));
+      }
+      VBDR_HIP(hipMemcpy(sk->bits + i * sk->z * sk->wstride, bp.data(), bp.size() * 4, hipMemcpyHostToDevice));
     }
   }
   if (sk->seen) {

@@ -28,7 +28,9 @@ struct vbdr_sketch {
   uint32_t A0, A1;
   uint64_t t;
   uint64_t mstride, wstride;
-  uint8_t* dr;
+  uint8_t* dr;                    // byte DRs, plane-major (fast and small layouts)
+  uint32_t* bits;                 // packed layout: bit-plane (r-1)*z + b holds bit b of DR r, 32 BDRs a word
+  uint32_t z, Lc;                 // packed layout: bits per DR, recorders per BDR (else 8 and L)
   uint32_t* seen;
   uint8_t* reg;
   unsigned long long* hist;
@@ -46,6 +48,7 @@ struct vbdr_sketch {
   unsigned long long* ovf_u;   // [est_hc] overflow partial sums
   uint32_t* ovf_v;             // [est_hc]
   uint32_t est_cap, est_hc;
+  bool bin_ok, est_ok;            // the binned scan / estimate workspaces may be allocated (on request)
   uint32_t* def_rec;              // [def_tiles][def_cap] deferred scan records (pidx << 5 | LBP1-1)
   unsigned long long* def_fill;   // [def_tiles + 1] records per tile; the last word flags direct updates
   uint32_t def_tiles, def_cap;
@@ -59,6 +62,8 @@ struct vbdr_sketch {
 
 // vbdr_sketch_create_layout without the optional large-pool workspaces.
 int vbdr_sketch_create_lean(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out);
+
+constexpr uint64_t kPackedMaxM = 1ull << 26;  // packed pools: records' tiles must fit the deferred scan's LDS
 
 // Records the calling thread's error message and returns code.
 int vbdr_fail(int code, const char* fmt, ...);

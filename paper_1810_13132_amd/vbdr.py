@@ -18,7 +18,7 @@ import torch  # loads the HIP runtime libvbdr.so then binds to
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libvbdr.so")
 
-LAYOUTS = {"fast": 0, "small": 1}
+LAYOUTS = {"fast": 0, "small": 1, "packed": 2}
 ESTIMATORS = {"hll": 0, "loglog": 1, "pcsa": 2}
 NBINS = 33
 STATUS = {0: "VBDR_OK", -1: "VBDR_EINVAL", -2: "VBDR_ENOMEM", -3: "VBDR_EHIP", -4: "VBDR_ESTATE"}
@@ -33,7 +33,8 @@ class VbdrError(RuntimeError):
 class Info(C.Structure):
     _fields_ = [("m", C.c_uint64), ("g", C.c_uint32), ("b", C.c_uint32), ("L", C.c_uint32), ("k", C.c_uint32),
                 ("layout", C.c_int32), ("A0", C.c_uint32), ("A1", C.c_uint32), ("t", C.c_uint64),
-                ("state_bytes", C.c_uint64), ("est_parts", C.c_int32), ("scan_deferred", C.c_int32)]
+                ("state_bytes", C.c_uint64), ("est_parts", C.c_int32), ("scan_deferred", C.c_int32),
+                ("Lc", C.c_uint32), ("dr_bits", C.c_uint32)]
 
 
 class Tuning(C.Structure):
@@ -53,7 +54,8 @@ class BatchTuning(C.Structure):
                 ("use_graph", C.c_int32)]
 
 
-EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_destroy", "vbdr_scan_slice",
+EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_create_packed", "vbdr_sketch_destroy",
+           "vbdr_scan_slice",
            "vbdr_advance_slice", "vbdr_estimate", "vbdr_estimate_ex", "vbdr_sketch_info", "vbdr_export_state",
            "vbdr_import_state", "vbdr_last_error", "vbdr_sketch_set_tuning", "vbdr_sketch_get_tuning",
            "vbdr_mlp_create", "vbdr_mlp_destroy", "vbdr_features", "vbdr_estimate_learned", "vbdr_trainer_create",
@@ -79,6 +81,7 @@ def lib():
         vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
         L.vbdr_sketch_create.argtypes = [u64, u32, u32, u64, C.POINTER(vp)]
         L.vbdr_sketch_create_layout.argtypes = [u64, u32, u32, u64, i32, C.POINTER(vp)]
+        L.vbdr_sketch_create_packed.argtypes = [u64, u32, u32, u64, u32, C.POINTER(vp)]
         L.vbdr_sketch_destroy.argtypes = [vp]
         L.vbdr_sketch_destroy.restype = None
         L.vbdr_scan_slice.argtypes = [vp, vp, u64, vp]
@@ -153,11 +156,16 @@ _U32 = (torch.int32, torch.uint32)
 class Sketch:
     """A VBDR sketch living on the current device."""
 
-    def __init__(self, m: int, g: int, k: int, hash_seed: int = 0, layout: str = "fast", _borrow=None):
+    def __init__(self, m: int, g: int, k: int, hash_seed: int = 0, layout: str = "fast", Lc: int = 0, _borrow=None):
+        """layout "fast", "small" or "packed" (z-bit DRs, Lc recorders per BDR; Lc = 0 means 33 - log2 g)."""
         self._owned = _borrow is None
         if _borrow is None:
             h = C.c_void_p()
-            _check(lib().vbdr_sketch_create_layout(m, g, k, hash_seed, LAYOUTS[layout], C.byref(h)))
+            if layout == "packed":
+                Lc = Lc or 33 - (int(g).bit_length() - 1)
+                _check(lib().vbdr_sketch_create_packed(m, g, k, hash_seed, Lc, C.byref(h)))
+            else:
+                _check(lib().vbdr_sketch_create_layout(m, g, k, hash_seed, LAYOUTS[layout], C.byref(h)))
         else:
             h = C.c_void_p(_borrow)
         self._h = h
@@ -165,6 +173,7 @@ class Sketch:
         self.layout = {v: key for key, v in LAYOUTS.items()}[i.layout]
         self.m, self.g, self.b, self.L, self.k = i.m, i.g, i.b, i.L, i.k
         self.A0, self.A1 = i.A0, i.A1
+        self.Lc, self.dr_bits = i.Lc, i.dr_bits
 
     def close(self):
         h = getattr(self, "_h", None)
