@@ -330,7 +330,8 @@ def main():
     adv = "k_advance_packed" if args.layout == "packed" else "k_advance_defer" if info.scan_deferred else "k_advance"
     kernels = {"scan": "k_scan_defer" if info.scan_deferred else "k_scan",
                "advance": adv + " + k_hist_reset",
-               "estimate": ("k_estimate_part + k_estimate_final" if info.est_parts > 1 else "k_estimate")}
+               "estimate": ("k_est_tile_bin + k_est_tile_gather + k_est_tile_final" if info.est_tiled else
+                            "k_estimate_part + k_estimate_final" if info.est_parts > 1 else "k_estimate")}
     traffic = traffic_from_counters(f"{dom}:{args.layout}:{w.name}", units)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernels[dom],

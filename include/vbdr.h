@@ -87,6 +87,7 @@ typedef struct vbdr_info {
     int32_t scan_deferred; /* 1 when scans defer their updates to the advance (scan_defer = 1) */
     uint32_t Lc;          /* recorders per BDR (L except for the packed layout) */
     uint32_t dr_bits;     /* bits per DR: 8, or z for the packed layout */
+    int32_t est_tiled;    /* 1 when plain estimates take the LDS-tiled path (est_binned = 3, eligible pool) */
 } vbdr_info;
 
 /*
@@ -225,17 +226,24 @@ int vbdr_sketch_info(const vbdr_sketch *sk, vbdr_info *out);
  *                      (default: 2);
  *   est_binned         for pools of 2^22 BDRs and more: 1 = hash every
  *                      (host, i) once and bin the gathers by XCD range;
- *                      2 = hash on every XCD and gather only the own range
- *                      (default: 2);
+ *                      2 = hash on every XCD and gather only the own range;
+ *                      3 = hash every (host, i) once into runs per tile of
+ *                      at most 2^18 registers, gather every register from a
+ *                      tile held in LDS, add per-tile sums (pools of at most
+ *                      2^26 BDRs, 64 <= g <= 8192; elsewhere 3 acts as 2)
+ *                      (default: 3);
  *   est_parts          pool ranges of the XCD-partitioned estimate, 8 (one
  *                      per XCD, default) or 4 (two XCDs per range: half the
  *                      hashing, twice the cache footprint per XCD);
  *   est_bin_hosts      hosts per pass of the binned estimate (its gather
  *                      runs take about 4*g bytes per host; default: as many
- *                      as the run buffer holds);
- *   est_bin_cap        slots per (host, range) run of the binned estimate,
- *                      at most the default g/8 + g/16 + 32; entries beyond
- *                      it are gathered directly by the first pass;
+ *                      as the run buffer holds); for the tiled estimate,
+ *                      hosts per block, rounded down to a multiple of 2048
+ *                      (at least 2048, at most the default min(2^27/g, 2^17));
+ *   est_bin_cap        slots per run of the binned (per host and range) or
+ *                      tiled (per 2048 hosts and tile) estimate, at most the
+ *                      default; entries beyond it are gathered directly by
+ *                      the first pass;
  *   scan_defer         for pools of 2^22..2^27 BDRs: 1 = the scan only
  *                      writes each pair's (pidx, LBP1) record, sorted by
  *                      tile of 2^15 BDRs, and the advance applies the records

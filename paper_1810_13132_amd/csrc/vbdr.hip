@@ -33,7 +33,7 @@ static vbdr_tuning default_tuning(int layout) {
   t.scan_blocks_per_cu = 16;
   t.est_blocks_per_cu = 64;
   t.scan_binned = 2;  // measured: the direct scan is as fast or faster at 2^26 pairs per slice
-  t.est_binned = 2;
+  t.est_binned = 3;  // measured: tiled 2.04 ms, partitioned 2.39 ms at 407k hosts, g = 1024, m = 2^26
   t.est_parts = 8;
   t.est_bin_hosts = 0;
   t.est_bin_cap = 0;
@@ -335,9 +335,10 @@ static_assert(kDeferTile == kDeferBlock * 32, "one thread advances 32 BDRs of a 
 static_assert(kPad % 32 == 0, "tiles of the deferred advance start on whole bit words");
 
 // Exclusive prefix sums of a[0..n) into out[0..n) by one workgroup of
-// kDeferBlock threads, n <= 4 * kDeferBlock; wsum holds kDeferBlock / 64 words.
+// BLOCK threads, n <= 4 * BLOCK; wsum holds BLOCK / 64 words.
+template <int BLOCK = kDeferBlock>
 __device__ void block_exclusive_scan(const uint32_t* a, uint32_t* out, uint32_t n, uint32_t* wsum) {
-  const uint32_t per = (n + kDeferBlock - 1) / kDeferBlock;
+  const uint32_t per = (n + BLOCK - 1) / BLOCK;
   const uint32_t lo = threadIdx.x * per;
   uint32_t v[4] = {0, 0, 0, 0}, sum = 0;
 #pragma unroll
@@ -354,7 +355,7 @@ __device__ void block_exclusive_scan(const uint32_t* a, uint32_t* out, uint32_t 
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t run = 0;
-    for (int w = 0; w < kDeferBlock / 64; ++w) {
+    for (int w = 0; w < BLOCK / 64; ++w) {
       const uint32_t t = wsum[w];
       wsum[w] = run;
       run += t;
@@ -1097,6 +1098,268 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ est, c
   }
 }
 
+// ------------------------------------------------ estimate, LDS-tiled
+// The partitioned and binned estimates both stop at the L2's rate of random
+// 1-byte gathers.  Tiled: the pool's nibble registers are cut into nt <= 256
+// tiles of TR = 2^shift registers (at most 128 KiB of nibbles), one per
+// workgroup, held in LDS.  Per block of B hosts:
+//   pass 1 hashes every (host, i) once and appends the record
+//          (offset in tile << 11 | host slot in its sub-block of 2048) to the
+//          run of (sub-block, tile), sorted by tile in LDS as in the deferred
+//          scan;
+//   pass 2 runs tile t on one workgroup: it loads the tile into LDS once and,
+//          sub-block by sub-block, gathers the runs' registers from LDS into
+//          per-host sums (U + V << 48, exact integers) and writes them out;
+//   pass 3 adds a host's nt partial sums (and any run overflow) and applies
+//          the FP64 epilogue of the other estimates.
+// Every gather is an LDS read; memory sees only streaming records and sums.
+constexpr uint32_t kTileSub = 2048;       // hosts per sub-block (11-bit slot)
+constexpr uint32_t kTileMaxShift = 18;    // 2^18 registers = 128 KiB of nibbles
+constexpr int kTileBinLog = 10;
+constexpr int kTileBinBlock = 1 << kTileBinLog;  // pass 1 workgroup
+constexpr int kTilePer = 8;               // (host, i) pairs per thread and chunk of pass 1
+constexpr uint32_t kTileChunk = kTileBinBlock * kTilePer;
+
+__host__ __device__ __forceinline__ uint32_t tile_chunk_hosts(uint32_t lg) {
+  const uint32_t h = kTileChunk >> lg;
+  return h < 64u ? h : 64u;
+}
+
+__device__ __forceinline__ unsigned long long sum_term(uint32_t r) {
+  return (1ull << (32 - r)) | (r == 0 ? (1ull << 48) : 0ull);
+}
+
+// Pass 1.  A chunk is hpc = min(kTileChunk / g, 64) consecutive hosts of one
+// sub-block.  Each (host, i) is hashed once and appended to the LDS bucket of
+// its tile (capb entries; an entry beyond it is gathered directly into the
+// host's overflow sum).  Wave 0 then reserves every bucket's place in the run
+// of (sub-block, tile), one atomic per bucket, and loads the next chunk's host
+// keys; the other waves copy the buckets out.  Wave 0 stores nothing, so its
+// waits for atomics and loads never wait for stores (the vector memory counter
+// is shared by both).  All chunks of a sub-block run on one XCD (workgroup b on
+// XCD b % 8), so that the partly written lines at the ends of a run's segments
+// merge in that XCD's L2.  LDS: cnt[nt], cntc[nt], base[nt], kmix[64],
+// bucket[nt][capb], s1[g].
+__global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_est_tile_bin(
+    const uint32_t* __restrict__ hosts, uint32_t nh, const uint32_t* __restrict__ s1g, uint32_t g, uint32_t lg,
+    uint32_t m, uint32_t shift, uint32_t nt, uint32_t capb, uint32_t cap, uint32_t* __restrict__ recs,
+    uint32_t* __restrict__ fill, const uint8_t* __restrict__ reg, unsigned long long* __restrict__ ovf) {
+  extern __shared__ uint32_t lds[];
+  constexpr uint32_t kCopyWaves = kTileBinBlock / 64 - 1;
+  const uint32_t hpc = tile_chunk_hosts(lg);  // divides kTileSub
+  uint32_t* cnt = lds;
+  uint32_t* cntc = cnt + nt;
+  uint32_t* base = cntc + nt;
+  uint32_t* kmix = base + nt;
+  uint32_t* bucket = kmix + 64;
+  uint32_t* s1l = bucket + nt * capb;
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t tmask = (1u << shift) - 1;
+  const uint32_t xcd = blockIdx.x & 7, per_xcd = gridDim.x >> 3;  // the grid is a multiple of 8
+  const uint32_t cps = kTileSub / hpc, nsb = (nh + kTileSub - 1) / kTileSub;
+  // first host of the k-th chunk of this XCD (sub-blocks xcd, xcd + 8, ...), ~0u past the end
+  auto chunk_start = [&](uint32_t k) -> uint32_t {
+    const uint32_t sb = xcd + 8 * (k / cps);
+    if (sb >= nsb) return ~0u;
+    const uint32_t c0 = sb * kTileSub + (k % cps) * hpc;
+    return c0 < nh ? c0 : ~0u;
+  };
+  auto host_of = [&](uint32_t c0) -> bool { return c0 != ~0u && lane < hpc && c0 + lane < nh; };
+  uint32_t k = blockIdx.x >> 3;
+  uint32_t c0 = chunk_start(k);
+  for (uint32_t i = threadIdx.x; i < g; i += kTileBinBlock) s1l[i] = s1g[i];
+  for (uint32_t t = threadIdx.x; t < nt; t += kTileBinBlock) cnt[t] = 0;
+  if (wave == 0) kmix[lane] = host_of(c0) ? mm3_key(hosts[c0 + lane]) : 0u;
+  __syncthreads();
+  while (c0 != ~0u) {
+    const uint32_t c0n = chunk_start(k + per_xcd);
+    uint32_t hnext = 0;
+    if (wave == 0 && host_of(c0n)) hnext = hosts[c0n + lane];
+    const uint32_t sb = c0 / kTileSub, slot0 = c0 & (kTileSub - 1);
+    unsigned long long* ovf_sb = ovf + (uint64_t)sb * kTileSub;
+    const uint32_t npairs = (nh - c0 < hpc ? nh - c0 : hpc) << lg;
+    // pair u of a thread: index (u * kTileBinBlock + tx) of the chunk, host index >> lg, i = index mod g.
+    // tx is opaque to the compiler so that the LDS addresses are formed here, not kept live across chunks.
+    uint32_t tx = threadIdx.x;
+    asm volatile("" : "+v"(tx));
+    uint32_t pv[kTilePer], qv[kTilePer];
+    if (lg <= kTileBinLog) {  // one seed per thread; hosts (tx >> lg) + u * (kTileBinBlock >> lg)
+      const uint32_t sv = s1l[tx & (g - 1)];
+      const uint32_t* kp = kmix + (tx >> lg);
+      const uint32_t kst = kTileBinBlock >> lg;
+#pragma unroll
+      for (int u = 0; u < kTilePer; ++u) {  // branch-free: kmix is zero past the chunk's hosts
+        const uint32_t p = reduce_m(mm3_seeded(kp[(u * kst) & 63u], sv), m);
+        pv[u] = (uint32_t)u * kTileBinBlock + tx < npairs ? p : ~0u;
+      }
+    } else {  // one host for g / kTileBinBlock consecutive u
+      const uint32_t gw = g >> kTileBinLog, hs = lg - kTileBinLog;
+#pragma unroll
+      for (int u = 0; u < kTilePer; ++u) {
+        const uint32_t p = reduce_m(mm3_seeded(kmix[(uint32_t)u >> hs], s1l[(((uint32_t)u & (gw - 1)) << kTileBinLog) + tx]), m);
+        pv[u] = (uint32_t)u * kTileBinBlock + tx < npairs ? p : ~0u;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kTilePer; ++u)
+      if (pv[u] != ~0u) qv[u] = atomicAdd(&cnt[pv[u] >> shift], 1u);
+#pragma unroll
+    for (int u = 0; u < kTilePer; ++u) {
+      if (pv[u] == ~0u) continue;
+      const uint32_t p = pv[u], hl = ((uint32_t)u * kTileBinBlock + threadIdx.x) >> lg;
+      if (qv[u] < capb)
+        bucket[(p >> shift) * capb + qv[u]] = ((p & tmask) << 11) | (slot0 + hl);
+      else  // bucket full
+        atomicAdd(ovf_sb + slot0 + hl, sum_term(reg[p]));
+    }
+    __syncthreads();
+    if (wave == 0) {  // nt <= 256: four buckets per lane, reservations issued together
+      uint32_t cq[4], bq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t t = lane + 64u * q;
+        cq[q] = 0;
+        bq[q] = 0;
+        if (t < nt) {
+          cq[q] = cnt[t] < capb ? cnt[t] : capb;
+          cnt[t] = 0;
+          if (cq[q]) bq[q] = atomicAdd(&fill[sb * nt + t], cq[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t t = lane + 64u * q;
+        if (t < nt) {
+          cntc[t] = cq[q];
+          base[t] = bq[q];
+        }
+      }
+      kmix[lane] = host_of(c0n) ? mm3_key(hnext) : 0u;
+    }
+    __syncthreads();
+    if (wave != 0) {
+#pragma unroll 2
+      for (uint32_t t = wave - 1; t < nt; t += kCopyWaves) {
+        const uint32_t c = cntc[t], b0 = base[t];
+        uint32_t* run = recs + ((uint64_t)sb * nt + t) * cap;
+        for (uint32_t i = lane; i < c; i += 64) {
+          const uint32_t rec = bucket[t * capb + i];
+          if (b0 + i < cap)
+            run[b0 + i] = rec;
+          else  // run full: gather directly
+            atomicAdd(ovf_sb + (rec & (kTileSub - 1)), sum_term(reg[((uint64_t)t << shift) + (rec >> 11)]));
+        }
+      }
+    }
+    __syncthreads();
+    k += per_xcd;
+    c0 = c0n;
+  }
+}
+
+// Pass 2: one workgroup per tile.  LDS: the tile's TR/2 nibble bytes.
+__global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* __restrict__ reg4,
+                                                                 const uint8_t* __restrict__ reg, uint64_t mstride,
+                                                                 uint32_t shift, uint32_t nt, uint32_t nsb,
+                                                                 uint32_t cap, const uint32_t* __restrict__ recs,
+                                                                 const uint32_t* __restrict__ fill,
+                                                                 unsigned long long* __restrict__ part, uint32_t B) {
+  extern __shared__ uint32_t tile_w[];
+  __shared__ unsigned long long acc[kTileSub];
+  const uint32_t t = blockIdx.x;
+  const uint64_t tbase = (uint64_t)t << shift;
+  const uint64_t nbytes = ((tbase + (1ull << shift) < mstride ? tbase + (1ull << shift) : mstride) - tbase) / 2;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(reg4 + tbase / 2);
+  for (uint64_t q = threadIdx.x; q < nbytes / 4; q += kDeferBlock) tile_w[q] = src[q];
+  const uint8_t* tl = reinterpret_cast<const uint8_t*>(tile_w);
+  // the first kTilePre records of every run are loaded one sub-block ahead
+  constexpr int kTilePre = 8;
+  uint32_t nxt[kTilePre], n_nxt;
+  {
+    const uint32_t f = fill[t];
+    n_nxt = f < cap ? f : cap;
+#pragma unroll
+    for (int u = 0; u < kTilePre; ++u) {
+      const uint32_t j = threadIdx.x + u * kDeferBlock;
+      nxt[u] = j < n_nxt ? recs[(uint64_t)t * cap + j] : 0u;
+    }
+  }
+  for (uint32_t sbk = 0; sbk < nsb; ++sbk) {
+    uint32_t cur[kTilePre];
+    const uint32_t n = n_nxt;
+#pragma unroll
+    for (int u = 0; u < kTilePre; ++u) cur[u] = nxt[u];
+    if (sbk + 1 < nsb) {
+      const uint32_t f = fill[(sbk + 1) * nt + t];
+      n_nxt = f < cap ? f : cap;
+      const uint32_t* nrun = recs + ((uint64_t)(sbk + 1) * nt + t) * cap;
+#pragma unroll
+      for (int u = 0; u < kTilePre; ++u) {
+        const uint32_t j = threadIdx.x + u * kDeferBlock;
+        nxt[u] = j < n_nxt ? nrun[j] : 0u;
+      }
+    }
+    for (uint32_t q = threadIdx.x; q < kTileSub; q += kDeferBlock) acc[q] = 0;
+    __syncthreads();
+    const uint32_t* run = recs + ((uint64_t)sbk * nt + t) * cap;
+#pragma unroll
+    for (int u = 0; u < kTilePre; ++u) {
+      const uint32_t j = threadIdx.x + u * kDeferBlock;
+      if (j < n) {
+        const uint32_t off = cur[u] >> 11;
+        const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
+        const uint32_t r = nib < 15u ? nib : (uint32_t)reg[tbase + off];
+        atomicAdd(&acc[cur[u] & (kTileSub - 1)], sum_term(r));
+      }
+    }
+    for (uint32_t j = threadIdx.x + kTilePre * kDeferBlock; j < n; j += kDeferBlock) {  // long runs
+      const uint32_t rec = run[j];
+      const uint32_t off = rec >> 11;
+      const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
+      const uint32_t r = nib < 15u ? nib : (uint32_t)reg[tbase + off];
+      atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(r));
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < kTileSub; q += kDeferBlock) part[(uint64_t)t * B + sbk * kTileSub + q] = acc[q];
+  }
+}
+
+// Pass 3: one thread per host of the block.
+__global__ __launch_bounds__(256) void k_est_tile_final(uint32_t nh, uint32_t g, uint32_t m, uint32_t nt, uint32_t B,
+                                                        const unsigned long long* __restrict__ hist,
+                                                        const unsigned long long* __restrict__ part,
+                                                        const unsigned long long* __restrict__ ovf,
+                                                        float* __restrict__ out) {
+  __shared__ double em_sh;
+  if (threadIdx.x == 0) em_sh = pool_estimate(hist, (double)m);
+  __syncthreads();
+  const uint32_t h = blockIdx.x * 256 + threadIdx.x;
+  if (h >= nh) return;
+  unsigned long long U = 0, V = 0;
+  const unsigned long long o = ovf[h];
+  U = o & ((1ull << 48) - 1);
+  V = o >> 48;
+  uint32_t t = 0;
+  for (; t + 8 <= nt; t += 8) {
+    unsigned long long v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(uint64_t)(t + u) * B + h];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      U += v[u] & ((1ull << 48) - 1);
+      V += v[u] >> 48;
+    }
+  }
+  for (; t < nt; ++t) {
+    const unsigned long long v = part[(uint64_t)t * B + h];
+    U += v & ((1ull << 48) - 1);
+    V += v >> 48;
+  }
+  const double Es = hll_estimate(U, V, (double)g);
+  const double n = noise_removed(Es, em_sh, (double)m, (double)g);
+  out[h] = (float)(n > 0.0 ? n : 0.0);
+}
+
 // Nibble copy of the registers (after a state import).
 __global__ void k_pack_reg4(const uint8_t* __restrict__ reg, uint8_t* __restrict__ reg4, uint64_t nbytes4) {
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nbytes4; q += (uint64_t)gridDim.x * blockDim.x) {
@@ -1226,6 +1489,25 @@ namespace {
 // sorted chunk (s1 goes to LDS only if it fits beside them).
 size_t defer_scan_lds(uint32_t tiles) { return (size_t)(2 * tiles + kDeferChunk) * 4; }
 
+// Workspaces of the LDS-tiled estimate (records, run lengths, partial and
+// overflow sums of one block of hosts), once the variant is selected.
+int alloc_tiled(vbdr_sketch* sk) {
+  if (!sk->tl_ok || sk->tl_rec) return VBDR_OK;
+  const uint64_t nsb = sk->tl_B / kTileSub;
+  const uint64_t rec_b = nsb * sk->tl_nt * sk->tl_cap * 4, fill_b = nsb * sk->tl_nt * 4;
+  const uint64_t part_b = (uint64_t)sk->tl_nt * sk->tl_B * 8, ovf_b = (uint64_t)sk->tl_B * 8;
+  if (hipMalloc(&sk->tl_rec, rec_b) != hipSuccess || hipMalloc(&sk->tl_fill, fill_b) != hipSuccess ||
+      hipMalloc(&sk->tl_part, part_b) != hipSuccess || hipMalloc(&sk->tl_ovf, ovf_b) != hipSuccess) {
+    (void)hipGetLastError();
+    for (void* q : {(void*)sk->tl_rec, (void*)sk->tl_fill, (void*)sk->tl_part, (void*)sk->tl_ovf})
+      if (q) (void)hipFree(q);
+    sk->tl_rec = nullptr, sk->tl_fill = nullptr, sk->tl_part = nullptr, sk->tl_ovf = nullptr;
+    return vbdr_fail(VBDR_ENOMEM, "allocation of the tiled-estimate workspace failed");
+  }
+  sk->bytes += rec_b + fill_b + part_b + ovf_b;
+  return VBDR_OK;
+}
+
 int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, bool lean, uint32_t Lc,
                   vbdr_sketch** out) {
   if (!out) return vbdr_fail(VBDR_EINVAL, "out is NULL");
@@ -1326,6 +1608,28 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
                 part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + def_bytes;
     sk->bin_ok = bin_bytes != 0;  // allocated when the variant is selected (vbdr_sketch_set_tuning)
     sk->est_ok = est_bytes != 0;
+    if (!lean && m >= kPartMinM && sk->mstride <= (1ull << 26) && g >= 64 && g <= kStageMaxG) {
+      uint32_t sh = 12;
+      while ((1ull << sh) * 256 < sk->mstride) sh++;
+      const uint32_t nt = (uint32_t)((sk->mstride + (1ull << sh) - 1) >> sh);
+      uint64_t B = (1ull << 27) / g;
+      B = B < (1ull << 17) ? B : (1ull << 17);
+      B = B / kTileSub * kTileSub;
+      uint32_t lg = 0;
+      while ((1u << lg) < g) lg++;
+      // bucket of a (chunk, tile): Eb entries expected, room for Eb + 4 sqrt(Eb) + 4
+      const double Eb = (double)(tile_chunk_hosts(lg) << lg) * (double)(1ull << sh) / (double)m;
+      const uint32_t capb = ((uint32_t)(Eb + 4.0 * std::sqrt(Eb) + 4.0) + 3u) & ~3u;
+      const size_t lds1 = (size_t)(3 * nt + 64 + (size_t)nt * capb + g) * 4;
+      const size_t lds2 = ((size_t)1 << sh) / 2 + kTileSub * 8;
+      if (sh <= kTileMaxShift && B >= kTileSub && lds1 + 1024 <= (size_t)lds_max && lds2 + 1024 <= (size_t)lds_max) {
+        const double E = (double)kTileSub * g * (double)(1ull << sh) / (double)m;
+        sk->tl_ok = true;
+        sk->tl_shift = sh, sk->tl_nt = nt, sk->tl_B = (uint32_t)B, sk->tl_capb = capb;
+        sk->tl_cap = (uint32_t)(E + 6.0 * std::sqrt(E) + 64.0);
+      }
+    }
+    if (sk->tune.est_binned == 3 && (rc = alloc_tiled(sk)) != VBDR_OK) break;
     hipStream_t st = nullptr;
     if ((rc = init_state(sk, st)) != VBDR_OK) break;
     hipLaunchKernelGGL(k_seeds, dim3((g + 255) / 256), dim3(256), 0, st, sk->s1, g, sk->A0);
@@ -1390,6 +1694,10 @@ void vbdr_sketch_destroy(vbdr_sketch* sk) {
   if (sk->def_rec) (void)hipFree(sk->def_rec);
   if (sk->def_fill) (void)hipFree(sk->def_fill);
   if (sk->preg) (void)hipFree(sk->preg);
+  if (sk->tl_rec) (void)hipFree(sk->tl_rec);
+  if (sk->tl_fill) (void)hipFree(sk->tl_fill);
+  if (sk->tl_part) (void)hipFree(sk->tl_part);
+  if (sk->tl_ovf) (void)hipFree(sk->tl_ovf);
   if (sk->psum) (void)hipFree(sk->psum);
   if (prev >= 0 && prev != sk->device) (void)hipSetDevice(prev);
   delete sk;
@@ -1399,7 +1707,7 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
   if (!sk || !tuning) return vbdr_fail(VBDR_EINVAL, "NULL argument");
   if (tuning->scan_test_first < 0 || tuning->scan_test_first > 2) return vbdr_fail(VBDR_EINVAL, "scan_test_first must be 0, 1 or 2");
   if (tuning->scan_binned < 0 || tuning->scan_binned > 2) return vbdr_fail(VBDR_EINVAL, "scan_binned must be 0, 1 or 2");
-  if (tuning->est_binned < 0 || tuning->est_binned > 2) return vbdr_fail(VBDR_EINVAL, "est_binned must be 0, 1 or 2");
+  if (tuning->est_binned < 0 || tuning->est_binned > 3) return vbdr_fail(VBDR_EINVAL, "est_binned must be 0..3");
   if (tuning->est_parts != 0 && tuning->est_parts != 4 && tuning->est_parts != 8)
     return vbdr_fail(VBDR_EINVAL, "est_parts must be 0, 4 or 8");
   if (tuning->scan_blocks_per_cu > 64 || tuning->est_blocks_per_cu > 64)
@@ -1441,6 +1749,8 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
     }
     sk->bytes += slots + cnt + (uint64_t)sk->est_hc * 12;
   }
+  if (sk->tune.est_binned == 3)
+    if (int rc = alloc_tiled(sk)) return rc;
   if (sk->def_rec && sk->tune.scan_defer != old_defer) {
     // pending records go to the pool; the bsLBP1 planes may now hold bits
     if (int rc = vbdr_check_device(sk)) return rc;
@@ -1468,6 +1778,7 @@ int vbdr_sketch_info(const vbdr_sketch* sk, vbdr_info* out) {
   out->scan_deferred = sk->def_rec && (sk->tune.scan_defer == 1 || sk->layout == VBDR_LAYOUT_PACKED);
   out->Lc = sk->Lc;
   out->dr_bits = sk->z;
+  out->est_tiled = sk->tl_rec != nullptr && sk->tune.est_binned == 3;
   return VBDR_OK;
 }
 
@@ -1585,6 +1896,42 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
   const bool stage = sk->g <= kStageMaxG;
   const bool extra = raw_es_dev || hist_dev;
   const size_t lds = stage ? (size_t)sk->g * 4 : 0;
+  if (sk->tl_rec && sk->tune.est_binned == 3 && !extra && n_hosts < (1ull << 32)) {
+    uint32_t B = sk->tl_B;
+    if (sk->tune.est_bin_hosts && sk->tune.est_bin_hosts < B)
+      B = sk->tune.est_bin_hosts < kTileSub ? kTileSub : sk->tune.est_bin_hosts / kTileSub * kTileSub;
+    const uint32_t nt = sk->tl_nt, g = sk->g;
+    const uint32_t cap = sk->tune.est_bin_cap && sk->tune.est_bin_cap < sk->tl_cap ? sk->tune.est_bin_cap : sk->tl_cap;
+    uint32_t lg = 0;
+    while ((1u << lg) < g) lg++;
+    // a bucket never needs more room than the run it is copied to
+    const uint32_t hpc = tile_chunk_hosts(lg), capb = sk->tl_capb < cap ? sk->tl_capb : cap;
+    const size_t lds1 = (size_t)(3 * nt + 64 + (size_t)nt * capb + g) * 4;  // fits: checked at creation
+    for (uint64_t c = 0; c < n_hosts; c += B) {
+      const uint32_t nh = (uint32_t)(n_hosts - c < B ? n_hosts - c : B);
+      const uint32_t nsb = (nh + kTileSub - 1) / kTileSub;
+      hipLaunchKernelGGL(k_fill_u32, dim3(grid_cap(sk, ((uint64_t)nsb * nt + 255) / 256, 4)), dim3(256), 0, st,
+                         sk->tl_fill, (uint64_t)nsb * nt, 0u);
+      VBDR_LAUNCHED("k_fill_u32(tl_fill)");
+      hipLaunchKernelGGL(k_fill_u32, dim3(grid_cap(sk, ((uint64_t)nh * 2 + 255) / 256, 4)), dim3(256), 0, st,
+                         reinterpret_cast<uint32_t*>(sk->tl_ovf), (uint64_t)nh * 2, 0u);
+      VBDR_LAUNCHED("k_fill_u32(tl_ovf)");
+      // eight workgroups (one per XCD) per unit of per_xcd; an XCD owns every eighth sub-block
+      const uint64_t xcd_chunks = (uint64_t)((nsb + 7) / 8) * (kTileSub / hpc);
+      const uint32_t per_xcd = grid_cap(sk, xcd_chunks * 8, 2) / 8;
+      hipLaunchKernelGGL(k_est_tile_bin, dim3(8 * (per_xcd ? per_xcd : 1)), dim3(kTileBinBlock), lds1, st,
+                         hosts_dev + c, nh, sk->s1, g, lg, (uint32_t)sk->m, sk->tl_shift, nt, capb, cap, sk->tl_rec,
+                         sk->tl_fill, sk->reg, sk->tl_ovf);
+      VBDR_LAUNCHED("k_est_tile_bin");
+      hipLaunchKernelGGL(k_est_tile_gather, dim3(nt), dim3(kDeferBlock), ((size_t)1 << sk->tl_shift) / 2, st, sk->reg4,
+                         sk->reg, sk->mstride, sk->tl_shift, nt, nsb, cap, sk->tl_rec, sk->tl_fill, sk->tl_part, B);
+      VBDR_LAUNCHED("k_est_tile_gather");
+      hipLaunchKernelGGL(k_est_tile_final, dim3((nh + 255) / 256), dim3(256), 0, st, nh, g, (uint32_t)sk->m, nt, B,
+                         sk->hist, sk->tl_part, sk->tl_ovf, out_dev + c);
+      VBDR_LAUNCHED("k_est_tile_final");
+    }
+    return VBDR_OK;
+  }
   if (sk->est_slots && sk->tune.est_binned == 1 && !extra) {
     const uint32_t hc = sk->est_hc;
     const uint32_t cap = sk->tune.est_bin_cap && sk->tune.est_bin_cap < sk->est_cap ? sk->tune.est_bin_cap : sk->est_cap;
@@ -1653,6 +2000,10 @@ int vbdr_enable_pcsa(vbdr_sketch* sk, int on) {
     if (hipMalloc(&sk->preg, sk->mstride) != hipSuccess || hipMalloc(&sk->psum, 8) != hipSuccess) {
       (void)hipGetLastError();
       if (sk->preg) (void)hipFree(sk->preg);
+  if (sk->tl_rec) (void)hipFree(sk->tl_rec);
+  if (sk->tl_fill) (void)hipFree(sk->tl_fill);
+  if (sk->tl_part) (void)hipFree(sk->tl_part);
+  if (sk->tl_ovf) (void)hipFree(sk->tl_ovf);
       sk->preg = nullptr;
       return vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed", (unsigned long long)sk->mstride);
     }

@@ -49,6 +49,13 @@ struct vbdr_sketch {
   uint32_t* ovf_v;             // [est_hc]
   uint32_t est_cap, est_hc;
   bool bin_ok, est_ok;            // the binned scan / estimate workspaces may be allocated (on request)
+  bool tl_ok;                     // the LDS-tiled estimate fits this pool (workspaces on request)
+  uint32_t tl_shift, tl_nt, tl_B, tl_cap;  // tile = 2^tl_shift registers; tiles; hosts per block; records per run
+  uint32_t tl_capb;               // entries per LDS bucket of a (chunk, tile) in the first pass
+  uint32_t* tl_rec;               // [B / 2048][nt][cap] records of a block
+  uint32_t* tl_fill;              // [B / 2048][nt] run lengths
+  unsigned long long* tl_part;    // [nt][B] per-tile sums of a block's hosts
+  unsigned long long* tl_ovf;     // [B] sums of run overflows
   uint32_t* def_rec;              // [def_tiles][def_cap] deferred scan records (pidx << 5 | LBP1-1)
   unsigned long long* def_fill;   // [def_tiles + 1] records per tile; the last word flags direct updates
   uint32_t def_tiles, def_cap;

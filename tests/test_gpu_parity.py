@@ -168,10 +168,11 @@ def test_parity_tiny_workload(V, O, layout):
 
 @pytest.mark.parametrize("layout", ["fast", "small"])
 def test_parity_large_pool_partitioned_estimate(V, O, layout):
-    """Pools of 2^22 BDRs and more take the XCD-partitioned estimate; more
-    hosts than one partition pass holds (2^17) exercise the chunking.  The
-    plain estimate (partitioned) is checked against the oracle and against
-    estimate_ex (direct gathers); both must agree bit for bit."""
+    """Pools of 2^22 BDRs and more take the LDS-tiled estimate (default) or
+    the XCD-partitioned one; more hosts than one pass or block holds (2^17)
+    exercise the chunking.  The plain estimate is checked against the oracle
+    and against estimate_ex (direct gathers), and every variant must agree
+    with it bit for bit."""
     m, g, k, seed = (1 << 22) + 77, 256, 3, 13
     rng = np.random.default_rng(seed)
     aips = rng.integers(0, 2**32, 5000, dtype=np.uint64).astype(np.uint32)
@@ -196,10 +197,20 @@ def test_parity_large_pool_partitioned_estimate(V, O, layout):
     hd = _dev(V, hosts)
     plain = sk.estimate(hd)
     assert torch.equal(b.estimate(hd), plain)
+    # the default is the LDS-tiled estimate; the XCD-partitioned one gives the same bits
+    assert sk.info().est_tiled == 1
+    sk.set_tuning(est_binned=2)
+    assert sk.info().est_tiled == 0 and sk.info().est_parts == 8
+    assert torch.equal(sk.estimate(hd), plain)
     # the binned estimate (each (host, i) hashed once) gives the same bits,
     # in one pass, in ragged passes, and with runs too short for most hosts
     for tune in ({}, {"est_bin_hosts": 40000}, {"est_bin_cap": 20}, {"est_bin_hosts": 999, "est_bin_cap": 33}):
         sk.set_tuning(est_binned=1, **tune)
+        assert torch.equal(sk.estimate(hd), plain), tune
+    # the LDS-tiled estimate: more hosts than one block (2^17); buckets and runs too
+    # short for most tiles (their overflow is gathered directly); blocks of 4096 hosts
+    for tune in ({}, {"est_bin_cap": 40}, {"est_bin_cap": 9}, {"est_bin_hosts": 5000}):
+        sk.set_tuning(est_binned=3, **tune)
         assert torch.equal(sk.estimate(hd), plain), tune
 
 
@@ -225,8 +236,9 @@ def test_binned_estimate_pow2_pool_ragged_g(V, O, layout):
     assert_estimates_close(V, O, sk, osk, hosts)
     hd = _dev(V, hosts)
     plain = sk.estimate(hd)
-    for tune in ({}, {"est_bin_cap": 10}):
-        sk.set_tuning(est_binned=1, **tune)
+    for tune in ({"est_binned": 2}, {"est_binned": 1}, {"est_binned": 1, "est_bin_cap": 10}, {"est_binned": 3},
+                 {"est_binned": 3, "est_bin_cap": 7}):
+        sk.set_tuning(**tune)
         assert torch.equal(sk.estimate(hd), plain), tune
 
 
