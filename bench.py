@@ -51,6 +51,19 @@ def algorithmic_bytes(kind, w, layout, L, n_hosts, dr_bits=8):
     raise ValueError(kind)
 
 
+def tiled_design_bytes(w, n_hosts):
+    """HBM bytes the LDS-tiled estimate moves by construction: each (host, i)
+    record written and read once (8 B), each (tile, host) partial sum written
+    and read once (16 B), host id and estimate (8 B).  Tiles: at most 256, of
+    2^s registers with s >= 12 the smallest that covers the padded pool."""
+    mstride = (w.m + 4095) // 4096 * 4096
+    s = 12
+    while (1 << s) * 256 < mstride:
+        s += 1
+    nt = (mstride + (1 << s) - 1) >> s
+    return n_hosts * (8 * w.g + 16 * nt + 8)
+
+
 # gfx950 L2: 8 XCDs x 16 channels, one tag lookup per channel per clock at 2.4 GHz.
 # A random 1-byte register gather that misses L1 costs one such request.
 L2_REQ_PEAK = 8 * 16 * 2.4e9
@@ -70,7 +83,10 @@ def traffic_from_counters(kernel_name, n_launch_units):
     k = c.get("kernels", {}).get(kernel_name)
     if not k:
         return None
-    return (k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"]) * 1024.0
+    b = (k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"]) * 1024.0
+    if k.get("units_per_call"):  # per-call work that varies (hosts estimated): scale to this run's units
+        b *= n_launch_units / k["units_per_call"]
+    return b
 
 
 def cpu_baseline(w, layout, slice0, hosts_sample, n_active, Lc=0):
@@ -330,13 +346,20 @@ def main():
     adv = "k_advance_packed" if args.layout == "packed" else "k_advance_defer" if info.scan_deferred else "k_advance"
     kernels = {"scan": "k_scan_defer" if info.scan_deferred else "k_scan",
                "advance": adv + " + k_hist_reset",
-               "estimate": ("k_est_tile_bin + k_est_tile_gather + k_est_tile_final" if info.est_tiled else
+               "estimate": ("k_est_tile_clear + k_est_tile_bin + k_est_tile_gather + k_est_tile_final"
+                            if info.est_tiled else
                             "k_estimate_part + k_estimate_final" if info.est_parts > 1 else "k_estimate")}
     traffic = traffic_from_counters(f"{dom}:{args.layout}:{w.name}", units)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernels[dom],
                 "algorithmic_bytes_per_launch": alg}
-    if dom == "estimate":
+    if dom == "estimate" and info.est_tiled:
+        # the tiled estimate trades L2 gathers for streamed records and per-tile partial sums
+        b = tiled_design_bytes(w, units)
+        rate = b / (avg["estimate"] * 1e-3) / 1e9
+        roofline["design_bytes"] = {"per_launch": b, "achieved": round(rate, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(rate / HBM_PEAK_GBS, 4)}
+    elif dom == "estimate":
         # the estimate moves few bytes; its limit is the L2 request rate of g random gathers per host
         gathers = units * w.g / (avg["estimate"] * 1e-3)
         roofline["l2_requests"] = {"achieved": gathers, "peak": L2_REQ_PEAK, "unit": "requests/s",

@@ -1125,8 +1125,23 @@ __host__ __device__ __forceinline__ uint32_t tile_chunk_hosts(uint32_t lg) {
   return h < 64u ? h : 64u;
 }
 
+// LDS bytes of pass 1 (layout at the kernel).
+inline size_t tile_bin_lds(uint32_t nt, uint32_t capb, uint32_t g) {
+  return ((size_t)3 * nt + 1 + 64 + (size_t)(nt + 1) * (capb + 1) + g) * 4;
+}
+
 __device__ __forceinline__ unsigned long long sum_term(uint32_t r) {
   return (1ull << (32 - r)) | (r == 0 ? (1ull << 48) : 0ull);
+}
+
+// Zeroes a block's run lengths and overflow sums (as 32-bit words).
+__global__ void k_est_tile_clear(uint32_t* __restrict__ a, uint64_t na, uint32_t* __restrict__ b, uint64_t nb) {
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < na + nb; q += (uint64_t)gridDim.x * blockDim.x) {
+    if (q < na)
+      a[q] = 0u;
+    else
+      b[q - na] = 0u;
+  }
 }
 
 // Pass 1.  A chunk is hpc = min(kTileChunk / g, 64) consecutive hosts of one
@@ -1138,8 +1153,10 @@ __device__ __forceinline__ unsigned long long sum_term(uint32_t r) {
 // waits for atomics and loads never wait for stores (the vector memory counter
 // is shared by both).  All chunks of a sub-block run on one XCD (workgroup b on
 // XCD b % 8), so that the partly written lines at the ends of a run's segments
-// merge in that XCD's L2.  LDS: cnt[nt], cntc[nt], base[nt], kmix[64],
-// bucket[nt][capb], s1[g].
+// merge in that XCD's L2.  Pairs past the chunk's end count into a spare
+// tile nt, and entries beyond a bucket's capacity go to a spare last slot, so
+// that the append is branch-free.  LDS: cnt[nt + 1], cntc[nt], base[nt],
+// kmix[64], bucket[nt + 1][capb + 1], s1[g].
 __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_est_tile_bin(
     const uint32_t* __restrict__ hosts, uint32_t nh, const uint32_t* __restrict__ s1g, uint32_t g, uint32_t lg,
     uint32_t m, uint32_t shift, uint32_t nt, uint32_t capb, uint32_t cap, uint32_t* __restrict__ recs,
@@ -1147,12 +1164,13 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8
   extern __shared__ uint32_t lds[];
   constexpr uint32_t kCopyWaves = kTileBinBlock / 64 - 1;
   const uint32_t hpc = tile_chunk_hosts(lg);  // divides kTileSub
+  const uint32_t bstride = capb + 1;
   uint32_t* cnt = lds;
-  uint32_t* cntc = cnt + nt;
+  uint32_t* cntc = cnt + nt + 1;
   uint32_t* base = cntc + nt;
   uint32_t* kmix = base + nt;
   uint32_t* bucket = kmix + 64;
-  uint32_t* s1l = bucket + nt * capb;
+  uint32_t* s1l = bucket + (nt + 1) * bstride;
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t tmask = (1u << shift) - 1;
   const uint32_t xcd = blockIdx.x & 7, per_xcd = gridDim.x >> 3;  // the grid is a multiple of 8
@@ -1168,7 +1186,7 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8
   uint32_t k = blockIdx.x >> 3;
   uint32_t c0 = chunk_start(k);
   for (uint32_t i = threadIdx.x; i < g; i += kTileBinBlock) s1l[i] = s1g[i];
-  for (uint32_t t = threadIdx.x; t < nt; t += kTileBinBlock) cnt[t] = 0;
+  for (uint32_t t = threadIdx.x; t <= nt; t += kTileBinBlock) cnt[t] = 0;
   if (wave == 0) kmix[lane] = host_of(c0) ? mm3_key(hosts[c0 + lane]) : 0u;
   __syncthreads();
   while (c0 != ~0u) {
@@ -1201,16 +1219,20 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8
       }
     }
 #pragma unroll
-    for (int u = 0; u < kTilePer; ++u)
-      if (pv[u] != ~0u) qv[u] = atomicAdd(&cnt[pv[u] >> shift], 1u);
+    for (int u = 0; u < kTilePer; ++u) qv[u] = atomicAdd(&cnt[pv[u] != ~0u ? pv[u] >> shift : nt], 1u);
+    bool full = false;
 #pragma unroll
     for (int u = 0; u < kTilePer; ++u) {
-      if (pv[u] == ~0u) continue;
-      const uint32_t p = pv[u], hl = ((uint32_t)u * kTileBinBlock + threadIdx.x) >> lg;
-      if (qv[u] < capb)
-        bucket[(p >> shift) * capb + qv[u]] = ((p & tmask) << 11) | (slot0 + hl);
-      else  // bucket full
-        atomicAdd(ovf_sb + slot0 + hl, sum_term(reg[p]));
+      const uint32_t p = pv[u], hl = ((uint32_t)u * kTileBinBlock + tx) >> lg;
+      const uint32_t t = p != ~0u ? p >> shift : nt;
+      bucket[__umul24(t, bstride) + (qv[u] < capb ? qv[u] : capb)] = ((p & tmask) << 11) | (slot0 + hl);
+      full |= p != ~0u && qv[u] >= capb;
+    }
+    if (full) {  // rare: entries beyond a bucket's capacity are gathered directly
+#pragma unroll
+      for (int u = 0; u < kTilePer; ++u)
+        if (pv[u] != ~0u && qv[u] >= capb)
+          atomicAdd(ovf_sb + slot0 + (((uint32_t)u * kTileBinBlock + tx) >> lg), sum_term(reg[pv[u]]));
     }
     __syncthreads();
     if (wave == 0) {  // nt <= 256: four buckets per lane, reservations issued together
@@ -1243,7 +1265,7 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8
         const uint32_t c = cntc[t], b0 = base[t];
         uint32_t* run = recs + ((uint64_t)sb * nt + t) * cap;
         for (uint32_t i = lane; i < c; i += 64) {
-          const uint32_t rec = bucket[t * capb + i];
+          const uint32_t rec = bucket[t * bstride + i];
           if (b0 + i < cap)
             run[b0 + i] = rec;
           else  // run full: gather directly
@@ -1620,7 +1642,7 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
       // bucket of a (chunk, tile): Eb entries expected, room for Eb + 4 sqrt(Eb) + 4
       const double Eb = (double)(tile_chunk_hosts(lg) << lg) * (double)(1ull << sh) / (double)m;
       const uint32_t capb = ((uint32_t)(Eb + 4.0 * std::sqrt(Eb) + 4.0) + 3u) & ~3u;
-      const size_t lds1 = (size_t)(3 * nt + 64 + (size_t)nt * capb + g) * 4;
+      const size_t lds1 = tile_bin_lds(nt, capb, g);
       const size_t lds2 = ((size_t)1 << sh) / 2 + kTileSub * 8;
       if (sh <= kTileMaxShift && B >= kTileSub && lds1 + 1024 <= (size_t)lds_max && lds2 + 1024 <= (size_t)lds_max) {
         const double E = (double)kTileSub * g * (double)(1ull << sh) / (double)m;
@@ -1906,16 +1928,14 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
     while ((1u << lg) < g) lg++;
     // a bucket never needs more room than the run it is copied to
     const uint32_t hpc = tile_chunk_hosts(lg), capb = sk->tl_capb < cap ? sk->tl_capb : cap;
-    const size_t lds1 = (size_t)(3 * nt + 64 + (size_t)nt * capb + g) * 4;  // fits: checked at creation
+    const size_t lds1 = tile_bin_lds(nt, capb, g);  // fits: checked at creation
     for (uint64_t c = 0; c < n_hosts; c += B) {
       const uint32_t nh = (uint32_t)(n_hosts - c < B ? n_hosts - c : B);
       const uint32_t nsb = (nh + kTileSub - 1) / kTileSub;
-      hipLaunchKernelGGL(k_fill_u32, dim3(grid_cap(sk, ((uint64_t)nsb * nt + 255) / 256, 4)), dim3(256), 0, st,
-                         sk->tl_fill, (uint64_t)nsb * nt, 0u);
-      VBDR_LAUNCHED("k_fill_u32(tl_fill)");
-      hipLaunchKernelGGL(k_fill_u32, dim3(grid_cap(sk, ((uint64_t)nh * 2 + 255) / 256, 4)), dim3(256), 0, st,
-                         reinterpret_cast<uint32_t*>(sk->tl_ovf), (uint64_t)nh * 2, 0u);
-      VBDR_LAUNCHED("k_fill_u32(tl_ovf)");
+      hipLaunchKernelGGL(k_est_tile_clear, dim3(grid_cap(sk, ((uint64_t)nsb * nt + 2ull * nh + 255) / 256, 4)),
+                         dim3(256), 0, st, sk->tl_fill, (uint64_t)nsb * nt, reinterpret_cast<uint32_t*>(sk->tl_ovf),
+                         (uint64_t)nh * 2);
+      VBDR_LAUNCHED("k_est_tile_clear");
       // eight workgroups (one per XCD) per unit of per_xcd; an XCD owns every eighth sub-block
       const uint64_t xcd_chunks = (uint64_t)((nsb + 7) / 8) * (kTileSub / hpc);
       const uint32_t per_xcd = grid_cap(sk, xcd_chunks * 8, 2) / 8;
