@@ -27,13 +27,19 @@
 
 using namespace vbdr;
 
-static vbdr_tuning default_tuning(int layout) {
+// Pools from 2^25 BDRs take the LDS-tiled estimate by default: their nibble
+// registers fill an XCD's 4 MB L2 share or more, where the partitioned gather
+// slows down (measured at m = 2^26, g = 1024: tiled 1.84 ms, partitioned 2.39
+// ms; at m = 2^24, g = 2048: partitioned 0.80 ms, tiled 0.86 ms).
+constexpr uint64_t kTileDefaultMinM = 1ull << 25;
+
+static vbdr_tuning default_tuning(int layout, uint64_t m) {
   vbdr_tuning t;
   t.scan_test_first = layout == VBDR_LAYOUT_FAST ? 1 : 2;
   t.scan_blocks_per_cu = 16;
   t.est_blocks_per_cu = 64;
   t.scan_binned = 2;  // measured: the direct scan is as fast or faster at 2^26 pairs per slice
-  t.est_binned = 3;  // measured: tiled 2.04 ms, partitioned 2.39 ms at 407k hosts, g = 1024, m = 2^26
+  t.est_binned = m >= kTileDefaultMinM ? 3 : 2;
   t.est_parts = 8;
   t.est_bin_hosts = 0;
   t.est_bin_cap = 0;
@@ -1127,7 +1133,7 @@ __host__ __device__ __forceinline__ uint32_t tile_chunk_hosts(uint32_t lg) {
 
 // LDS bytes of pass 1 (layout at the kernel).
 inline size_t tile_bin_lds(uint32_t nt, uint32_t capb, uint32_t g) {
-  return ((size_t)3 * nt + 1 + 64 + (size_t)(nt + 1) * (capb + 1) + g) * 4;
+  return ((size_t)(nt + 1) * (((capb + 4) & ~3u) | 4u) + 3 * (size_t)nt + 1 + 64 + g) * 4;
 }
 
 __device__ __forceinline__ unsigned long long sum_term(uint32_t r) {
@@ -1164,13 +1170,14 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8
   extern __shared__ uint32_t lds[];
   constexpr uint32_t kCopyWaves = kTileBinBlock / 64 - 1;
   const uint32_t hpc = tile_chunk_hosts(lg);  // divides kTileSub
-  const uint32_t bstride = capb + 1;
-  uint32_t* cnt = lds;
+  // room for the spare slot; rows 16-byte aligned, 4 mod 8 words apart so that rows start on different banks
+  const uint32_t bstride = ((capb + 4) & ~3u) | 4u;
+  uint32_t* bucket = lds;
+  uint32_t* cnt = bucket + (nt + 1) * bstride;
   uint32_t* cntc = cnt + nt + 1;
   uint32_t* base = cntc + nt;
   uint32_t* kmix = base + nt;
-  uint32_t* bucket = kmix + 64;
-  uint32_t* s1l = bucket + (nt + 1) * bstride;
+  uint32_t* s1l = kmix + 64;
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t tmask = (1u << shift) - 1;
   const uint32_t xcd = blockIdx.x & 7, per_xcd = gridDim.x >> 3;  // the grid is a multiple of 8
@@ -1245,7 +1252,7 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8
         if (t < nt) {
           cq[q] = cnt[t] < capb ? cnt[t] : capb;
           cnt[t] = 0;
-          if (cq[q]) bq[q] = atomicAdd(&fill[sb * nt + t], cq[q]);
+          if (cq[q]) bq[q] = atomicAdd(&fill[sb * nt + t], (cq[q] + 3u) & ~3u);  // whole quads
         }
       }
 #pragma unroll
@@ -1259,17 +1266,24 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8
       kmix[lane] = host_of(c0n) ? mm3_key(hnext) : 0u;
     }
     __syncthreads();
-    if (wave != 0) {
-#pragma unroll 2
-      for (uint32_t t = wave - 1; t < nt; t += kCopyWaves) {
+    if (wave != 0) {  // 16 lanes per bucket, four records (16 bytes) per lane; the tail quad padded with ~0u
+      const uint32_t ql = lane & 15;
+      for (uint32_t t = 4 * (wave - 1) + (lane >> 4); t < nt; t += 4 * kCopyWaves) {
         const uint32_t c = cntc[t], b0 = base[t];
         uint32_t* run = recs + ((uint64_t)sb * nt + t) * cap;
-        for (uint32_t i = lane; i < c; i += 64) {
-          const uint32_t rec = bucket[t * bstride + i];
-          if (b0 + i < cap)
-            run[b0 + i] = rec;
-          else  // run full: gather directly
-            atomicAdd(ovf_sb + (rec & (kTileSub - 1)), sum_term(reg[((uint64_t)t << shift) + (rec >> 11)]));
+        for (uint32_t i = 4 * ql; i < c; i += 64) {
+          uint4 v = *reinterpret_cast<const uint4*>(bucket + t * bstride + i);
+          if (i + 1 >= c) v.y = ~0u;
+          if (i + 2 >= c) v.z = ~0u;
+          if (i + 3 >= c) v.w = ~0u;
+          if (b0 + i < cap) {  // cap and b0 are multiples of 4: the quad fits whole
+            *reinterpret_cast<uint4*>(run + b0 + i) = v;
+          } else {  // run full: gather directly
+            const uint32_t r4[4] = {v.x, v.y, v.z, v.w};
+            for (int j = 0; j < 4; ++j)
+              if (r4[j] != ~0u)
+                atomicAdd(ovf_sb + (r4[j] & (kTileSub - 1)), sum_term(reg[((uint64_t)t << shift) + (r4[j] >> 11)]));
+          }
         }
       }
     }
@@ -1327,7 +1341,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
 #pragma unroll
     for (int u = 0; u < kTilePre; ++u) {
       const uint32_t j = threadIdx.x + u * kDeferBlock;
-      if (j < n) {
+      if (j < n && cur[u] != ~0u) {  // ~0u pads a run to whole quads
         const uint32_t off = cur[u] >> 11;
         const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
         const uint32_t r = nib < 15u ? nib : (uint32_t)reg[tbase + off];
@@ -1336,6 +1350,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     }
     for (uint32_t j = threadIdx.x + kTilePre * kDeferBlock; j < n; j += kDeferBlock) {  // long runs
       const uint32_t rec = run[j];
+      if (rec == ~0u) continue;
       const uint32_t off = rec >> 11;
       const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
       const uint32_t r = nib < 15u ? nib : (uint32_t)reg[tbase + off];
@@ -1562,7 +1577,7 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
       break;
     }
     sk->m = m, sk->g = g, sk->k = k, sk->layout = layout, sk->lean = lean;
-    sk->tune = default_tuning(layout);
+    sk->tune = default_tuning(layout, m);
     while ((1u << sk->b) < g) sk->b++;
     sk->L = 33 - sk->b;
     const uint64_t x = splitmix64_first(hash_seed);
@@ -1648,7 +1663,7 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
         const double E = (double)kTileSub * g * (double)(1ull << sh) / (double)m;
         sk->tl_ok = true;
         sk->tl_shift = sh, sk->tl_nt = nt, sk->tl_B = (uint32_t)B, sk->tl_capb = capb;
-        sk->tl_cap = (uint32_t)(E + 6.0 * std::sqrt(E) + 64.0);
+        sk->tl_cap = ((uint32_t)(E + 6.0 * std::sqrt(E) + 64.0) + 3u) & ~3u;  // runs hold whole quads
       }
     }
     if (sk->tune.est_binned == 3 && (rc = alloc_tiled(sk)) != VBDR_OK) break;
@@ -1738,7 +1753,7 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
   if (sk->layout == VBDR_LAYOUT_PACKED && tuning->scan_defer == 2)
     return vbdr_fail(VBDR_EINVAL, "the packed layout always defers its scans");
   const int old_defer = sk->tune.scan_defer;
-  sk->tune = default_tuning(sk->layout);
+  sk->tune = default_tuning(sk->layout, sk->m);
   if (tuning->scan_test_first) sk->tune.scan_test_first = tuning->scan_test_first;
   if (tuning->scan_blocks_per_cu) sk->tune.scan_blocks_per_cu = tuning->scan_blocks_per_cu;
   if (tuning->est_blocks_per_cu) sk->tune.est_blocks_per_cu = tuning->est_blocks_per_cu;
@@ -1923,7 +1938,8 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
     if (sk->tune.est_bin_hosts && sk->tune.est_bin_hosts < B)
       B = sk->tune.est_bin_hosts < kTileSub ? kTileSub : sk->tune.est_bin_hosts / kTileSub * kTileSub;
     const uint32_t nt = sk->tl_nt, g = sk->g;
-    const uint32_t cap = sk->tune.est_bin_cap && sk->tune.est_bin_cap < sk->tl_cap ? sk->tune.est_bin_cap : sk->tl_cap;
+    uint32_t cap = sk->tune.est_bin_cap && sk->tune.est_bin_cap < sk->tl_cap ? sk->tune.est_bin_cap : sk->tl_cap;
+    cap = cap < 4u ? 4u : cap & ~3u;  // runs hold whole quads of records
     uint32_t lg = 0;
     while ((1u << lg) < g) lg++;
     // a bucket never needs more room than the run it is copied to

@@ -168,11 +168,11 @@ def test_parity_tiny_workload(V, O, layout):
 
 @pytest.mark.parametrize("layout", ["fast", "small"])
 def test_parity_large_pool_partitioned_estimate(V, O, layout):
-    """Pools of 2^22 BDRs and more take the LDS-tiled estimate (default) or
-    the XCD-partitioned one; more hosts than one pass or block holds (2^17)
-    exercise the chunking.  The plain estimate is checked against the oracle
-    and against estimate_ex (direct gathers), and every variant must agree
-    with it bit for bit."""
+    """Pools of 2^22 BDRs and more take the XCD-partitioned estimate (default
+    below 2^25 BDRs) or the LDS-tiled one; more hosts than one pass or block
+    holds (2^17) exercise the chunking.  The plain estimate is checked against
+    the oracle and against estimate_ex (direct gathers), and every variant must
+    agree with it bit for bit."""
     m, g, k, seed = (1 << 22) + 77, 256, 3, 13
     rng = np.random.default_rng(seed)
     aips = rng.integers(0, 2**32, 5000, dtype=np.uint64).astype(np.uint32)
@@ -197,11 +197,8 @@ def test_parity_large_pool_partitioned_estimate(V, O, layout):
     hd = _dev(V, hosts)
     plain = sk.estimate(hd)
     assert torch.equal(b.estimate(hd), plain)
-    # the default is the LDS-tiled estimate; the XCD-partitioned one gives the same bits
-    assert sk.info().est_tiled == 1
-    sk.set_tuning(est_binned=2)
+    # below 2^25 BDRs the default is the XCD-partitioned estimate
     assert sk.info().est_tiled == 0 and sk.info().est_parts == 8
-    assert torch.equal(sk.estimate(hd), plain)
     # the binned estimate (each (host, i) hashed once) gives the same bits,
     # in one pass, in ragged passes, and with runs too short for most hosts
     for tune in ({}, {"est_bin_hosts": 40000}, {"est_bin_cap": 20}, {"est_bin_hosts": 999, "est_bin_cap": 33}):
@@ -240,6 +237,33 @@ def test_binned_estimate_pow2_pool_ragged_g(V, O, layout):
                  {"est_binned": 3, "est_bin_cap": 7}):
         sk.set_tuning(**tune)
         assert torch.equal(sk.estimate(hd), plain), tune
+
+
+def test_default_estimate_by_pool_size(V):
+    """Pools from 2^25 BDRs default to the LDS-tiled estimate, smaller ones to
+    the partitioned one; on the same sketch the tiled, partitioned and direct
+    (estimate_ex) gathers agree bit for bit."""
+    assert V.Sketch((1 << 25) - 4096, 1024, 4, 3, "small").info().est_tiled == 0
+    m, g, k = 1 << 25, 1024, 4
+    sk = V.Sketch(m, g, k, 3, "small")
+    assert sk.info().est_tiled == 1
+    rng = np.random.default_rng(3)
+    aips = rng.integers(0, 2**32, 3000, dtype=np.uint64).astype(np.uint32)
+    for t in range(2):
+        n = 1 << 20
+        pairs = np.stack([aips[rng.integers(0, len(aips), n)],
+                          rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
+        sk.scan_slice(_dev(V, pairs.reshape(-1)))
+        sk.advance_slice()
+    hosts = np.concatenate([aips, rng.integers(0, 2**32, 1001, dtype=np.uint64).astype(np.uint32)])
+    hd = _dev(V, hosts)
+    tiled = sk.estimate(hd)
+    direct = sk.estimate_ex(hd)[0]
+    sk.set_tuning(est_binned=2)
+    assert sk.info().est_tiled == 0
+    part = sk.estimate(hd)
+    assert torch.equal(tiled, part) and torch.equal(tiled, direct)
+    assert (tiled[: len(aips)] > 0).all()
 
 
 @pytest.mark.parametrize("layout", ["fast", "small"])
