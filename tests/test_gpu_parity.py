@@ -239,6 +239,50 @@ def test_binned_estimate_pow2_pool_ragged_g(V, O, layout):
         assert torch.equal(sk.estimate(hd), plain), tune
 
 
+def test_two_stream_schedule_matches_one_stream(V):
+    """Slice t+1's scan may run on a second stream while slice t is estimated
+    (it needs only slice t's advance).  That schedule gives the same estimates
+    and the same state as the sequential one, with deferred scans and the
+    tiled estimate."""
+    m, g, k = 1 << 22, 256, 3
+    rng = np.random.default_rng(17)
+    aips = rng.integers(0, 2**32, 4000, dtype=np.uint64).astype(np.uint32)
+    hd = _dev(V, aips)
+    a = V.Sketch(m, g, k, 5, "small")
+    b = V.Sketch(m, g, k, 5, "small")
+    for s_ in (a, b):
+        s_.set_tuning(est_binned=3)
+    assert a.info().est_tiled == 1 and a.info().scan_deferred == 1
+    main, side = torch.cuda.current_stream(), torch.cuda.Stream()
+    slices = []
+    for t in range(5):
+        n = 1 << 19
+        pairs = np.stack([aips[rng.integers(0, len(aips), n)],
+                          rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
+        slices.append(_dev(V, pairs.reshape(-1)))
+    outs_a, outs_b, adv = [], [], None
+    for t in range(5):
+        a.scan_slice(slices[t])
+        a.advance_slice()
+        outs_a.append(a.estimate(hd))
+        if adv is not None:
+            side.wait_event(adv)
+        b.scan_slice(slices[t], stream=side)
+        done = torch.cuda.Event()
+        done.record(side)
+        main.wait_event(done)
+        b.advance_slice(stream=main)
+        adv = torch.cuda.Event()
+        adv.record(main)
+        outs_b.append(b.estimate(hd, stream=main))
+    torch.cuda.synchronize()
+    for t in range(5):
+        assert torch.equal(outs_a[t], outs_b[t]), t
+    sa, sb = a.state(), b.state()
+    for key in ("dr", "reg", "hist"):
+        assert np.array_equal(sa[key], sb[key]), key
+
+
 def test_default_estimate_by_pool_size(V):
     """Pools from 2^25 BDRs default to the LDS-tiled estimate, smaller ones to
     the partitioned one; on the same sketch the tiled, partitioned and direct
