@@ -54,14 +54,14 @@ def algorithmic_bytes(kind, w, layout, L, n_hosts, dr_bits=8):
 def tiled_design_bytes(w, n_hosts):
     """HBM bytes the LDS-tiled estimate moves by construction: each (host, i)
     record written and read once (8 B), each (tile, host) partial sum written
-    and read once (16 B), host id and estimate (8 B).  Tiles: at most 256, of
+    and read once (8 B), host id and estimate (8 B).  Tiles: at most 256, of
     2^s registers with s >= 12 the smallest that covers the padded pool."""
     mstride = (w.m + 4095) // 4096 * 4096
     s = 12
     while (1 << s) * 256 < mstride:
         s += 1
     nt = (mstride + (1 << s) - 1) >> s
-    return n_hosts * (8 * w.g + 16 * nt + 8)
+    return n_hosts * (8 * w.g + 8 * nt + 8)
 
 
 # gfx950 L2: 8 XCDs x 16 channels, one tag lookup per channel per clock at 2.4 GHz.

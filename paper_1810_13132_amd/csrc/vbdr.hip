@@ -1140,6 +1140,18 @@ __device__ __forceinline__ unsigned long long sum_term(uint32_t r) {
   return (1ull << (32 - r)) | (r == 0 ? (1ull << 48) : 0ull);
 }
 
+// A (tile, host) sum U + V << 48 in 32 bits: V << 27 | U >> 18.  Exact when
+// every register was below 15 (terms 2^(32-r) are multiples of 2^18), V <= 30
+// and U >> 18 < 2^27; otherwise the sum goes to the host's overflow sum and
+// the entry is 0.
+__device__ __forceinline__ uint32_t pack_part(unsigned long long a, unsigned long long* ovf_h) {
+  const unsigned long long U = a & ((1ull << 48) - 1), V = a >> 48;
+  if ((U & ((1ull << 18) - 1)) == 0 && V <= 30 && (U >> 18) < (1ull << 27))
+    return (uint32_t)(V << 27 | U >> 18);
+  atomicAdd(ovf_h, a);
+  return 0u;
+}
+
 // Zeroes a block's run lengths and overflow sums (as 32-bit words).
 __global__ void k_est_tile_clear(uint32_t* __restrict__ a, uint64_t na, uint32_t* __restrict__ b, uint64_t nb) {
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < na + nb; q += (uint64_t)gridDim.x * blockDim.x) {
@@ -1299,7 +1311,8 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
                                                                  uint32_t shift, uint32_t nt, uint32_t nsb,
                                                                  uint32_t cap, const uint32_t* __restrict__ recs,
                                                                  const uint32_t* __restrict__ fill,
-                                                                 unsigned long long* __restrict__ part, uint32_t B) {
+                                                                 uint32_t* __restrict__ part, uint32_t B,
+                                                                 unsigned long long* __restrict__ ovf) {
   extern __shared__ uint32_t tile_w[];
   __shared__ unsigned long long acc[kTileSub];
   const uint32_t t = blockIdx.x;
@@ -1357,14 +1370,17 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
       atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(r));
     }
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < kTileSub; q += kDeferBlock) part[(uint64_t)t * B + sbk * kTileSub + q] = acc[q];
+    for (uint32_t q = threadIdx.x; q < kTileSub; q += kDeferBlock) {
+      const uint32_t h = sbk * kTileSub + q;
+      part[(uint64_t)t * B + h] = pack_part(acc[q], ovf + h);
+    }
   }
 }
 
 // Pass 3: one thread per host of the block.
 __global__ __launch_bounds__(256) void k_est_tile_final(uint32_t nh, uint32_t g, uint32_t m, uint32_t nt, uint32_t B,
                                                         const unsigned long long* __restrict__ hist,
-                                                        const unsigned long long* __restrict__ part,
+                                                        const uint32_t* __restrict__ part,
                                                         const unsigned long long* __restrict__ ovf,
                                                         float* __restrict__ out) {
   __shared__ double em_sh;
@@ -1376,22 +1392,24 @@ __global__ __launch_bounds__(256) void k_est_tile_final(uint32_t nh, uint32_t g,
   const unsigned long long o = ovf[h];
   U = o & ((1ull << 48) - 1);
   V = o >> 48;
+  unsigned long long Us = 0;  // in units of 2^18
   uint32_t t = 0;
   for (; t + 8 <= nt; t += 8) {
-    unsigned long long v[8];
+    uint32_t v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) v[u] = part[(uint64_t)(t + u) * B + h];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      U += v[u] & ((1ull << 48) - 1);
-      V += v[u] >> 48;
+      Us += v[u] & ((1u << 27) - 1);
+      V += v[u] >> 27;
     }
   }
   for (; t < nt; ++t) {
-    const unsigned long long v = part[(uint64_t)t * B + h];
-    U += v & ((1ull << 48) - 1);
-    V += v >> 48;
+    const uint32_t v = part[(uint64_t)t * B + h];
+    Us += v & ((1u << 27) - 1);
+    V += v >> 27;
   }
+  U += Us << 18;
   const double Es = hll_estimate(U, V, (double)g);
   const double n = noise_removed(Es, em_sh, (double)m, (double)g);
   out[h] = (float)(n > 0.0 ? n : 0.0);
@@ -1532,7 +1550,7 @@ int alloc_tiled(vbdr_sketch* sk) {
   if (!sk->tl_ok || sk->tl_rec) return VBDR_OK;
   const uint64_t nsb = sk->tl_B / kTileSub;
   const uint64_t rec_b = nsb * sk->tl_nt * sk->tl_cap * 4, fill_b = nsb * sk->tl_nt * 4;
-  const uint64_t part_b = (uint64_t)sk->tl_nt * sk->tl_B * 8, ovf_b = (uint64_t)sk->tl_B * 8;
+  const uint64_t part_b = (uint64_t)sk->tl_nt * sk->tl_B * 4, ovf_b = (uint64_t)sk->tl_B * 8;
   if (hipMalloc(&sk->tl_rec, rec_b) != hipSuccess || hipMalloc(&sk->tl_fill, fill_b) != hipSuccess ||
       hipMalloc(&sk->tl_part, part_b) != hipSuccess || hipMalloc(&sk->tl_ovf, ovf_b) != hipSuccess) {
     (void)hipGetLastError();
@@ -1960,7 +1978,8 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
                          sk->tl_fill, sk->reg, sk->tl_ovf);
       VBDR_LAUNCHED("k_est_tile_bin");
       hipLaunchKernelGGL(k_est_tile_gather, dim3(nt), dim3(kDeferBlock), ((size_t)1 << sk->tl_shift) / 2, st, sk->reg4,
-                         sk->reg, sk->mstride, sk->tl_shift, nt, nsb, cap, sk->tl_rec, sk->tl_fill, sk->tl_part, B);
+                         sk->reg, sk->mstride, sk->tl_shift, nt, nsb, cap, sk->tl_rec, sk->tl_fill, sk->tl_part, B,
+                         sk->tl_ovf);
       VBDR_LAUNCHED("k_est_tile_gather");
       hipLaunchKernelGGL(k_est_tile_final, dim3((nh + 255) / 256), dim3(256), 0, st, nh, g, (uint32_t)sk->m, nt, B,
                          sk->hist, sk->tl_part, sk->tl_ovf, out_dev + c);

@@ -54,7 +54,7 @@ struct vbdr_sketch {
   uint32_t tl_capb;               // entries per LDS bucket of a (chunk, tile) in the first pass
   uint32_t* tl_rec;               // [B / 2048][nt][cap] records of a block
   uint32_t* tl_fill;              // [B / 2048][nt] run lengths
-  unsigned long long* tl_part;    // [nt][B] per-tile sums of a block's hosts
+  uint32_t* tl_part;              // [nt][B] per-tile sums of a block's hosts, packed (exact or moved to tl_ovf)
   unsigned long long* tl_ovf;     // [B] sums of run overflows
   uint32_t* def_rec;              // [def_tiles][def_cap] deferred scan records (pidx << 5 | LBP1-1)
   unsigned long long* def_fill;   // [def_tiles + 1] records per tile; the last word flags direct updates
