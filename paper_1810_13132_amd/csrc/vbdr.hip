@@ -338,6 +338,7 @@ constexpr int kDeferPer = 32;
 constexpr uint32_t kDeferChunk = kDeferBlock * kDeferPer;
 constexpr uint32_t kDeferWords = kDeferTile / 32;  // bit words per plane of a tile
 static_assert(kDeferTile == kDeferBlock * 32, "one thread advances 32 BDRs of a tile");
+static_assert((kDeferSlots * kDeferTile) % 4 == 0, "record runs start 16-byte aligned");
 static_assert(kPad % 32 == 0, "tiles of the deferred advance start on whole bit words");
 
 // Exclusive prefix sums of a[0..n) into out[0..n) by one workgroup of
@@ -478,6 +479,34 @@ __global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restr
   }
 }
 
+// OR a tile's n records into its LDS bit-planes (plane LBP1-1, bit = BDR in
+// the tile).  The run starts 16-byte aligned (its capacity is a multiple of
+// 4), so each thread loads quads of records, four quads at a time, before the
+// LDS atomics: one load per record, waited for one at a time, left the
+// advance bound by load latency.
+__device__ __forceinline__ void records_to_planes(const uint32_t* __restrict__ r, uint32_t n, uint32_t* pm) {
+  for (uint32_t q0 = threadIdx.x; 4 * q0 < n; q0 += 4 * kDeferBlock) {
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t q = q0 + (uint32_t)u * kDeferBlock;
+      v[u] = 4 * q < n ? *reinterpret_cast<const u32x4*>(r + 4 * q) : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t q = q0 + (uint32_t)u * kDeferBlock;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (4 * q + e < n) {
+          const uint32_t rec = v[u][e];
+          const uint32_t p = (rec >> 5) & (kDeferTile - 1);
+          atomicOr(&pm[(rec & 31u) * kDeferWords + (p >> 5)], 1u << (p & 31));
+        }
+      }
+    }
+  }
+}
+
 // One workgroup per tile; LDS: L planes of kDeferWords bit words.
 template <bool FAST>
 __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restrict__ dr, uint64_t mstride,
@@ -510,11 +539,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
   __syncthreads();
   if (threadIdx.x == 0) fill[tile] = 0;  // every thread has read it
   const uint32_t* r = recs + (uint64_t)tile * cap;
-  for (uint32_t j = threadIdx.x; j < n; j += kDeferBlock) {
-    const uint32_t rec = r[j];
-    const uint32_t p = (rec >> 5) & (kDeferTile - 1);
-    atomicOr(&pm[(rec & 31u) * kDeferWords + (p >> 5)], 1u << (p & 31));
-  }
+  records_to_planes(r, n, pm);
   __syncthreads();
   uint32_t P[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (live) {
@@ -560,20 +585,23 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __rest
   __syncthreads();
   if (threadIdx.x == 0) fill[tile] = 0;  // every thread has read it
   const uint32_t* r = recs + (uint64_t)tile * cap;
-  for (uint32_t j = threadIdx.x; j < n; j += kDeferBlock) {
-    const uint32_t rec = r[j];
-    const uint32_t p = (rec >> 5) & (kDeferTile - 1);
-    atomicOr(&pm[(rec & 31u) * kDeferWords + (p >> 5)], 1u << (p & 31));
-  }
+  records_to_planes(r, n, pm);
   __syncthreads();
   const uint64_t w = (uint64_t)tile * kDeferWords + threadIdx.x;
   if (w < wstride) {
     uint32_t R[8] = {0, 0, 0, 0, 0, 0, 0, 0}, done = 0;
+    uint32_t dn[8];  // the next recorder's words load while this one is processed
+#pragma unroll
+    for (int b = 0; b < 8; ++b) dn[b] = (uint32_t)b < z ? bits[((uint64_t)(Lc - 1) * z + b) * wstride + w] : 0u;
     for (int rr = (int)Lc; rr >= 1; --rr) {
       const uint64_t pb = (uint64_t)(rr - 1) * z;
       uint32_t d[8];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) d[b] = (uint32_t)b < z ? bits[(pb + b) * wstride + w] : 0u;
+      for (int b = 0; b < 8; ++b) d[b] = dn[b];
+      if (rr > 1) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) dn[b] = (uint32_t)b < z ? bits[(pb - z + b) * wstride + w] : 0u;
+      }
       const uint32_t set = pm[(uint32_t)(rr - 1) * kDeferWords + threadIdx.x];
 #pragma unroll
       for (int b = 0; b < 8; ++b) d[b] &= ~set;  // SetDR (Alg. 9) of the slice
@@ -1024,11 +1052,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_now_export(const uint32_t* __re
   if (recs) {
     const unsigned long long f = fill[tile];
     const uint32_t n = f < cap ? (uint32_t)f : cap;
-    for (uint32_t j = threadIdx.x; j < n; j += kDeferBlock) {
-      const uint32_t rec = recs[(uint64_t)tile * cap + j];
-      const uint32_t p = (rec >> 5) & (kDeferTile - 1);
-      atomicOr(&pm[(rec & 31u) * kDeferWords + (p >> 5)], 1u << (p & 31));
-    }
+    records_to_planes(recs + (uint64_t)tile * cap, n, pm);
   }
   __syncthreads();
   const uint64_t base = (uint64_t)tile * kDeferTile + (uint64_t)threadIdx.x * 32;

@@ -231,15 +231,24 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
   uint32_t folded = 0;
   uint32_t sn = 0;
   if (FAST && use_seen) sn = seen[(uint64_t)(L - 1) * wstride + (base >> 5)];
+  // two planes in flight: plane i is processed while i-1 and i-2 load (one
+  // plane of lookahead left too few bytes in flight per CU to cover latency)
+  u32x4 nn0 = {0u, 0u, 0u, 0u}, nn1 = {0u, 0u, 0u, 0u};
+  if (L >= 2) {
+    const uint8_t* nx = dr + (uint64_t)(L - 2) * mstride + base;
+    nn0 = *reinterpret_cast<const u32x4*>(nx);
+    nn1 = *reinterpret_cast<const u32x4*>(nx + 16);
+  }
   for (int i = (int)L; i >= 1; --i) {
     const u32x4 d0 = dn0, d1 = dn1;
     const uint32_t s = sn;
-    if (i > 1) {
-      const uint8_t* nx = dr + (uint64_t)(i - 2) * mstride + base;
-      dn0 = *reinterpret_cast<const u32x4*>(nx);
-      dn1 = *reinterpret_cast<const u32x4*>(nx + 16);
-      if (FAST && use_seen) sn = seen[(uint64_t)(i - 2) * wstride + (base >> 5)];
+    dn0 = nn0, dn1 = nn1;
+    if (i > 2) {
+      const uint8_t* nx = dr + (uint64_t)(i - 3) * mstride + base;
+      nn0 = *reinterpret_cast<const u32x4*>(nx);
+      nn1 = *reinterpret_cast<const u32x4*>(nx + 16);
     }
+    if (i > 1 && FAST && use_seen) sn = seen[(uint64_t)(i - 2) * wstride + (base >> 5)];
     const uint32_t bits = s | pm[(uint32_t)(i - 1) * pm_stride];
     uint32_t fold = 0;
     if constexpr (FAST) {
