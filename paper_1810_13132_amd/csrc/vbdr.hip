@@ -595,9 +595,9 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __rest
     for (int b = 0; b < 8; ++b) dn[b] = (uint32_t)b < z ? bits[((uint64_t)(Lc - 1) * z + b) * wstride + w] : 0u;
     for (int rr = (int)Lc; rr >= 1; --rr) {
       const uint64_t pb = (uint64_t)(rr - 1) * z;
-      uint32_t d[8];
+      uint32_t d[8], o[8];  // o: the words as loaded
 #pragma unroll
-      for (int b = 0; b < 8; ++b) d[b] = dn[b];
+      for (int b = 0; b < 8; ++b) d[b] = o[b] = dn[b];
       if (rr > 1) {
 #pragma unroll
         for (int b = 0; b < 8; ++b) dn[b] = (uint32_t)b < z ? bits[(pb - z + b) * wstride + w] : 0u;
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __rest
         const uint32_t t = d[b] & carry;
         d[b] ^= carry;
         carry = t;
-        bits[(pb + b) * wstride + w] = d[b];
+        if (d[b] != o[b]) bits[(pb + b) * wstride + w] = d[b];  // saturated, unset words stay as they are
       }
     }
     const uint64_t base = w * 32;

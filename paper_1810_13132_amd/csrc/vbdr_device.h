@@ -268,9 +268,12 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
       if (!FAST && preg) Q[w] = (Q[w] & act) | (~act & ((uint32_t)(i - 1) * 0x01010101u));
       if (w < 4) nd0[w] = y; else nd1[w - 4] = y;
     }
+    // a saturated DR that was not set this slice stays 255: vectors that did not
+    // change are not written back (most of the high planes, whose DRs are rarely set)
     uint8_t* out = dr + (uint64_t)(i - 1) * mstride + base;
-    *reinterpret_cast<u32x4*>(out) = nd0;
-    *reinterpret_cast<u32x4*>(out + 16) = nd1;
+    if ((nd0[0] ^ d0[0]) | (nd0[1] ^ d0[1]) | (nd0[2] ^ d0[2]) | (nd0[3] ^ d0[3])) *reinterpret_cast<u32x4*>(out) = nd0;
+    if ((nd1[0] ^ d1[0]) | (nd1[1] ^ d1[1]) | (nd1[2] ^ d1[2]) | (nd1[3] ^ d1[3]))
+      *reinterpret_cast<u32x4*>(out + 16) = nd1;
   }
   if (FAST && use_seen)
     for (uint32_t i = 0; i < L; ++i) seen[(uint64_t)i * wstride + (base >> 5)] = 0;
