@@ -1330,6 +1330,7 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8
 }
 
 // Pass 2: one workgroup per tile.  LDS: the tile's TR/2 nibble bytes.
+template <int PRE>
 __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* __restrict__ reg4,
                                                                  const uint8_t* __restrict__ reg, uint64_t mstride,
                                                                  uint32_t shift, uint32_t nt, uint32_t nsb,
@@ -1345,53 +1346,75 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
   const uint32_t* src = reinterpret_cast<const uint32_t*>(reg4 + tbase / 2);
   for (uint64_t q = threadIdx.x; q < nbytes / 4; q += kDeferBlock) tile_w[q] = src[q];
   const uint8_t* tl = reinterpret_cast<const uint8_t*>(tile_w);
-  // the first kTilePre records of every run are loaded one sub-block ahead
-  constexpr int kTilePre = 8;
-  uint32_t nxt[kTilePre], n_nxt;
+  // the first PRE * kDeferBlock records of every run (all of it, for runs of
+  // the expected length) are loaded one sub-block ahead
+  uint32_t nxt[PRE], n_nxt;
   {
     const uint32_t f = fill[t];
     n_nxt = f < cap ? f : cap;
 #pragma unroll
-    for (int u = 0; u < kTilePre; ++u) {
+    for (int u = 0; u < PRE; ++u) {
       const uint32_t j = threadIdx.x + u * kDeferBlock;
-      nxt[u] = j < n_nxt ? recs[(uint64_t)t * cap + j] : 0u;
+      nxt[u] = j < n_nxt ? recs[(uint64_t)t * cap + j] : ~0u;
     }
   }
   for (uint32_t sbk = 0; sbk < nsb; ++sbk) {
-    uint32_t cur[kTilePre];
+    uint32_t cur[PRE];
     const uint32_t n = n_nxt;
 #pragma unroll
-    for (int u = 0; u < kTilePre; ++u) cur[u] = nxt[u];
+    for (int u = 0; u < PRE; ++u) cur[u] = nxt[u];
     if (sbk + 1 < nsb) {
       const uint32_t f = fill[(sbk + 1) * nt + t];
       n_nxt = f < cap ? f : cap;
       const uint32_t* nrun = recs + ((uint64_t)(sbk + 1) * nt + t) * cap;
 #pragma unroll
-      for (int u = 0; u < kTilePre; ++u) {
+      for (int u = 0; u < PRE; ++u) {
         const uint32_t j = threadIdx.x + u * kDeferBlock;
-        nxt[u] = j < n_nxt ? nrun[j] : 0u;
+        nxt[u] = j < n_nxt ? nrun[j] : ~0u;
       }
     }
     for (uint32_t q = threadIdx.x; q < kTileSub; q += kDeferBlock) acc[q] = 0;
     __syncthreads();
     const uint32_t* run = recs + ((uint64_t)sbk * nt + t) * cap;
+    // Registers of 15 and more (nibble 15) are read from the byte array after
+    // the loop, so that no load in it waits behind the prefetch.  ~0u pads a
+    // run to whole quads (and marks prefetch slots past its end).
+    uint32_t wide = 0;
 #pragma unroll
-    for (int u = 0; u < kTilePre; ++u) {
-      const uint32_t j = threadIdx.x + u * kDeferBlock;
-      if (j < n && cur[u] != ~0u) {  // ~0u pads a run to whole quads
+    for (int u = 0; u < PRE; ++u) {
+      if (cur[u] != ~0u) {
         const uint32_t off = cur[u] >> 11;
         const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
-        const uint32_t r = nib < 15u ? nib : (uint32_t)reg[tbase + off];
-        atomicAdd(&acc[cur[u] & (kTileSub - 1)], sum_term(r));
+        if (nib < 15u)
+          atomicAdd(&acc[cur[u] & (kTileSub - 1)], sum_term(nib));
+        else
+          wide |= 1u << u;
       }
     }
-    for (uint32_t j = threadIdx.x + kTilePre * kDeferBlock; j < n; j += kDeferBlock) {  // long runs
+    bool wide_long = false;
+    for (uint32_t j = threadIdx.x + PRE * kDeferBlock; j < n; j += kDeferBlock) {  // runs longer than expected
       const uint32_t rec = run[j];
       if (rec == ~0u) continue;
       const uint32_t off = rec >> 11;
       const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
-      const uint32_t r = nib < 15u ? nib : (uint32_t)reg[tbase + off];
-      atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(r));
+      if (nib < 15u)
+        atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(nib));
+      else
+        wide_long = true;
+    }
+    if (wide) {
+#pragma unroll
+      for (int u = 0; u < PRE; ++u)
+        if ((wide >> u) & 1u) atomicAdd(&acc[cur[u] & (kTileSub - 1)], sum_term(reg[tbase + (cur[u] >> 11)]));
+    }
+    if (wide_long) {
+      for (uint32_t j = threadIdx.x + PRE * kDeferBlock; j < n; j += kDeferBlock) {
+        const uint32_t rec = run[j];
+        if (rec == ~0u) continue;
+        const uint32_t off = rec >> 11;
+        if (((tl[off >> 1] >> ((off & 1u) << 2)) & 15u) == 15u)
+          atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(reg[tbase + off]));
+      }
     }
     __syncthreads();
     for (uint32_t q = threadIdx.x; q < kTileSub; q += kDeferBlock) {
@@ -2001,7 +2024,9 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
                          hosts_dev + c, nh, sk->s1, g, lg, (uint32_t)sk->m, sk->tl_shift, nt, capb, cap, sk->tl_rec,
                          sk->tl_fill, sk->reg, sk->tl_ovf);
       VBDR_LAUNCHED("k_est_tile_bin");
-      hipLaunchKernelGGL(k_est_tile_gather, dim3(nt), dim3(kDeferBlock), ((size_t)1 << sk->tl_shift) / 2, st, sk->reg4,
+      // prefetch depth: the whole run when runs are near their expected length
+      const auto gather = cap <= 12u * kDeferBlock ? k_est_tile_gather<12> : k_est_tile_gather<20>;
+      hipLaunchKernelGGL(gather, dim3(nt), dim3(kDeferBlock), ((size_t)1 << sk->tl_shift) / 2, st, sk->reg4,
                          sk->reg, sk->mstride, sk->tl_shift, nt, nsb, cap, sk->tl_rec, sk->tl_fill, sk->tl_part, B,
                          sk->tl_ovf);
       VBDR_LAUNCHED("k_est_tile_gather");
