@@ -187,7 +187,8 @@ __device__ __forceinline__ void advance_group(uint8_t* dr, uint64_t mstride, uin
       if (!FAST && preg) Q[w] = (Q[w] & act) | (~act & ((uint32_t)(i - 1) * 0x01010101u));
       nd[w] = y;
     }
-    *reinterpret_cast<u32x4*>(dr + (uint64_t)(i - 1) * mstride + base) = nd;
+    if ((nd[0] ^ d[0]) | (nd[1] ^ d[1]) | (nd[2] ^ d[2]) | (nd[3] ^ d[3]))  // saturated, unset DRs stay 255
+      *reinterpret_cast<u32x4*>(dr + (uint64_t)(i - 1) * mstride + base) = nd;
   }
   if (!FAST && preg) {
     *reinterpret_cast<u32x4*>(preg + base) = u32x4{Q[0], Q[1], Q[2], Q[3]};
