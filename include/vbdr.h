@@ -231,7 +231,7 @@ int vbdr_sketch_info(const vbdr_sketch *sk, vbdr_info *out);
  *                      at most 2^18 registers, gather every register from a
  *                      tile held in LDS, add per-tile sums (pools of at most
  *                      2^26 BDRs, 64 <= g <= 8192; elsewhere 3 acts as 2)
- *                      (default: 3 for pools of 2^25 BDRs and more, else 2);
+ *                      (default: 3 for pools of 2^24 BDRs and more, else 2);
  *   est_parts          pool ranges of the XCD-partitioned estimate, 8 (one
  *                      per XCD, default) or 4 (two XCDs per range: half the
  *                      hashing, twice the cache footprint per XCD);

@@ -27,11 +27,11 @@
 
 using namespace vbdr;
 
-// Pools from 2^25 BDRs take the LDS-tiled estimate by default: their nibble
-// registers fill an XCD's 4 MB L2 share or more, where the partitioned gather
-// slows down (measured at m = 2^26, g = 1024: tiled 1.84 ms, partitioned 2.39
-// ms; at m = 2^24, g = 2048: partitioned 0.80 ms, tiled 0.86 ms).
-constexpr uint64_t kTileDefaultMinM = 1ull << 25;
+// Pools from 2^24 BDRs take the LDS-tiled estimate by default (measured at
+// m = 2^26, g = 1024: tiled 1.65 ms, partitioned 2.39 ms; at m = 2^24,
+// g = 2048: tiled 0.60 ms, partitioned 0.80 ms).  Below, the partitioned
+// gather's per-XCD ranges are at most 512 KB and stay in the L2s.
+constexpr uint64_t kTileDefaultMinM = 1ull << 24;
 
 static vbdr_tuning default_tuning(int layout, uint64_t m) {
   vbdr_tuning t;
@@ -1147,7 +1147,7 @@ constexpr uint32_t kTileSub = 2048;       // hosts per sub-block (11-bit slot)
 constexpr uint32_t kTileMaxShift = 18;    // 2^18 registers = 128 KiB of nibbles
 constexpr int kTileBinLog = 10;
 constexpr int kTileBinBlock = 1 << kTileBinLog;  // pass 1 workgroup
-constexpr int kTilePer = 8;               // (host, i) pairs per thread and chunk of pass 1
+constexpr int kTilePer = 16;              // (host, i) pairs per thread and chunk of pass 1
 constexpr uint32_t kTileChunk = kTileBinBlock * kTilePer;
 
 __host__ __device__ __forceinline__ uint32_t tile_chunk_hosts(uint32_t lg) {
@@ -1199,7 +1199,7 @@ __global__ void k_est_tile_clear(uint32_t* __restrict__ a, uint64_t na, uint32_t
 // tile nt, and entries beyond a bucket's capacity go to a spare last slot, so
 // that the append is branch-free.  LDS: cnt[nt + 1], cntc[nt], base[nt],
 // kmix[64], bucket[nt + 1][capb + 1], s1[g].
-__global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_est_tile_bin(
+__global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_est_tile_bin(
     const uint32_t* __restrict__ hosts, uint32_t nh, const uint32_t* __restrict__ s1g, uint32_t g, uint32_t lg,
     uint32_t m, uint32_t shift, uint32_t nt, uint32_t capb, uint32_t cap, uint32_t* __restrict__ recs,
     uint32_t* __restrict__ fill, const uint8_t* __restrict__ reg, unsigned long long* __restrict__ ovf) {
@@ -2019,7 +2019,7 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
       VBDR_LAUNCHED("k_est_tile_clear");
       // eight workgroups (one per XCD) per unit of per_xcd; an XCD owns every eighth sub-block
       const uint64_t xcd_chunks = (uint64_t)((nsb + 7) / 8) * (kTileSub / hpc);
-      const uint32_t per_xcd = grid_cap(sk, xcd_chunks * 8, 2) / 8;
+      const uint32_t per_xcd = grid_cap(sk, xcd_chunks * 8, 1) / 8;  // one workgroup per CU (LDS)
       hipLaunchKernelGGL(k_est_tile_bin, dim3(8 * (per_xcd ? per_xcd : 1)), dim3(kTileBinBlock), lds1, st,
                          hosts_dev + c, nh, sk->s1, g, lg, (uint32_t)sk->m, sk->tl_shift, nt, capb, cap, sk->tl_rec,
                          sk->tl_fill, sk->reg, sk->tl_ovf);

@@ -169,7 +169,7 @@ def test_parity_tiny_workload(V, O, layout):
 @pytest.mark.parametrize("layout", ["fast", "small"])
 def test_parity_large_pool_partitioned_estimate(V, O, layout):
     """Pools of 2^22 BDRs and more take the XCD-partitioned estimate (default
-    below 2^25 BDRs) or the LDS-tiled one; more hosts than one pass or block
+    below 2^24 BDRs) or the LDS-tiled one; more hosts than one pass or block
     holds (2^17) exercise the chunking.  The plain estimate is checked against
     the oracle and against estimate_ex (direct gathers), and every variant must
     agree with it bit for bit."""
@@ -197,7 +197,7 @@ def test_parity_large_pool_partitioned_estimate(V, O, layout):
     hd = _dev(V, hosts)
     plain = sk.estimate(hd)
     assert torch.equal(b.estimate(hd), plain)
-    # below 2^25 BDRs the default is the XCD-partitioned estimate
+    # below 2^24 BDRs the default is the XCD-partitioned estimate
     assert sk.info().est_tiled == 0 and sk.info().est_parts == 8
     # the binned estimate (each (host, i) hashed once) gives the same bits,
     # in one pass, in ragged passes, and with runs too short for most hosts
@@ -284,11 +284,11 @@ def test_two_stream_schedule_matches_one_stream(V):
 
 
 def test_default_estimate_by_pool_size(V):
-    """Pools from 2^25 BDRs default to the LDS-tiled estimate, smaller ones to
+    """Pools from 2^24 BDRs default to the LDS-tiled estimate, smaller ones to
     the partitioned one; on the same sketch the tiled, partitioned and direct
     (estimate_ex) gathers agree bit for bit."""
-    assert V.Sketch((1 << 25) - 4096, 1024, 4, 3, "small").info().est_tiled == 0
-    m, g, k = 1 << 25, 1024, 4
+    assert V.Sketch((1 << 24) - 4096, 1024, 4, 3, "small").info().est_tiled == 0
+    m, g, k = 1 << 24, 1024, 4
     sk = V.Sketch(m, g, k, 3, "small")
     assert sk.info().est_tiled == 1
     rng = np.random.default_rng(3)
