@@ -1143,7 +1143,8 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ est, c
 //   pass 3 adds a host's nt partial sums (and any run overflow) and applies
 //          the FP64 epilogue of the other estimates.
 // Every gather is an LDS read; memory sees only streaming records and sums.
-constexpr uint32_t kTileSub = 2048;       // hosts per sub-block (11-bit slot)
+constexpr uint32_t kTileSlotBits = 11;
+constexpr uint32_t kTileSub = 1u << kTileSlotBits;  // hosts per sub-block (slot bits of a record)
 constexpr uint32_t kTileMaxShift = 18;    // 2^18 registers = 128 KiB of nibbles
 constexpr int kTileBinLog = 10;
 constexpr int kTileBinBlock = 1 << kTileBinLog;  // pass 1 workgroup
@@ -1268,7 +1269,7 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
     for (int u = 0; u < kTilePer; ++u) {
       const uint32_t p = pv[u], hl = ((uint32_t)u * kTileBinBlock + tx) >> lg;
       const uint32_t t = p != ~0u ? p >> shift : nt;
-      bucket[__umul24(t, bstride) + (qv[u] < capb ? qv[u] : capb)] = ((p & tmask) << 11) | (slot0 + hl);
+      bucket[__umul24(t, bstride) + (qv[u] < capb ? qv[u] : capb)] = ((p & tmask) << kTileSlotBits) | (slot0 + hl);
       full |= p != ~0u && qv[u] >= capb;
     }
     if (full) {  // rare: entries beyond a bucket's capacity are gathered directly
@@ -1318,7 +1319,7 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
             const uint32_t r4[4] = {v.x, v.y, v.z, v.w};
             for (int j = 0; j < 4; ++j)
               if (r4[j] != ~0u)
-                atomicAdd(ovf_sb + (r4[j] & (kTileSub - 1)), sum_term(reg[((uint64_t)t << shift) + (r4[j] >> 11)]));
+                atomicAdd(ovf_sb + (r4[j] & (kTileSub - 1)), sum_term(reg[((uint64_t)t << shift) + (r4[j] >> kTileSlotBits)]));
           }
         }
       }
@@ -1383,7 +1384,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
 #pragma unroll
     for (int u = 0; u < PRE; ++u) {
       if (cur[u] != ~0u) {
-        const uint32_t off = cur[u] >> 11;
+        const uint32_t off = cur[u] >> kTileSlotBits;
         const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
         if (nib < 15u)
           atomicAdd(&acc[cur[u] & (kTileSub - 1)], sum_term(nib));
@@ -1395,7 +1396,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     for (uint32_t j = threadIdx.x + PRE * kDeferBlock; j < n; j += kDeferBlock) {  // runs longer than expected
       const uint32_t rec = run[j];
       if (rec == ~0u) continue;
-      const uint32_t off = rec >> 11;
+      const uint32_t off = rec >> kTileSlotBits;
       const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
       if (nib < 15u)
         atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(nib));
@@ -1405,13 +1406,13 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     if (wide) {
 #pragma unroll
       for (int u = 0; u < PRE; ++u)
-        if ((wide >> u) & 1u) atomicAdd(&acc[cur[u] & (kTileSub - 1)], sum_term(reg[tbase + (cur[u] >> 11)]));
+        if ((wide >> u) & 1u) atomicAdd(&acc[cur[u] & (kTileSub - 1)], sum_term(reg[tbase + (cur[u] >> kTileSlotBits)]));
     }
     if (wide_long) {
       for (uint32_t j = threadIdx.x + PRE * kDeferBlock; j < n; j += kDeferBlock) {
         const uint32_t rec = run[j];
         if (rec == ~0u) continue;
-        const uint32_t off = rec >> 11;
+        const uint32_t off = rec >> kTileSlotBits;
         if (((tl[off >> 1] >> ((off & 1u) << 2)) & 15u) == 15u)
           atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(reg[tbase + off]));
       }
