@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restr
         direct = true;
       }
     }
-    if (FAST && direct) fill[tiles] = 1ull;
+    if (direct) fill[tiles] = 1ull;  // fast: the advance reads bsLBP1; small: its saturation masks are stale
     __syncthreads();
   }
 }
@@ -517,7 +517,8 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
                                                                const uint32_t* __restrict__ recs,
                                                                unsigned long long* __restrict__ fill, uint32_t cap,
                                                                uint32_t tiles, uint8_t* __restrict__ preg,
-                                                               unsigned long long* __restrict__ psum) {
+                                                               unsigned long long* __restrict__ psum,
+                                                               uint32_t* __restrict__ sat) {
   extern __shared__ uint32_t pm[];
   __shared__ uint32_t lh[kDeferBlock / 64][kBins];
   const uint32_t tile = blockIdx.x;
@@ -527,6 +528,8 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
   const unsigned long long f = fill[tile];
   const uint32_t n = f < cap ? (uint32_t)f : cap;
   const bool use_seen = FAST && fill[tiles] != 0;
+  // the saturation masks hold only if no DR changed outside the advance since the last one
+  const bool sat_ok = sat != nullptr && fill[tiles] == 0;
   // the top plane's load goes out before the record phase
   const uint64_t base = (uint64_t)tile * kDeferTile + (uint64_t)threadIdx.x * 32;
   const bool live = base < mstride;
@@ -544,8 +547,9 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
   uint32_t P[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (live) {
     uint32_t R[8];
+    uint32_t* satw = sat ? sat + (base >> 5) : nullptr;
     advance_group32<FAST>(dr, mstride, seen, wstride, reg, reg4, base, L, swar_gt_bias(thr), pm + threadIdx.x,
-                          kDeferWords, use_seen, top0, top1, R, preg, P);
+                          kDeferWords, use_seen, top0, top1, R, preg, P, satw, sat_ok ? *satw : 0u);
 #pragma unroll
     for (int j = 0; j < 32; ++j)
       if (base + j < m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
@@ -669,7 +673,7 @@ __global__ __launch_bounds__(256) void k_defer_flush(const uint32_t* __restrict_
   __syncthreads();
   if (threadIdx.x == 0) {
     fill[tile] = 0;
-    if (FAST && n) fill[tiles] = 1ull;
+    if (n) fill[tiles] = 1ull;
   }
 }
 
@@ -1531,6 +1535,10 @@ int init_state(vbdr_sketch* sk, hipStream_t st) {
                        (uint64_t)(sk->def_tiles + 1) * 2, 0u);
     VBDR_LAUNCHED("k_fill_u32(def_fill)");
   }
+  if (sk->sat) {  // no plane known saturated: the first advance reads every DR
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid), dim3(256), 0, st, sk->sat, sk->wstride, 0u);
+    VBDR_LAUNCHED("k_fill_u32(sat)");
+  }
   return VBDR_OK;
 }
 
@@ -1701,14 +1709,16 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
         hipMalloc(&sk->est_ws, (uint64_t)kLearnChunk * 4) != hipSuccess ||
 
         (def_bytes && hipMalloc(&sk->def_rec, (uint64_t)sk->def_tiles * sk->def_cap * 4) != hipSuccess) ||
-        (def_bytes && hipMalloc(&sk->def_fill, (uint64_t)(sk->def_tiles + 1) * 8) != hipSuccess)) {
+        (def_bytes && hipMalloc(&sk->def_fill, (uint64_t)(sk->def_tiles + 1) * 8) != hipSuccess) ||
+        (def_bytes && dr_bytes && hipMalloc(&sk->sat, sk->wstride * 4) != hipSuccess)) {
       (void)hipGetLastError();
       rc = vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed",
                 (unsigned long long)(dr_bytes + seen_bytes + sk->mstride * 3 / 2 + part_bytes));
       break;
     }
     sk->bytes = dr_bytes + bits_bytes + seen_bytes + sk->mstride * 3 / 2 + 64 * sizeof(unsigned long long) + (uint64_t)g * 4 +
-                part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + def_bytes;
+                part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + def_bytes +
+                (sk->sat ? sk->wstride * 4 : 0);
     sk->bin_ok = bin_bytes != 0;  // allocated when the variant is selected (vbdr_sketch_set_tuning)
     sk->est_ok = est_bytes != 0;
     if (!lean && m >= kPartMinM && sk->mstride <= (1ull << 26) && g >= 64 && g <= kStageMaxG) {
@@ -1796,6 +1806,7 @@ void vbdr_sketch_destroy(vbdr_sketch* sk) {
   if (sk->ovf_v) (void)hipFree(sk->ovf_v);
   if (sk->def_rec) (void)hipFree(sk->def_rec);
   if (sk->def_fill) (void)hipFree(sk->def_fill);
+  if (sk->sat) (void)hipFree(sk->sat);
   if (sk->preg) (void)hipFree(sk->preg);
   if (sk->tl_rec) (void)hipFree(sk->tl_rec);
   if (sk->tl_fill) (void)hipFree(sk->tl_fill);
@@ -1972,7 +1983,7 @@ int vbdr_advance_slice(vbdr_sketch* sk, void* stream) {
     auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_advance_defer<true> : k_advance_defer<false>;
     hipLaunchKernelGGL(kern, dim3(sk->def_tiles), dim3(kDeferBlock), (size_t)sk->L * kDeferWords * 4, st, sk->dr,
                        sk->mstride, sk->seen, sk->wstride, sk->reg, sk->reg4, sk->m, sk->L, sk->k - 1, sk->hist,
-                       sk->def_rec, sk->def_fill, sk->def_cap, sk->def_tiles, sk->preg, sk->psum);
+                       sk->def_rec, sk->def_fill, sk->def_cap, sk->def_tiles, sk->preg, sk->psum, sk->sat);
     VBDR_LAUNCHED("k_advance_defer");
     hipLaunchKernelGGL(k_defer_flag, dim3(1), dim3(64), 0, st, sk->def_fill, sk->def_tiles, 0ull);
     VBDR_LAUNCHED("k_defer_flag");

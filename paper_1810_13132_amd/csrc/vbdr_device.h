@@ -222,7 +222,8 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
                                                 uint8_t* reg, uint8_t* reg4, uint64_t base, uint32_t L,
                                                 uint32_t gt_bias, const uint32_t* pm, uint32_t pm_stride,
                                                 bool use_seen, u32x4 dn0, u32x4 dn1, uint32_t R[8],
-                                                uint8_t* preg = nullptr, uint32_t* P = nullptr) {
+                                                uint8_t* preg = nullptr, uint32_t* P = nullptr,
+                                                uint32_t* satw = nullptr, uint32_t sat_in = 0u) {
   uint32_t M[8], Q[8];
 #pragma unroll
   for (int w = 0; w < 8; ++w) {
@@ -233,21 +234,32 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
   uint32_t sn = 0;
   if (FAST && use_seen) sn = seen[(uint64_t)(L - 1) * wstride + (base >> 5)];
   // two planes in flight: plane i is processed while i-1 and i-2 load (one
-  // plane of lookahead left too few bytes in flight per CU to cover latency)
-  u32x4 nn0 = {0u, 0u, 0u, 0u}, nn1 = {0u, 0u, 0u, 0u};
-  if (L >= 2) {
+  // plane of lookahead left too few bytes in flight per CU to cover latency).
+  // Bit r-1 of sat_in: the 32 DR[r] were all 255 after the last advance and
+  // nothing but the advance has written DRs since; with no record of this
+  // slice in that plane they are 255 now and stay 255, so they are neither
+  // loaded nor stored.
+  const u32x4 ff = {~0u, ~0u, ~0u, ~0u};
+  auto skip = [&](int r) -> bool { return ((sat_in >> (r - 1)) & 1u) && pm[(uint32_t)(r - 1) * pm_stride] == 0u; };
+  u32x4 nn0 = ff, nn1 = ff;
+  if (L >= 2 && !skip((int)L - 1)) {
     const uint8_t* nx = dr + (uint64_t)(L - 2) * mstride + base;
     nn0 = *reinterpret_cast<const u32x4*>(nx);
     nn1 = *reinterpret_cast<const u32x4*>(nx + 16);
   }
+  uint32_t sat_out = 0;
   for (int i = (int)L; i >= 1; --i) {
     const u32x4 d0 = dn0, d1 = dn1;
     const uint32_t s = sn;
     dn0 = nn0, dn1 = nn1;
     if (i > 2) {
-      const uint8_t* nx = dr + (uint64_t)(i - 3) * mstride + base;
-      nn0 = *reinterpret_cast<const u32x4*>(nx);
-      nn1 = *reinterpret_cast<const u32x4*>(nx + 16);
+      if (skip(i - 2)) {
+        nn0 = ff, nn1 = ff;
+      } else {
+        const uint8_t* nx = dr + (uint64_t)(i - 3) * mstride + base;
+        nn0 = *reinterpret_cast<const u32x4*>(nx);
+        nn1 = *reinterpret_cast<const u32x4*>(nx + 16);
+      }
     }
     if (i > 1 && FAST && use_seen) sn = seen[(uint64_t)(i - 2) * wstride + (base >> 5)];
     const uint32_t bits = s | pm[(uint32_t)(i - 1) * pm_stride];
@@ -275,7 +287,9 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
     if ((nd0[0] ^ d0[0]) | (nd0[1] ^ d0[1]) | (nd0[2] ^ d0[2]) | (nd0[3] ^ d0[3])) *reinterpret_cast<u32x4*>(out) = nd0;
     if ((nd1[0] ^ d1[0]) | (nd1[1] ^ d1[1]) | (nd1[2] ^ d1[2]) | (nd1[3] ^ d1[3]))
       *reinterpret_cast<u32x4*>(out + 16) = nd1;
+    if ((nd0[0] & nd0[1] & nd0[2] & nd0[3] & nd1[0] & nd1[1] & nd1[2] & nd1[3]) == ~0u) sat_out |= 1u << (i - 1);
   }
+  if (satw) *satw = sat_out;  // always: sat_in is 0 when the stored masks were stale
   if (FAST && use_seen)
     for (uint32_t i = 0; i < L; ++i) seen[(uint64_t)i * wstride + (base >> 5)] = 0;
   *reinterpret_cast<u32x4*>(reg + base) = u32x4{R[0], R[1], R[2], R[3]};
