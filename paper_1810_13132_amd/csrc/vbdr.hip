@@ -1334,7 +1334,8 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
   }
 }
 
-// Pass 2: one workgroup per tile.  LDS: the tile's TR/2 nibble bytes.
+// Pass 2: one workgroup per tile.  LDS: the tile's TR/2 nibble bytes (dynamic)
+// and two buffers of per-host sums (static): 160 KiB for tiles of 2^18.
 template <int PRE>
 __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* __restrict__ reg4,
                                                                  const uint8_t* __restrict__ reg, uint64_t mstride,
@@ -1344,7 +1345,9 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
                                                                  uint32_t* __restrict__ part, uint32_t B,
                                                                  unsigned long long* __restrict__ ovf) {
   extern __shared__ uint32_t tile_w[];
-  __shared__ unsigned long long acc[kTileSub];
+  // per-host sums, double-buffered: one barrier per sub-block
+  __shared__ unsigned long long acc2[2][kTileSub];
+  for (uint32_t q = threadIdx.x; q < 2 * kTileSub; q += kDeferBlock) (&acc2[0][0])[q] = 0;
   const uint32_t t = blockIdx.x;
   const uint64_t tbase = (uint64_t)t << shift;
   const uint64_t nbytes = ((tbase + (1ull << shift) < mstride ? tbase + (1ull << shift) : mstride) - tbase) / 2;
@@ -1364,6 +1367,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     }
   }
   for (uint32_t sbk = 0; sbk < nsb; ++sbk) {
+    unsigned long long* acc = acc2[sbk & 1];
     uint32_t cur[PRE];
     const uint32_t n = n_nxt;
 #pragma unroll
@@ -1378,8 +1382,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
         nxt[u] = j < n_nxt ? nrun[j] : ~0u;
       }
     }
-    for (uint32_t q = threadIdx.x; q < kTileSub; q += kDeferBlock) acc[q] = 0;
-    __syncthreads();
+    if (sbk == 0) __syncthreads();  // the tile and the zeroed accumulators
     const uint32_t* run = recs + ((uint64_t)sbk * nt + t) * cap;
     // Registers of 15 and more (nibble 15) are read from the byte array after
     // the loop, so that no load in it waits behind the prefetch.  ~0u pads a
@@ -1425,6 +1428,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     for (uint32_t q = threadIdx.x; q < kTileSub; q += kDeferBlock) {
       const uint32_t h = sbk * kTileSub + q;
       part[(uint64_t)t * B + h] = pack_part(acc[q], ovf + h);
+      acc[q] = 0;  // gathered into again two sub-blocks on, after the next barrier
     }
   }
 }
@@ -1734,8 +1738,8 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
       const double Eb = (double)(tile_chunk_hosts(lg) << lg) * (double)(1ull << sh) / (double)m;
       const uint32_t capb = ((uint32_t)(Eb + 4.0 * std::sqrt(Eb) + 4.0) + 3u) & ~3u;
       const size_t lds1 = tile_bin_lds(nt, capb, g);
-      const size_t lds2 = ((size_t)1 << sh) / 2 + kTileSub * 8;
-      if (sh <= kTileMaxShift && B >= kTileSub && lds1 + 1024 <= (size_t)lds_max && lds2 + 1024 <= (size_t)lds_max) {
+      const size_t lds2 = ((size_t)1 << sh) / 2 + 2 * kTileSub * 8;  // the tile and two accumulator buffers
+      if (sh <= kTileMaxShift && B >= kTileSub && lds1 + 1024 <= (size_t)lds_max && lds2 <= (size_t)lds_max) {
         const double E = (double)kTileSub * g * (double)(1ull << sh) / (double)m;
         sk->tl_ok = true;
         sk->tl_shift = sh, sk->tl_nt = nt, sk->tl_B = (uint32_t)B, sk->tl_capb = capb;
