@@ -204,8 +204,8 @@ def test_parity_large_pool_partitioned_estimate(V, O, layout):
     for tune in ({}, {"est_bin_hosts": 40000}, {"est_bin_cap": 20}, {"est_bin_hosts": 999, "est_bin_cap": 33}):
         sk.set_tuning(est_binned=1, **tune)
         assert torch.equal(sk.estimate(hd), plain), tune
-    # the LDS-tiled estimate: more hosts than one block (2^17); buckets and runs too
-    # short for most tiles (their overflow is gathered directly); blocks of 4096 hosts
+    # the LDS-tiled estimate: one block; buckets and runs too short for most tiles
+    # (their overflow is gathered directly); 33 blocks of at most 4096 hosts
     for tune in ({}, {"est_bin_cap": 40}, {"est_bin_cap": 9}, {"est_bin_hosts": 5000}):
         sk.set_tuning(est_binned=3, **tune)
         assert torch.equal(sk.estimate(hd), plain), tune
