@@ -396,7 +396,7 @@ __device__ __forceinline__ void apply_record(uint32_t rec, uint8_t* dr, uint64_t
 }
 
 // LDS: cnt[tiles], start[tiles], sorted[kDeferChunk], then s1 if staged.
-template <bool FAST>
+template <bool FAST, bool STAGE>
 __global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restrict__ pairs, uint64_t n,
                                                             const uint32_t* __restrict__ s1g, uint32_t g, int stage,
                                                             uint32_t b, uint32_t A1, uint32_t m, uint32_t tiles,
@@ -410,12 +410,12 @@ __global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restr
   uint32_t* cnt = lds;
   uint32_t* start = lds + tiles;
   uint32_t* sorted = lds + 2 * tiles;
-  const uint32_t* s1 = s1g;
-  if (stage) {
-    uint32_t* s = sorted + kDeferChunk;
-    for (uint32_t i = threadIdx.x; i < g; i += kDeferBlock) s[i] = s1g[i];
-    s1 = s;
-  }
+  // the seeds from LDS when staged (a pointer that may point to either makes
+  // every seed read a flat load, waited for one at a time)
+  uint32_t* s1l = sorted + kDeferChunk;
+  if (STAGE)
+    for (uint32_t i = threadIdx.x; i < g; i += kDeferBlock) s1l[i] = s1g[i];
+  (void)stage;
   for (uint64_t c0 = (uint64_t)blockIdx.x * kDeferChunk; c0 < n; c0 += (uint64_t)gridDim.x * kDeferChunk) {
     for (uint32_t t = threadIdx.x; t < tiles; t += kDeferBlock) cnt[t] = 0;
     __syncthreads();
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restr
         if (i < n) {
           uint32_t vidx, rho;
           bip_map(p[v].y, A1, b, vidx, rho);
-          const uint32_t pidx = reduce_m(mm3(p[v].x, s1[vidx]), m);
+          const uint32_t pidx = reduce_m(mm3(p[v].x, STAGE ? s1l[vidx] : s1g[vidx]), m);
           rec[u] = (pidx << 5) | ((rho < Lc ? rho : Lc) - 1);  // LBP1 above Lc is recorded at Lc
           r = atomicAdd(&cnt[pidx / kDeferTile], 1u);
         }
@@ -1923,7 +1923,8 @@ int vbdr_scan_slice(vbdr_sketch* sk, const uint32_t* pairs_dev, uint64_t n, void
     VBDR_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, sk->device));
     const int stage_s1 = base_lds + (size_t)sk->g * 4 + 1024 <= (size_t)lds_max;
     const uint32_t dgrid = grid_cap(sk, (n + kDeferChunk - 1) / kDeferChunk, 1);
-    auto kern = sk->layout == VBDR_LAYOUT_FAST ? k_scan_defer<true> : k_scan_defer<false>;
+    auto kern = sk->layout == VBDR_LAYOUT_FAST ? (stage_s1 ? k_scan_defer<true, true> : k_scan_defer<true, false>)
+                                               : (stage_s1 ? k_scan_defer<false, true> : k_scan_defer<false, false>);
     hipLaunchKernelGGL(kern, dim3(dgrid), dim3(kDeferBlock), base_lds + (stage_s1 ? (size_t)sk->g * 4 : 0), st, p, n,
                        sk->s1, sk->g, stage_s1, sk->b, sk->A1, m32, sk->def_tiles, sk->def_cap, sk->def_rec,
                        sk->def_fill, sk->dr, sk->mstride, sk->seen, sk->wstride, sk->Lc, sk->bits, sk->z);
