@@ -398,6 +398,12 @@ def main():
                    "state_bytes": int(info.state_bytes)},
         "hosts_per_s": float(np.sum(timed_active) / (np.sum(kms["estimate"]) * 1e-3)),
         "scan_pairs_per_s": w.pairs_per_slice / (avg["scan"] * 1e-3),
+        # the scan step against the HBM peak: algorithmic bytes per pair (pair + state update)
+        "scan_roofline": {"achieved": round(algorithmic_bytes("scan", w, args.layout, L, units, sk.dr_bits)
+                                            / (avg["scan"] * 1e-3) / 1e9, 2),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(algorithmic_bytes("scan", w, args.layout, L, units, sk.dr_bits)
+                                        / (avg["scan"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
         "roofline": roofline,
     }
