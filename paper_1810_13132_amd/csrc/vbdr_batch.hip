@@ -76,14 +76,22 @@ __global__ __launch_bounds__(kBBlock) void k_batch_scan(const BatchDesc* __restr
     const uint64_t lo = (uint64_t)(item - starts[s]) * tile;
     const uint64_t hi = lo + tile < D.n_pairs ? lo + tile : D.n_pairs;
     const u32x2* pairs = reinterpret_cast<const u32x2*>(D.pairs);
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBBlock) {
-      const u32x2 p = __builtin_nontemporal_load(pairs + i);
+    constexpr int kPer = 8;  // pairs per thread at a time: their loads and state reads overlap
+    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)kPer * kBBlock) {
+      u32x2 p[kPer];
+      bool ok[kPer];
+#pragma unroll
+      for (int v = 0; v < kPer; ++v) {
+        const uint64_t i = i0 + (uint64_t)v * kBBlock;
+        ok[v] = i < hi;
+        p[v] = ok[v] ? __builtin_nontemporal_load(pairs + i) : u32x2{0u, 0u};
+      }
       if (D.layout == VBDR_LAYOUT_FAST) {
-        if (D.test) scan_pair<true, true>(p.x, p.y, D.s1, D.b, D.A1, D.m, D.dr, D.mstride, D.seen, D.wstride);
-        else scan_pair<true, false>(p.x, p.y, D.s1, D.b, D.A1, D.m, D.dr, D.mstride, D.seen, D.wstride);
+        if (D.test) scan_pairs<true, true, kPer>(p, ok, D.s1, D.b, D.A1, D.m, D.dr, D.mstride, D.seen, D.wstride);
+        else scan_pairs<true, false, kPer>(p, ok, D.s1, D.b, D.A1, D.m, D.dr, D.mstride, D.seen, D.wstride);
       } else {
-        if (D.test) scan_pair<false, true>(p.x, p.y, D.s1, D.b, D.A1, D.m, D.dr, D.mstride, D.seen, D.wstride);
-        else scan_pair<false, false>(p.x, p.y, D.s1, D.b, D.A1, D.m, D.dr, D.mstride, D.seen, D.wstride);
+        if (D.test) scan_pairs<false, true, kPer>(p, ok, D.s1, D.b, D.A1, D.m, D.dr, D.mstride, D.seen, D.wstride);
+        else scan_pairs<false, false, kPer>(p, ok, D.s1, D.b, D.A1, D.m, D.dr, D.mstride, D.seen, D.wstride);
       }
     }
   }

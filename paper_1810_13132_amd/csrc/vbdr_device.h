@@ -138,6 +138,41 @@ __device__ __forceinline__ void scan_pair(uint32_t aip, uint32_t bip, const uint
   }
 }
 
+// scan_pair for N pairs at once (valid where ok[v]): the state words of all N
+// are located first and, with TEST, read together, so that the N random reads
+// overlap instead of each waiting for the one before.
+template <bool FAST, bool TEST, int N>
+__device__ __forceinline__ void scan_pairs(const u32x2* p, const bool* ok, const uint32_t* s1, uint32_t b, uint32_t A1,
+                                           uint32_t m, uint8_t* dr, uint64_t mstride, uint32_t* seen,
+                                           uint64_t wstride) {
+  uint64_t off[N];
+  uint32_t bit[N];
+#pragma unroll
+  for (int v = 0; v < N; ++v) {
+    off[v] = 0;
+    bit[v] = 0;
+    if (ok[v]) {
+      uint32_t vidx, rho;
+      bip_map(p[v].y, A1, b, vidx, rho);
+      const uint32_t pidx = reduce_m(mm3(p[v].x, s1[vidx]), m);
+      off[v] = FAST ? (uint64_t)(rho - 1) * wstride + (pidx >> 5) : (uint64_t)(rho - 1) * mstride + pidx;
+      bit[v] = 1u << (pidx & 31);
+    }
+  }
+  uint32_t cur[N];
+#pragma unroll
+  for (int v = 0; v < N; ++v) cur[v] = TEST && ok[v] ? (FAST ? seen[off[v]] : (uint32_t)dr[off[v]]) : (FAST ? 0u : 1u);
+#pragma unroll
+  for (int v = 0; v < N; ++v) {
+    if (!ok[v]) continue;
+    if constexpr (FAST) {
+      if (!(cur[v] & bit[v])) atomicOr(seen + off[v], bit[v]);
+    } else {
+      if (cur[v] != 0) dr[off[v]] = 0;
+    }
+  }
+}
+
 // Advance 16 consecutive BDRs starting at `base` (a multiple of 16), planes
 // visited from LBP1 = L down to 1 with a one-plane prefetch.  Fast layout
 // (Alg. 6): slide every DR, zero the DR of the slice's highest LBP1, clear
