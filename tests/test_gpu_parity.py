@@ -283,6 +283,39 @@ def test_two_stream_schedule_matches_one_stream(V):
         assert np.array_equal(sa[key], sb[key]), key
 
 
+@pytest.mark.parametrize("g", [64, 2048, 8192])
+def test_tiled_estimate_edge_g(V, O, g):
+    """The tiled estimate at the ends of its g range: g = 64 (chunks of 64
+    hosts, half a chunk of pairs per thread unused), g = 2048 and 8192 (one
+    host spans several pair slots of every thread).  Bit-identical to the
+    partitioned and the direct gathers, and within the bar of the oracle."""
+    m, k, seed = 1 << 22, 2, 3
+    rng = np.random.default_rng(g)
+    aips = rng.integers(0, 2**32, 1500, dtype=np.uint64).astype(np.uint32)
+    sk = V.Sketch(m, g, k, seed, "small")
+    osk = O.Sketch(m, g, k, seed, LAYOUT_CODE["small"])
+    for t in range(2):
+        n = 1 << 18
+        pairs = np.stack([aips[rng.integers(0, len(aips), n)],
+                          rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
+        sk.scan_slice(_dev(V, pairs.reshape(-1)))
+        osk.scan(pairs)
+        sk.advance_slice()
+        osk.advance()
+    hosts = np.concatenate([aips, rng.integers(0, 2**32, 2049, dtype=np.uint64).astype(np.uint32)])
+    assert_estimates_close(V, O, sk, osk, hosts)
+    hd = _dev(V, hosts)
+    direct = sk.estimate_ex(hd)[0]
+    sk.set_tuning(est_binned=3)
+    assert sk.info().est_tiled == 1
+    tiled = sk.estimate(hd)
+    sk.set_tuning(est_binned=3, est_bin_hosts=2048)  # two blocks, the second ragged
+    tiled2 = sk.estimate(hd)
+    sk.set_tuning(est_binned=2)
+    part = sk.estimate(hd)
+    assert torch.equal(tiled, direct) and torch.equal(tiled2, direct) and torch.equal(part, direct)
+
+
 def test_default_estimate_by_pool_size(V):
     """Pools from 2^24 BDRs default to the LDS-tiled estimate, smaller ones to
     the partitioned one; on the same sketch the tiled, partitioned and direct
