@@ -1356,10 +1356,25 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
   const uint8_t* tl = reinterpret_cast<const uint8_t*>(tile_w);
   // the first PRE * kDeferBlock records of every run (all of it, for runs of
   // the expected length) are loaded one sub-block ahead
+  // run lengths of this tile's sub-blocks (at most 256) held in registers:
+  // lane l of every wave keeps sub-blocks l, l + 64, l + 128, l + 192, read
+  // with readlane, so no step waits for a length load before its gathers
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t fr[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t sb = 64u * q + lane;
+    const uint32_t f = sb < nsb ? fill[sb * nt + t] : 0u;
+    fr[q] = f < cap ? f : cap;
+  }
+  auto run_len = [&](uint32_t sb) -> uint32_t {
+    const uint32_t q = sb >> 6;
+    const uint32_t v = q == 0 ? fr[0] : q == 1 ? fr[1] : q == 2 ? fr[2] : fr[3];
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(sb & 63));
+  };
   uint32_t nxt[PRE], n_nxt;
   {
-    const uint32_t f = fill[t];
-    n_nxt = f < cap ? f : cap;
+    n_nxt = run_len(0);
 #pragma unroll
     for (int u = 0; u < PRE; ++u) {
       const uint32_t j = threadIdx.x + u * kDeferBlock;
@@ -1373,8 +1388,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
 #pragma unroll
     for (int u = 0; u < PRE; ++u) cur[u] = nxt[u];
     if (sbk + 1 < nsb) {
-      const uint32_t f = fill[(sbk + 1) * nt + t];
-      n_nxt = f < cap ? f : cap;
+      n_nxt = run_len(sbk + 1);
       const uint32_t* nrun = recs + ((uint64_t)(sbk + 1) * nt + t) * cap;
 #pragma unroll
       for (int u = 0; u < PRE; ++u) {
@@ -2032,6 +2046,7 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
     for (uint64_t c = 0; c < n_hosts; c += B) {
       const uint32_t nh = (uint32_t)(n_hosts - c < B ? n_hosts - c : B);
       const uint32_t nsb = (nh + kTileSub - 1) / kTileSub;
+      if (nsb > 256) return vbdr_fail(VBDR_EINVAL, "tiled estimate: more than 256 sub-blocks in a block");  // pass 2 holds 256 run lengths
       hipLaunchKernelGGL(k_est_tile_clear, dim3(grid_cap(sk, ((uint64_t)nsb * nt + 2ull * nh + 255) / 256, 4)),
                          dim3(256), 0, st, sk->tl_fill, (uint64_t)nsb * nt, reinterpret_cast<uint32_t*>(sk->tl_ovf),
                          (uint64_t)nh * 2);
