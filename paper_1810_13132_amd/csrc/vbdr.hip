@@ -1354,8 +1354,6 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
   const uint32_t* src = reinterpret_cast<const uint32_t*>(reg4 + tbase / 2);
   for (uint64_t q = threadIdx.x; q < nbytes / 4; q += kDeferBlock) tile_w[q] = src[q];
   const uint8_t* tl = reinterpret_cast<const uint8_t*>(tile_w);
-  // the first PRE * kDeferBlock records of every run (all of it, for runs of
-  // the expected length) are loaded one sub-block ahead
   // run lengths of this tile's sub-blocks (at most 256) held in registers:
   // lane l of every wave keeps sub-blocks l, l + 64, l + 128, l + 192, read
   // with readlane, so no step waits for a length load before its gathers
@@ -1372,6 +1370,8 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     const uint32_t v = q == 0 ? fr[0] : q == 1 ? fr[1] : q == 2 ? fr[2] : fr[3];
     return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(sb & 63));
   };
+  // the first PRE * kDeferBlock records of every run (all of it, for runs of
+  // the expected length) are loaded one sub-block ahead
   uint32_t nxt[PRE], n_nxt;
   {
     n_nxt = run_len(0);
