@@ -577,7 +577,8 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __rest
                                                                 uint8_t* __restrict__ reg, uint8_t* __restrict__ reg4,
                                                                 uint64_t m, unsigned long long* __restrict__ hist,
                                                                 const uint32_t* __restrict__ recs,
-                                                                unsigned long long* __restrict__ fill, uint32_t cap) {
+                                                                unsigned long long* __restrict__ fill, uint32_t cap,
+                                                                uint32_t tiles, uint32_t* __restrict__ sat) {
   extern __shared__ uint32_t pm[];
   __shared__ uint32_t lh[kDeferBlock / 64][kBins];
   const uint32_t tile = blockIdx.x;
@@ -586,6 +587,8 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __rest
   if (lane < kBins) lh[wave][lane] = 0;
   const unsigned long long f = fill[tile];
   const uint32_t n = f < cap ? (uint32_t)f : cap;
+  // the saturation masks hold only if no DR changed outside the advance since the last one
+  const bool sat_ok = sat != nullptr && fill[tiles] == 0;
   __syncthreads();
   if (threadIdx.x == 0) fill[tile] = 0;  // every thread has read it
   const uint32_t* r = recs + (uint64_t)tile * cap;
@@ -594,17 +597,27 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __rest
   const uint64_t w = (uint64_t)tile * kDeferWords + threadIdx.x;
   if (w < wstride) {
     uint32_t R[8] = {0, 0, 0, 0, 0, 0, 0, 0}, done = 0;
+    // bit rr-1: the 32 DR[rr] were all 2^z - 1 after the last advance; with no
+    // record of this slice they still are and stay so: not loaded, not stored
+    const uint32_t sat_in = sat_ok ? sat[w] : 0u;
+    uint32_t sat_out = 0;
+    auto skip = [&](int rr) -> bool {
+      return ((sat_in >> (rr - 1)) & 1u) && pm[(uint32_t)(rr - 1) * kDeferWords + threadIdx.x] == 0u;
+    };
     uint32_t dn[8];  // the next recorder's words load while this one is processed
+    const bool skip_top = skip((int)Lc);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) dn[b] = (uint32_t)b < z ? bits[((uint64_t)(Lc - 1) * z + b) * wstride + w] : 0u;
+    for (int b = 0; b < 8; ++b)
+      dn[b] = (uint32_t)b < z ? (skip_top ? ~0u : bits[((uint64_t)(Lc - 1) * z + b) * wstride + w]) : 0u;
     for (int rr = (int)Lc; rr >= 1; --rr) {
       const uint64_t pb = (uint64_t)(rr - 1) * z;
       uint32_t d[8], o[8];  // o: the words as loaded
 #pragma unroll
       for (int b = 0; b < 8; ++b) d[b] = o[b] = dn[b];
       if (rr > 1) {
+        const bool sk = skip(rr - 1);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) dn[b] = (uint32_t)b < z ? bits[(pb - z + b) * wstride + w] : 0u;
+        for (int b = 0; b < 8; ++b) dn[b] = (uint32_t)b < z ? (sk ? ~0u : bits[(pb - z + b) * wstride + w]) : 0u;
       }
       const uint32_t set = pm[(uint32_t)(rr - 1) * kDeferWords + threadIdx.x];
 #pragma unroll
@@ -637,7 +650,13 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __rest
         carry = t;
         if (d[b] != o[b]) bits[(pb + b) * wstride + w] = d[b];  // saturated, unset words stay as they are
       }
+      uint32_t all = ~0u;
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        if ((uint32_t)b < z) all &= d[b];
+      if (all == ~0u) sat_out |= 1u << (rr - 1);
     }
+    if (sat) sat[w] = sat_out;
     const uint64_t base = w * 32;
     *reinterpret_cast<u32x4*>(reg + base) = u32x4{R[0], R[1], R[2], R[3]};
     *reinterpret_cast<u32x4*>(reg + base + 16) = u32x4{R[4], R[5], R[6], R[7]};
@@ -1728,7 +1747,7 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
 
         (def_bytes && hipMalloc(&sk->def_rec, (uint64_t)sk->def_tiles * sk->def_cap * 4) != hipSuccess) ||
         (def_bytes && hipMalloc(&sk->def_fill, (uint64_t)(sk->def_tiles + 1) * 8) != hipSuccess) ||
-        (def_bytes && dr_bytes && hipMalloc(&sk->sat, sk->wstride * 4) != hipSuccess)) {
+        (def_bytes && hipMalloc(&sk->sat, sk->wstride * 4) != hipSuccess)) {
       (void)hipGetLastError();
       rc = vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed",
                 (unsigned long long)(dr_bytes + seen_bytes + sk->mstride * 3 / 2 + part_bytes));
@@ -1995,8 +2014,10 @@ int vbdr_advance_slice(vbdr_sketch* sk, void* stream) {
   if (sk->layout == VBDR_LAYOUT_PACKED) {
     hipLaunchKernelGGL(k_advance_packed, dim3(sk->def_tiles), dim3(kDeferBlock), (size_t)sk->Lc * kDeferWords * 4, st,
                        sk->bits, sk->wstride, sk->z, sk->Lc, sk->k, sk->reg, sk->reg4, sk->m, sk->hist, sk->def_rec,
-                       sk->def_fill, sk->def_cap);
+                       sk->def_fill, sk->def_cap, sk->def_tiles, sk->sat);
     VBDR_LAUNCHED("k_advance_packed");
+    hipLaunchKernelGGL(k_defer_flag, dim3(1), dim3(64), 0, st, sk->def_fill, sk->def_tiles, 0ull);
+    VBDR_LAUNCHED("k_defer_flag");
     sk->t++;
     return VBDR_OK;
   }

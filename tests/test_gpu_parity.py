@@ -457,10 +457,10 @@ def test_resume_from_exported_state(V, O):
     assert_state_equal(b.state(), a.state(), "fast", "resumed vs continuous")
 
 
-@pytest.mark.parametrize("layout", ["fast", "small"])
+@pytest.mark.parametrize("layout", ["fast", "small", "packed"])
 def test_import_over_saturated_planes(V, O, layout):
-    """The deferred advance skips planes it found saturated (all 255) last
-    time.  Importing a state into a sketch that has run (its masks say
+    """The deferred advance skips planes it found saturated (all 255, or
+    2^z - 1 for the packed layout) last time.  Importing a state into a sketch that has run (its masks say
     saturated where the imported DRs are not), flushing pending records on
     export, and overflowing record runs all change DRs outside the advance;
     each must make the next advance read every plane.  Checked against the
@@ -473,11 +473,12 @@ def test_import_over_saturated_planes(V, O, layout):
         return np.stack([aips[rng.integers(0, len(aips), n)],
                          rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
 
-    a = V.Sketch(m, g, k, 9, layout)
+    Lc = 24 if layout == "packed" else 0  # L = 27 at g = 64: the top recorders merge
+    a = V.Sketch(m, g, k, 9, layout, Lc=Lc)
     a.scan_slice(_dev(V, slice_pairs(1 << 16).reshape(-1)))
     a.advance_slice()  # most planes of most groups saturated
-    src = V.Sketch(m, g, k, 9, layout)
-    osk = O.Sketch(m, g, k, 9, LAYOUT_CODE[layout])
+    src = V.Sketch(m, g, k, 9, layout, Lc=Lc)
+    osk = O.Sketch(m, g, k, 9, O.GPACKED if layout == "packed" else LAYOUT_CODE[layout], Lc=Lc)
     for t in range(3):
         p_ = slice_pairs(1 << 19)
         src.scan_slice(_dev(V, p_.reshape(-1)))
