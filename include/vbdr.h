@@ -132,7 +132,10 @@ int vbdr_advance_slice(vbdr_sketch *sk, void *stream);
  * Computed in FP64, stored as FP32 (round to nearest).  Before the first
  * advance every estimate is 0.
  * hosts_dev: device array of n_hosts uint32 addresses; out_dev: device
- * array of n_hosts float.  n_hosts = 0 is a no-op.
+ * array of n_hosts float.  n_hosts = 0 is a no-op.  The estimate's
+ * workspaces belong to the sketch: two estimates of one sketch must not run
+ * concurrently (order them on one stream or with events); an estimate may
+ * run beside the next slice's scan, which touches none of its buffers.
  */
 int vbdr_estimate(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_hosts, float *out_dev, void *stream);
 
