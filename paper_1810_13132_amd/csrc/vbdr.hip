@@ -1390,29 +1390,35 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(sb & 63));
   };
   // the first PRE * kDeferBlock records of every run (all of it, for runs of
-  // the expected length) are loaded one sub-block ahead
-  uint32_t nxt[PRE], n_nxt;
+  // the expected length) are loaded one sub-block ahead, as whole quads: quad
+  // threadIdx.x + q * kDeferBlock of the run (runs hold whole quads).  One
+  // 16-byte load per quad instead of four 4-byte loads: pass 2 -3 % at g =
+  // 1024, -16 % at g = 2048.
+  static_assert(PRE % 4 == 0, "the prefetch holds whole quads");
+  constexpr int PQ = PRE / 4;
+  u32x4 nxt[PQ];
+  uint32_t n_nxt;
   {
     n_nxt = run_len(0);
 #pragma unroll
-    for (int u = 0; u < PRE; ++u) {
-      const uint32_t j = threadIdx.x + u * kDeferBlock;
-      nxt[u] = j < n_nxt ? recs[(uint64_t)t * cap + j] : ~0u;
+    for (int q = 0; q < PQ; ++q) {
+      const uint32_t j = 4 * (threadIdx.x + q * kDeferBlock);
+      nxt[q] = j < n_nxt ? *reinterpret_cast<const u32x4*>(recs + (uint64_t)t * cap + j) : u32x4{~0u, ~0u, ~0u, ~0u};
     }
   }
   for (uint32_t sbk = 0; sbk < nsb; ++sbk) {
     unsigned long long* acc = acc2[sbk & 1];
-    uint32_t cur[PRE];
+    u32x4 cur[PQ];
     const uint32_t n = n_nxt;
 #pragma unroll
-    for (int u = 0; u < PRE; ++u) cur[u] = nxt[u];
+    for (int q = 0; q < PQ; ++q) cur[q] = nxt[q];
     if (sbk + 1 < nsb) {
       n_nxt = run_len(sbk + 1);
       const uint32_t* nrun = recs + ((uint64_t)(sbk + 1) * nt + t) * cap;
 #pragma unroll
-      for (int u = 0; u < PRE; ++u) {
-        const uint32_t j = threadIdx.x + u * kDeferBlock;
-        nxt[u] = j < n_nxt ? nrun[j] : ~0u;
+      for (int q = 0; q < PQ; ++q) {
+        const uint32_t j = 4 * (threadIdx.x + q * kDeferBlock);
+        nxt[q] = j < n_nxt ? *reinterpret_cast<const u32x4*>(nrun + j) : u32x4{~0u, ~0u, ~0u, ~0u};
       }
     }
     if (sbk == 0) __syncthreads();  // the tile and the zeroed accumulators
@@ -1422,14 +1428,20 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     // run to whole quads (and marks prefetch slots past its end).
     uint32_t wide = 0;
 #pragma unroll
-    for (int u = 0; u < PRE; ++u) {
-      if (cur[u] != ~0u) {
-        const uint32_t off = cur[u] >> kTileSlotBits;
-        const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
-        if (nib < 15u)
-          atomicAdd(&acc[cur[u] & (kTileSub - 1)], sum_term(nib));
-        else
-          wide |= 1u << u;
+    for (int q = 0; q < PQ; ++q) {
+      uint32_t nib[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t off = cur[q][e] != ~0u ? cur[q][e] >> kTileSlotBits : 0u;  // padding reads offset 0
+        const uint32_t v = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
+        nib[e] = cur[q][e] != ~0u ? v : 16u;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (nib[e] < 15u)
+          atomicAdd(&acc[cur[q][e] & (kTileSub - 1)], sum_term(nib[e]));
+        else if (nib[e] == 15u)
+          wide |= 1u << (4 * q + e);
       }
     }
     bool wide_long = false;
@@ -1446,7 +1458,10 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     if (wide) {
 #pragma unroll
       for (int u = 0; u < PRE; ++u)
-        if ((wide >> u) & 1u) atomicAdd(&acc[cur[u] & (kTileSub - 1)], sum_term(reg[tbase + (cur[u] >> kTileSlotBits)]));
+        if ((wide >> u) & 1u) {
+          const uint32_t rec = cur[u >> 2][u & 3];
+          atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(reg[tbase + (rec >> kTileSlotBits)]));
+        }
     }
     if (wide_long) {
       for (uint32_t j = threadIdx.x + PRE * kDeferBlock; j < n; j += kDeferBlock) {
