@@ -316,6 +316,42 @@ def test_tiled_estimate_edge_g(V, O, g):
     assert torch.equal(tiled, direct) and torch.equal(tiled2, direct) and torch.equal(part, direct)
 
 
+def test_tiled_estimate_high_registers(V, O):
+    """Registers of 15 and more do not fit the tiled estimate's nibble tile:
+    its gathers read them from the byte array.  Registers 0..L are planted
+    through import (a third of them 15 or more); each sampled host's register
+    histogram must be the one the oracle's getPhyIdx (Alg. 3) gives over the
+    planted registers, its raw E_s the oracle's HyperLogLog of that histogram,
+    and every estimate path must give the same bits."""
+    m, g, k, seed = 1 << 22, 256, 3, 29
+    rng = np.random.default_rng(29)
+    a = V.Sketch(m, g, k, seed, "small")
+    st = a.state()
+    reg = rng.integers(0, 15, m).astype(np.uint8)
+    hi = rng.random(m) < 0.33
+    reg[hi] = rng.integers(15, a.L + 1, int(hi.sum())).astype(np.uint8)
+    st["reg"], st["hist"] = reg, np.bincount(reg, minlength=len(st["hist"])).astype(np.uint64)
+    b = V.Sketch(m, g, k, seed, "small")
+    b.load_state(st)
+    hosts = rng.integers(0, 2**32, 3000, dtype=np.uint64).astype(np.uint32)
+    hd = _dev(V, hosts)
+    out, raw, hh = b.estimate_ex(hd)
+    raw, hh = raw.cpu().numpy(), hh.cpu().numpy()
+    osk = O.Sketch(m, g, k, seed, LAYOUT_CODE["small"])
+    for j in range(0, len(hosts), 97):
+        idx = [osk.phy_idx(int(hosts[j]), i) for i in range(g)]
+        want = np.bincount(reg[idx], minlength=hh.shape[1])
+        assert np.array_equal(hh[j], want), j
+        assert (reg[idx] >= 15).any(), j
+        np.testing.assert_allclose(raw[j], O.hll_from_hist(want, g), rtol=1e-13, atol=0)
+    for tune in ({"est_binned": 3}, {"est_binned": 3, "est_bin_cap": 40}, {"est_binned": 3, "est_bin_hosts": 2048},
+                 {"est_binned": 2}, {"est_binned": 1}):
+        b.set_tuning(**tune)
+        if tune["est_binned"] == 3:
+            assert b.info().est_tiled == 1
+        assert torch.equal(b.estimate(hd), out), tune
+
+
 def test_default_estimate_by_pool_size(V):
     """Pools from 2^24 BDRs default to the LDS-tiled estimate, smaller ones to
     the partitioned one; on the same sketch the tiled, partitioned and direct
