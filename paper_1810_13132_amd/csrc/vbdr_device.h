@@ -303,6 +303,17 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
       fold = bits & ~folded;  // only the slice's highest LBP1 is recorded
       folded |= bits;
     }
+    // 32 DRs at 255 with no record this slice stay 255, none is active and
+    // nothing is stored: the SWAR work below is skipped, by whole waves for
+    // most of the high planes.  Decided from the loaded bytes, so it holds
+    // whether or not the saturation masks were trusted.
+    if (bits == 0u && (d0[0] & d0[1] & d0[2] & d0[3] & d1[0] & d1[1] & d1[2] & d1[3]) == ~0u) {
+      sat_out |= 1u << (i - 1);
+      if (!FAST && preg)
+#pragma unroll
+        for (int w = 0; w < 8; ++w) Q[w] = (uint32_t)(i - 1) * 0x01010101u;  // no active DR: the run restarts below
+      continue;
+    }
     u32x4 nd0, nd1;
 #pragma unroll
     for (int w = 0; w < 8; ++w) {
