@@ -334,6 +334,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_advance(uint8_t* __restrict__ dr,
 // the closed state unchanged.
 
 constexpr int kDeferBlock = 1024;
+constexpr int kHistCopies = 4;  // register histograms per wave in the deferred advances (a power of two)
 constexpr int kDeferPer = 32;
 constexpr uint32_t kDeferChunk = kDeferBlock * kDeferPer;
 constexpr uint32_t kDeferWords = kDeferTile / 32;  // bit words per plane of a tile
@@ -520,11 +521,13 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
                                                                unsigned long long* __restrict__ psum,
                                                                uint32_t* __restrict__ sat) {
   extern __shared__ uint32_t pm[];
-  __shared__ uint32_t lh[kDeferBlock / 64][kBins];
+  // four copies of each wave's register histogram (lane & 3): registers crowd a
+  // few values, and lanes adding to one LDS word are served one at a time
+  __shared__ uint32_t lh[kDeferBlock / 64][kHistCopies][kBins];
   const uint32_t tile = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (uint32_t i = threadIdx.x; i < L * kDeferWords; i += kDeferBlock) pm[i] = 0;
-  if (lane < kBins) lh[wave][lane] = 0;
+  for (int i = lane; i < kHistCopies * kBins; i += 64) (&lh[wave][0][0])[i] = 0;
   const unsigned long long f = fill[tile];
   const uint32_t n = f < cap ? (uint32_t)f : cap;
   const bool use_seen = FAST && fill[tiles] != 0;
@@ -552,13 +555,14 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
                           kDeferWords, use_seen, top0, top1, R, preg, P, satw, sat_ok ? *satw : 0u);
 #pragma unroll
     for (int j = 0; j < 32; ++j)
-      if (base + j < m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
+      if (base + j < m) atomicAdd(&lh[wave][lane & (kHistCopies - 1)][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
   }
   if (!FAST && preg) add_pcsa_sum<8>(P, psum);  // every lane of the wave takes part
   __syncthreads();
   if (threadIdx.x < kBins) {
     uint32_t c = 0;
-    for (int w = 0; w < kDeferBlock / 64; ++w) c += lh[w][threadIdx.x];
+    for (int w = 0; w < kDeferBlock / 64; ++w)
+      for (int q = 0; q < kHistCopies; ++q) c += lh[w][q][threadIdx.x];
     if (c) atomicAdd(hist + threadIdx.x, (unsigned long long)c);
   }
 }
@@ -580,11 +584,13 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __rest
                                                                 unsigned long long* __restrict__ fill, uint32_t cap,
                                                                 uint32_t tiles, uint32_t* __restrict__ sat) {
   extern __shared__ uint32_t pm[];
-  __shared__ uint32_t lh[kDeferBlock / 64][kBins];
+  // four copies of each wave's register histogram (lane & 3): registers crowd a
+  // few values, and lanes adding to one LDS word are served one at a time
+  __shared__ uint32_t lh[kDeferBlock / 64][kHistCopies][kBins];
   const uint32_t tile = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (uint32_t i = threadIdx.x; i < Lc * kDeferWords; i += kDeferBlock) pm[i] = 0;
-  if (lane < kBins) lh[wave][lane] = 0;
+  for (int i = lane; i < kHistCopies * kBins; i += 64) (&lh[wave][0][0])[i] = 0;
   const unsigned long long f = fill[tile];
   const uint32_t n = f < cap ? (uint32_t)f : cap;
   // the saturation masks hold only if no DR changed outside the advance since the last one
@@ -666,12 +672,13 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __rest
     *reinterpret_cast<u32x4*>(reg4 + base / 2) = nib;
 #pragma unroll
     for (int j = 0; j < 32; ++j)
-      if (base + j < m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
+      if (base + j < m) atomicAdd(&lh[wave][lane & (kHistCopies - 1)][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
   }
   __syncthreads();
   if (threadIdx.x < kBins) {
     uint32_t c = 0;
-    for (int v = 0; v < kDeferBlock / 64; ++v) c += lh[v][threadIdx.x];
+    for (int v = 0; v < kDeferBlock / 64; ++v)
+      for (int q = 0; q < kHistCopies; ++q) c += lh[v][q][threadIdx.x];
     if (c) atomicAdd(hist + threadIdx.x, (unsigned long long)c);
   }
 }
