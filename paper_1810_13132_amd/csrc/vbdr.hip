@@ -626,6 +626,16 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_packed(uint32_t* __rest
         for (int b = 0; b < 8; ++b) dn[b] = (uint32_t)b < z ? (sk ? ~0u : bits[(pb - z + b) * wstride + w]) : 0u;
       }
       const uint32_t set = pm[(uint32_t)(rr - 1) * kDeferWords + threadIdx.x];
+      {  // 32 DRs at 2^z - 1 (>= k: inactive) with no record stay so and are not stored
+        uint32_t all = ~0u;
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+          if ((uint32_t)b < z) all &= d[b];
+        if (set == 0u && all == ~0u) {
+          sat_out |= 1u << (rr - 1);
+          continue;
+        }
+      }
 #pragma unroll
       for (int b = 0; b < 8; ++b) d[b] &= ~set;  // SetDR (Alg. 9) of the slice
       uint32_t lt = 0, eq = ~0u;                   // IsActiveDR: value < k
