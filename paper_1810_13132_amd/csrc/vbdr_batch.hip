@@ -105,7 +105,8 @@ __global__ __launch_bounds__(kBBlock) void k_batch_advance(const BatchDesc* __re
                                                            BatchHdr* __restrict__ hdr, uint32_t S) {
   __shared__ uint32_t starts[kMaxBatch];
   __shared__ uint32_t cur;
-  __shared__ uint32_t lh[kBBlock / 64][kBins];
+  // four histogram copies per wave (lane & 3): registers crowd a few values
+  __shared__ uint32_t lh[kBBlock / 64][4][kBins];
   for (uint32_t s = threadIdx.x; s < S; s += kBBlock) starts[s] = d[s].adv_item0;
   const uint32_t total = hdr->adv_total;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch_advance(const BatchDesc* __re
     // before this item's reset
     const uint32_t item = next_item(&hdr->counter[1], &cur);
     if (item >= total) break;
-    if (lane < kBins) lh[wave][lane] = 0;
+    for (int i = lane; i < 4 * kBins; i += 64) (&lh[wave][0][0])[i] = 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const uint32_t s = find_sketch(starts, S, item);
@@ -128,11 +129,12 @@ __global__ __launch_bounds__(kBBlock) void k_batch_advance(const BatchDesc* __re
       advance_group<false>(D.dr, D.mstride, D.seen, D.wstride, D.reg, D.reg4, base, D.L, bias, R);
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-      if (base + j < D.m) atomicAdd(&lh[wave][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
+      if (base + j < D.m) atomicAdd(&lh[wave][lane & 3][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
     __syncthreads();
     if (threadIdx.x < kBins) {
       uint32_t c = 0;
-      for (int w = 0; w < kBBlock / 64; ++w) c += lh[w][threadIdx.x];
+      for (int w = 0; w < kBBlock / 64; ++w)
+        for (int q = 0; q < 4; ++q) c += lh[w][q][threadIdx.x];
       if (c) atomicAdd(D.hist + threadIdx.x, (unsigned long long)c);
     }
   }

@@ -210,6 +210,14 @@ __device__ __forceinline__ void advance_group(uint8_t* dr, uint64_t mstride, uin
       fold = bits & ~folded;  // only the slice's highest LBP1 is recorded
       folded |= bits;
     }
+    // 16 DRs at 255 with no record this slice stay 255 and none is active:
+    // nothing to compute or store (decided from the loaded bytes)
+    if ((d[0] & d[1] & d[2] & d[3]) == ~0u && fold == 0u) {
+      if (!FAST && preg)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) Q[w] = (uint32_t)(i - 1) * 0x01010101u;
+      continue;
+    }
     u32x4 nd;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
