@@ -71,7 +71,7 @@ enum vbdr_layout { VBDR_LAYOUT_FAST = 0, VBDR_LAYOUT_SMALL = 1, VBDR_LAYOUT_PACK
 enum vbdr_status {
     VBDR_OK = 0,
     VBDR_EINVAL = -1, /* bad argument (range, NULL, alignment, wrong device) */
-    VBDR_ENOMEM = -2, /* device allocation failed at create */
+    VBDR_ENOMEM = -2, /* a device allocation failed (create, enable_pcsa, set_tuning) */
     VBDR_EHIP = -3,   /* a HIP runtime call or kernel launch failed */
     VBDR_ESTATE = -4  /* call not valid in the sketch's current state */
 };
@@ -296,6 +296,14 @@ int vbdr_import_state(vbdr_sketch *sk, const uint8_t *dr_host, const uint32_t *b
 
 /* Message of the calling thread's last error ("" if none).  Valid until the next call. */
 const char *vbdr_last_error(void);
+
+/*
+ * Testing aid for the out-of-memory paths: the library's device allocation
+ * that comes after `after` more successful ones fails as if the device were
+ * full, so the call that needed it returns VBDR_ENOMEM; after < 0 cancels.
+ * Process-wide (one counter for every thread and device).  Returns VBDR_OK.
+ */
+int vbdr_test_fail_alloc(int64_t after);
 
 /* ------------------------------------------------------------------------
  * Learned estimator (an addition beside the paper's estimate, not from it).

@@ -16,6 +16,7 @@
 // scanned (pidx < m), keep DR = 255 and register 0, and are not counted.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -50,6 +51,27 @@ static vbdr_tuning default_tuning(int layout, uint64_t m) {
 namespace {
 thread_local std::string g_err;
 }  // namespace
+
+namespace {
+// allocations left before the one vbdr_test_fail_alloc makes fail; -1: none fails
+std::atomic<int64_t> g_allocs_before_failure{-1};
+}  // namespace
+
+hipError_t vbdr_malloc_bytes(void** p, size_t bytes) {
+  int64_t left = g_allocs_before_failure.load();
+  while (left >= 0 && !g_allocs_before_failure.compare_exchange_weak(left, left - 1)) {
+  }
+  if (left == 0) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+extern "C" int vbdr_test_fail_alloc(int64_t after) {
+  g_allocs_before_failure.store(after < 0 ? -1 : after);
+  return VBDR_OK;
+}
 
 int vbdr_fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -1676,8 +1698,8 @@ int alloc_tiled(vbdr_sketch* sk) {
   const uint64_t nsb = sk->tl_B / kTileSub;
   const uint64_t rec_b = nsb * sk->tl_nt * sk->tl_cap * 4, fill_b = nsb * sk->tl_nt * 4;
   const uint64_t part_b = (uint64_t)sk->tl_nt * sk->tl_B * 4, ovf_b = (uint64_t)sk->tl_B * 8;
-  if (hipMalloc(&sk->tl_rec, rec_b) != hipSuccess || hipMalloc(&sk->tl_fill, fill_b) != hipSuccess ||
-      hipMalloc(&sk->tl_part, part_b) != hipSuccess || hipMalloc(&sk->tl_ovf, ovf_b) != hipSuccess) {
+  if (vbdr_malloc(&sk->tl_rec, rec_b) != hipSuccess || vbdr_malloc(&sk->tl_fill, fill_b) != hipSuccess ||
+      vbdr_malloc(&sk->tl_part, part_b) != hipSuccess || vbdr_malloc(&sk->tl_ovf, ovf_b) != hipSuccess) {
     (void)hipGetLastError();
     for (void* q : {(void*)sk->tl_rec, (void*)sk->tl_fill, (void*)sk->tl_part, (void*)sk->tl_ovf})
       if (q) (void)hipFree(q);
@@ -1766,20 +1788,20 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
       sk->est_hc = (uint32_t)(hc / 64 * 64);
       est_bytes = 8ull * sk->est_hc * sk->est_cap * 4 + 8ull * sk->est_hc * 4 + (uint64_t)sk->est_hc * 12;
     }
-    if ((dr_bytes && hipMalloc(&sk->dr, dr_bytes) != hipSuccess) ||
-        (bits_bytes && hipMalloc(&sk->bits, bits_bytes) != hipSuccess) || hipMalloc(&sk->reg, sk->mstride) != hipSuccess ||
-        hipMalloc(&sk->reg4, sk->mstride / 2) != hipSuccess ||
-        hipMalloc(&sk->hist, 64 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&sk->s1, (uint64_t)g * 4) != hipSuccess ||
-        (seen_bytes && hipMalloc(&sk->seen, seen_bytes) != hipSuccess) ||
-        (part_bytes && hipMalloc(&sk->part_u, (uint64_t)sk->parts * kPartChunk * 8) != hipSuccess) ||
-        (part_bytes && hipMalloc(&sk->part_v, (uint64_t)sk->parts * kPartChunk * 4) != hipSuccess) ||
-        hipMalloc(&sk->hist_ws, (uint64_t)sk->parts * kLearnChunk * kBins * 4) != hipSuccess ||
-        hipMalloc(&sk->est_ws, (uint64_t)kLearnChunk * 4) != hipSuccess ||
+    if ((dr_bytes && vbdr_malloc(&sk->dr, dr_bytes) != hipSuccess) ||
+        (bits_bytes && vbdr_malloc(&sk->bits, bits_bytes) != hipSuccess) || vbdr_malloc(&sk->reg, sk->mstride) != hipSuccess ||
+        vbdr_malloc(&sk->reg4, sk->mstride / 2) != hipSuccess ||
+        vbdr_malloc(&sk->hist, 64 * sizeof(unsigned long long)) != hipSuccess ||
+        vbdr_malloc(&sk->s1, (uint64_t)g * 4) != hipSuccess ||
+        (seen_bytes && vbdr_malloc(&sk->seen, seen_bytes) != hipSuccess) ||
+        (part_bytes && vbdr_malloc(&sk->part_u, (uint64_t)sk->parts * kPartChunk * 8) != hipSuccess) ||
+        (part_bytes && vbdr_malloc(&sk->part_v, (uint64_t)sk->parts * kPartChunk * 4) != hipSuccess) ||
+        vbdr_malloc(&sk->hist_ws, (uint64_t)sk->parts * kLearnChunk * kBins * 4) != hipSuccess ||
+        vbdr_malloc(&sk->est_ws, (uint64_t)kLearnChunk * 4) != hipSuccess ||
 
-        (def_bytes && hipMalloc(&sk->def_rec, (uint64_t)sk->def_tiles * sk->def_cap * 4) != hipSuccess) ||
-        (def_bytes && hipMalloc(&sk->def_fill, (uint64_t)(sk->def_tiles + 1) * 8) != hipSuccess) ||
-        (def_bytes && hipMalloc(&sk->sat, sk->wstride * 4) != hipSuccess)) {
+        (def_bytes && vbdr_malloc(&sk->def_rec, (uint64_t)sk->def_tiles * sk->def_cap * 4) != hipSuccess) ||
+        (def_bytes && vbdr_malloc(&sk->def_fill, (uint64_t)(sk->def_tiles + 1) * 8) != hipSuccess) ||
+        (def_bytes && vbdr_malloc(&sk->sat, sk->wstride * 4) != hipSuccess)) {
       (void)hipGetLastError();
       rc = vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed",
                 (unsigned long long)(dr_bytes + seen_bytes + sk->mstride * 3 / 2 + part_bytes));
@@ -1913,7 +1935,7 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
   if (tuning->scan_defer) sk->tune.scan_defer = tuning->scan_defer;
   // workspaces of the binned variants, on first selection
   if (sk->tune.scan_binned == 1 && sk->bin_ok && !sk->bins) {
-    if (hipMalloc(&sk->bins, 8ull * kBinCap * 4) != hipSuccess || hipMalloc(&sk->bin_fill, 64) != hipSuccess) {
+    if (vbdr_malloc(&sk->bins, 8ull * kBinCap * 4) != hipSuccess || vbdr_malloc(&sk->bin_fill, 64) != hipSuccess) {
       (void)hipGetLastError();
       if (sk->bins) (void)hipFree(sk->bins);
       sk->bins = nullptr;
@@ -1923,9 +1945,9 @@ int vbdr_sketch_set_tuning(vbdr_sketch* sk, const vbdr_tuning* tuning) {
   }
   if (sk->tune.est_binned == 1 && sk->est_ok && !sk->est_slots) {
     const uint64_t slots = 8ull * sk->est_hc * sk->est_cap * 4, cnt = 8ull * sk->est_hc * 4;
-    if (hipMalloc(&sk->est_slots, slots) != hipSuccess || hipMalloc(&sk->est_cnt, cnt) != hipSuccess ||
-        hipMalloc(&sk->ovf_u, (uint64_t)sk->est_hc * 8) != hipSuccess ||
-        hipMalloc(&sk->ovf_v, (uint64_t)sk->est_hc * 4) != hipSuccess) {
+    if (vbdr_malloc(&sk->est_slots, slots) != hipSuccess || vbdr_malloc(&sk->est_cnt, cnt) != hipSuccess ||
+        vbdr_malloc(&sk->ovf_u, (uint64_t)sk->est_hc * 8) != hipSuccess ||
+        vbdr_malloc(&sk->ovf_v, (uint64_t)sk->est_hc * 4) != hipSuccess) {
       (void)hipGetLastError();
       for (void* q : {(void*)sk->est_slots, (void*)sk->est_cnt, (void*)sk->ovf_u, (void*)sk->ovf_v})
         if (q) (void)hipFree(q);
@@ -2188,15 +2210,12 @@ int vbdr_enable_pcsa(vbdr_sketch* sk, int on) {
   if (int rc = vbdr_check_device(sk)) return rc;
   VBDR_HIP(hipDeviceSynchronize());
   if (on && !sk->preg) {
-    if (hipMalloc(&sk->preg, sk->mstride) != hipSuccess || hipMalloc(&sk->psum, 8) != hipSuccess) {
+    if (vbdr_malloc(&sk->preg, sk->mstride) != hipSuccess || vbdr_malloc(&sk->psum, 8) != hipSuccess) {
       (void)hipGetLastError();
       if (sk->preg) (void)hipFree(sk->preg);
-  if (sk->tl_rec) (void)hipFree(sk->tl_rec);
-  if (sk->tl_fill) (void)hipFree(sk->tl_fill);
-  if (sk->tl_part) (void)hipFree(sk->tl_part);
-  if (sk->tl_ovf) (void)hipFree(sk->tl_ovf);
-      sk->preg = nullptr;
-      return vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed", (unsigned long long)sk->mstride);
+      if (sk->psum) (void)hipFree(sk->psum);
+      sk->preg = nullptr, sk->psum = nullptr;
+      return vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed", (unsigned long long)sk->mstride + 8);
     }
     sk->bytes += sk->mstride + 8;
   } else if (!on && sk->preg) {

@@ -246,7 +246,7 @@ int vbdr_batch_create(uint32_t n_sketches, const vbdr_batch_params* params, vbdr
     }
     if (rc != VBDR_OK) break;
     const size_t tb = table_bytes(n_sketches);
-    if (hipMalloc(&bt->desc_dev, tb) != hipSuccess || hipHostMalloc(&bt->staging[0], tb) != hipSuccess ||
+    if (vbdr_malloc(&bt->desc_dev, tb) != hipSuccess || hipHostMalloc(&bt->staging[0], tb) != hipSuccess ||
         hipHostMalloc(&bt->staging[1], tb) != hipSuccess) {
       rc = vbdr_fail(VBDR_ENOMEM, "batch table allocation failed");
       break;

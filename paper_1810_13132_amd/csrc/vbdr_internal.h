@@ -76,6 +76,14 @@ constexpr uint64_t kPackedMaxM = 1ull << 26;  // packed pools: records' tiles mu
 // Records the calling thread's error message and returns code.
 int vbdr_fail(int code, const char* fmt, ...);
 
+// hipMalloc for every device allocation of the library, so that
+// vbdr_test_fail_alloc can make a chosen one fail.
+hipError_t vbdr_malloc_bytes(void** p, size_t bytes);
+template <class T>
+inline hipError_t vbdr_malloc(T** p, size_t bytes) {
+  return vbdr_malloc_bytes(reinterpret_cast<void**>(p), bytes);
+}
+
 #define VBDR_HIP(call)                                                                         \
   do {                                                                                         \
     hipError_t e_ = (call);                                                                    \

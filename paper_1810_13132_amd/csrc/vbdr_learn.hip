@@ -420,7 +420,7 @@ int vbdr_mlp_create(const float* params_host, const float* env_lo, const float* 
   }
   vbdr_mlp* mlp = new (std::nothrow) vbdr_mlp();
   if (!mlp) return vbdr_fail(VBDR_ENOMEM, "host allocation failed");
-  if (hipGetDevice(&mlp->device) != hipSuccess || hipMalloc(&mlp->dev, sizeof(MlpDev)) != hipSuccess) {
+  if (hipGetDevice(&mlp->device) != hipSuccess || vbdr_malloc(&mlp->dev, sizeof(MlpDev)) != hipSuccess) {
     delete mlp;
     return vbdr_fail(VBDR_ENOMEM, "device allocation of the MLP failed");
   }
@@ -500,9 +500,9 @@ int vbdr_trainer_create(const float* params_host, float lr, vbdr_trainer** out) 
   std::memset(tr, 0, sizeof(*tr));
   tr->lr = lr, tr->beta1 = 0.9f, tr->beta2 = 0.999f, tr->eps = 1e-8f;
   const size_t bytes = kParams * sizeof(float);
-  if (hipGetDevice(&tr->device) != hipSuccess || hipMalloc(&tr->params, bytes) != hipSuccess ||
-      hipMalloc(&tr->grads, bytes) != hipSuccess || hipMalloc(&tr->m1, bytes) != hipSuccess ||
-      hipMalloc(&tr->m2, bytes) != hipSuccess) {
+  if (hipGetDevice(&tr->device) != hipSuccess || vbdr_malloc(&tr->params, bytes) != hipSuccess ||
+      vbdr_malloc(&tr->grads, bytes) != hipSuccess || vbdr_malloc(&tr->m1, bytes) != hipSuccess ||
+      vbdr_malloc(&tr->m2, bytes) != hipSuccess) {
     vbdr_trainer_destroy(tr);
     return vbdr_fail(VBDR_ENOMEM, "device allocation of the trainer failed");
   }

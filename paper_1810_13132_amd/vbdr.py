@@ -63,7 +63,7 @@ EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_creat
            "vbdr_trainer_params", "vbdr_batch_create", "vbdr_batch_destroy", "vbdr_batch_sketch",
            "vbdr_batch_set_tuning", "vbdr_batch_get_tuning", "vbdr_batch_step", "vbdr_select_hosts",
            "vbdr_export_now", "vbdr_import_now", "vbdr_now_max", "vbdr_enable_pcsa", "vbdr_estimate_kind",
-           "vbdr_export_pcsa"]
+           "vbdr_export_pcsa", "vbdr_test_fail_alloc"]
 VOID_EXPORTS = ("vbdr_sketch_destroy", "vbdr_last_error", "vbdr_mlp_destroy", "vbdr_trainer_destroy",
                 "vbdr_batch_destroy", "vbdr_batch_sketch")
 MLP_IN, MLP_PARAMS = 67, 8577
@@ -117,6 +117,7 @@ def lib():
         L.vbdr_now_max.argtypes = [vp, vp, vp, u64, vp]
         L.vbdr_batch_step.argtypes = [vp, C.POINTER(vp), C.POINTER(u64), C.POINTER(vp), C.POINTER(u64),
                                       C.POINTER(vp), vp]
+        L.vbdr_test_fail_alloc.argtypes = [C.c_int64]
         L.vbdr_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name in VOID_EXPORTS:
@@ -353,6 +354,12 @@ def select_hosts(est: torch.Tensor, hosts: torch.Tensor, threshold: float, cap: 
     c = int(cnt.item())
     k = min(c, cap)
     return oh[:k], oe[:k], c
+
+
+def fail_allocation_after(n: int):
+    """Testing aid: the library's device allocation after n more successful
+    ones fails (VBDR_ENOMEM); n < 0 cancels."""
+    _check(lib().vbdr_test_fail_alloc(int(n)))
 
 
 def to_device_u32(a: np.ndarray, device="cuda") -> torch.Tensor:

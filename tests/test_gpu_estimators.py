@@ -85,3 +85,41 @@ def test_loglog_on_fast_layout_and_pcsa_refused(V, O):
         sk.enable_pcsa(True)
     with pytest.raises(V.VbdrError):
         sk.estimate_kind(V.to_device_u32(aips), "pcsa")
+
+
+def test_failed_pcsa_allocation_leaves_sketch_whole(V):
+    """An out-of-memory failure while enabling PCSA runs (either of its two
+    allocations) returns VBDR_ENOMEM and leaves the sketch as it was: the
+    LDS-tiled estimate's workspaces stay allocated and give the same
+    estimates, PCSA stays off, and enabling it again afterwards works."""
+    m, g, k = 1 << 24, 1024, 4
+    rng = np.random.default_rng(77)
+    aips = rng.integers(0, 2**32, 2000, dtype=np.uint64).astype(np.uint32)
+    sk = V.Sketch(m, g, k, 3, "small")
+    assert sk.info().est_tiled == 1
+    n = 1 << 20
+    pairs = np.stack([aips[rng.integers(0, len(aips), n)],
+                      rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
+    sk.scan_slice(V.to_device_u32(pairs.reshape(-1)))
+    sk.advance_slice()
+    hd = V.to_device_u32(aips)
+    before = sk.estimate(hd)
+    bytes0 = sk.info().state_bytes
+    try:
+        for after in (0, 1):  # the run array, then the pool sum
+            V.fail_allocation_after(after)
+            with pytest.raises(V.VbdrError) as e:
+                sk.enable_pcsa(True)
+            assert e.value.code == -2
+            V.fail_allocation_after(-1)
+            assert sk.info().state_bytes == bytes0 and sk.info().est_tiled == 1
+            assert torch.equal(sk.estimate(hd), before)
+            with pytest.raises(V.VbdrError) as e:
+                sk.estimate_kind(hd, "pcsa")
+            assert e.value.code == -4
+    finally:
+        V.fail_allocation_after(-1)
+    sk.enable_pcsa(True)
+    sk.advance_slice()
+    assert sk.estimate_kind(hd, "pcsa").shape == (len(aips),)
+    sk.close()
