@@ -58,6 +58,10 @@ def lib():
         L.vbdro_hll_from_hist.argtypes = [vp, C.c_double]
         L.vbdro_estimate.restype = None
         L.vbdro_estimate.argtypes = [vp, vp, u64, vp, vp, vp]
+        L.vbdro_estimate_registers.restype = C.c_int
+        L.vbdro_estimate_registers.argtypes = [u64, u32, u64, vp, vp, u64, vp, vp, vp]
+        L.vbdro_replay_state.restype = None
+        L.vbdro_replay_state.argtypes = [vp, u64, u32, u32, u32, u32, u32, vp, vp]
         L.vbdro_sum_lbp1.restype = u64
         L.vbdro_sum_lbp1.argtypes = [vp, u32]
         L.vbdro_loglog_alpha.restype = C.c_double
@@ -120,6 +124,28 @@ def map_pairs(m: int, g: int, hash_seed: int, pairs: np.ndarray):
     if lib().vbdro_map_pairs(m, g, hash_seed, _ptr(pairs), n, _ptr(pidx), _ptr(rho)) != 0:
         raise ValueError("bad parameters")
     return pidx, rho
+
+
+def estimate_registers(m: int, g: int, hash_seed: int, reg: np.ndarray, hosts, with_raw: bool = False,
+                       with_hist: bool = False):
+    """The estimate of Alg. 5 (histogram, HyperLogLog, noise removal) over a
+    register array reg (m uint8) given by the caller instead of a sketch's."""
+    reg = np.ascontiguousarray(reg, dtype=np.uint8).reshape(-1)
+    assert reg.shape == (m,)
+    hosts = np.ascontiguousarray(hosts, dtype=np.uint32).reshape(-1)
+    n = hosts.shape[0]
+    out = np.zeros(n, dtype=np.float32)
+    raw = np.zeros(n, dtype=np.float64)
+    hist = np.zeros((n, NBINS), dtype=np.uint32) if with_hist else None
+    if lib().vbdro_estimate_registers(m, g, hash_seed, _ptr(reg), _ptr(hosts), n, _ptr(out), _ptr(raw),
+                                      _ptr(hist)) != 0:
+        raise ValueError("bad parameters or register values")
+    res = [out]
+    if with_raw:
+        res.append(raw)
+    if with_hist:
+        res.append(hist)
+    return res[0] if len(res) == 1 else tuple(res)
 
 
 class Sketch:

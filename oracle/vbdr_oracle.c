@@ -259,11 +259,17 @@ static int IsActiveDR(uint8_t dr, uint32_t k) { return dr < k; }
 
 static uint8_t *DRV(vbdro_sketch *s, uint64_t p) { return s->drv + p * (s->L + 1); }
 
-/* Alg. 3 getPhyIdx: seed s1 from the virtual index, then hash the host. */
+/* Alg. 3 getPhyIdx: seed s1 from the virtual index, then hash the host
+ * into the pool of m BDRs. */
+static uint32_t phy_idx(uint64_t m, uint32_t A0, uint32_t aip, uint32_t i)
+{
+    uint32_t s1 = vbdro_H(i, 1ull << 32, A0);
+    return vbdro_H(aip, m, s1);
+}
+
 uint32_t vbdro_phy_idx(const vbdro_sketch *s, uint32_t aip, uint32_t i)
 {
-    uint32_t s1 = vbdro_H(i, 1ull << 32, s->A0);
-    return vbdro_H(aip, s->m, s1);
+    return phy_idx(s->m, s->A0, aip, i);
 }
 
 /* Steps shared by Alg. 4, 7 and 9: from a pair to (pidx, LBP1). */
@@ -413,21 +419,22 @@ double vbdro_hll_from_hist(const uint64_t *hist, double q)
 }
 
 /* Alg. 5 getSumLBP1, generalised from the sum of LBP1 values to their
- * histogram, then the noise-removed estimate.  hist_out (n*33, nullable)
- * receives each host's histogram; raw_es (nullable) its E_s. */
-void vbdro_estimate(vbdro_sketch *s, const uint32_t *hosts, uint64_t n, float *out, double *raw_es,
-                    uint32_t *hist_out)
+ * histogram, then the noise-removed estimate, for a pool of m registers
+ * reg[] whose histogram is pool_hist.  hist_out (n*33, nullable) receives
+ * each host's histogram; raw_es (nullable) its E_s. */
+static void estimate_hosts(uint64_t m, uint32_t g, uint32_t A0, const uint8_t *reg, const uint64_t *pool_hist,
+                           const uint32_t *hosts, uint64_t n, float *out, double *raw_es, uint32_t *hist_out)
 {
-    double Em = vbdro_hll_from_hist(s->pool_hist, (double)s->m);
+    double Em = vbdro_hll_from_hist(pool_hist, (double)m);
     for (uint64_t h = 0; h < n; h++) {
         uint64_t hist[NBINS];
         memset(hist, 0, sizeof(hist));
-        for (uint32_t i = 0; i < s->g; i++) {
-            uint32_t pidx = vbdro_phy_idx(s, hosts[h], i);
-            hist[s->reg[pidx]]++; /* the register GetLBP1BDR gave at the close */
+        for (uint32_t i = 0; i < g; i++) {
+            uint32_t pidx = phy_idx(m, A0, hosts[h], i);
+            hist[reg[pidx]]++; /* the register GetLBP1BDR gave at the close */
         }
-        double Es = vbdro_hll_from_hist(hist, (double)s->g);
-        double nh = ((double)s->m * Es - (double)s->g * Em) / ((double)s->m - (double)s->g);
+        double Es = vbdro_hll_from_hist(hist, (double)g);
+        double nh = ((double)m * Es - (double)g * Em) / ((double)m - (double)g);
         out[h] = (float)(nh > 0.0 ? nh : 0.0);
         if (raw_es)
             raw_es[h] = Es;
@@ -435,6 +442,33 @@ void vbdro_estimate(vbdro_sketch *s, const uint32_t *hosts, uint64_t n, float *o
             for (uint32_t r = 0; r < NBINS; r++)
                 hist_out[h * NBINS + r] = (uint32_t)hist[r];
     }
+}
+
+void vbdro_estimate(vbdro_sketch *s, const uint32_t *hosts, uint64_t n, float *out, double *raw_es,
+                    uint32_t *hist_out)
+{
+    estimate_hosts(s->m, s->g, s->A0, s->reg, s->pool_hist, hosts, n, out, raw_es, hist_out);
+}
+
+/* The same estimate over a register array given by the caller (m entries,
+ * each 0..32), for pools whose window state is computed another way (the
+ * closed form of the recorders).  -1 for bad parameters. */
+int vbdro_estimate_registers(uint64_t m, uint32_t g, uint64_t hash_seed, const uint8_t *reg, const uint32_t *hosts,
+                             uint64_t n, float *out, double *raw_es, uint32_t *hist_out)
+{
+    if (!is_pow2(g) || g < 2 || g > 65536u || m <= g || m >= (1ull << 32))
+        return -1;
+    uint64_t pool_hist[NBINS];
+    memset(pool_hist, 0, sizeof(pool_hist));
+    for (uint64_t p = 0; p < m; p++) {
+        if (reg[p] >= NBINS)
+            return -1;
+        pool_hist[reg[p]]++;
+    }
+    uint64_t st = hash_seed;
+    uint32_t A0 = (uint32_t)vbdro_splitmix64(&st);
+    estimate_hosts(m, g, A0, reg, pool_hist, hosts, n, out, raw_es, hist_out);
+    return 0;
 }
 
 /* LogLog constant alpha_q of Durand and Flajolet (2003),
@@ -536,4 +570,45 @@ void vbdro_get_state(const vbdro_sketch *s, uint8_t *dr, uint32_t *bs, uint8_t *
     }
     if (hist)
         memcpy(hist, s->pool_hist, sizeof(s->pool_hist));
+}
+
+/* ------------------------------------------------------------------ */
+/* Closed-form window state                                            */
+/* ------------------------------------------------------------------ */
+
+/* The pool's state from the slice of each (BDR, LBP1)'s last record, the
+ * quantity Sec. 3's DR counts from: last[p*L + r-1] = 1 + that slice, 0 if
+ * LBP1 r was never recorded at BDR p.  A DR holds base - last, saturated at
+ * sat (base = t for the fast layout, whose fold sets the DR after the
+ * slide; t + 1 for the small layout, whose slide follows the read), and the
+ * register (Alg. 2) is the largest LBP1 whose last record falls in the
+ * window, last >= lo.  With cap < L the packed layout's recorders: LBP1
+ * values cap..L share recorder cap, recorders above cap read sat.
+ * dr (m*L, nullable) and reg (m) receive the canonical state. */
+void vbdro_replay_state(const uint16_t *last, uint64_t m, uint32_t L, uint32_t cap, uint32_t sat, uint32_t base,
+                        uint32_t lo, uint8_t *dr, uint8_t *reg)
+{
+    for (uint64_t p = 0; p < m; p++) {
+        const uint16_t *row = last + p * L;
+        uint32_t top = 0;
+        for (uint32_t r = 1; r <= L; r++) {
+            uint32_t s = 0;
+            if (r < cap) {
+                s = row[r - 1];
+            } else if (r == cap) {
+                for (uint32_t q = cap; q <= L; q++) /* the merged recorder: the latest record */
+                    if (row[q - 1] > s)
+                        s = row[q - 1];
+            }
+            if (s > 0 && s >= lo)
+                top = r;
+            if (dr) {
+                uint32_t v = sat;
+                if (s > 0 && base - s < sat)
+                    v = base - s;
+                dr[p * L + (r - 1)] = (uint8_t)v;
+            }
+        }
+        reg[p] = (uint8_t)top;
+    }
 }

@@ -3,7 +3,7 @@
 Samples are (features, ln(1 + n)) of every host after every slice once the
 window is full, on streams shaped like the tiny workload (2^12 hosts, 2^20
 pairs per slice, 12 slices, m = 2^18, g = 256, k = 4): training seeds 0..99
-(10^6 samples drawn from the 368,640), evaluation seeds 100..109.  Features
+(10^6 samples drawn from the 3,686,400), evaluation seeds 100..109.  Features
 come from the library's own scan / advance / feature kernels; the truth is the
 exact distinct count of the window's pairs (Definition 1), computed on the
 device with sort-unique.  Training runs the library's float32 Adam kernels.

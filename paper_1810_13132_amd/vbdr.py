@@ -313,6 +313,13 @@ class Sketch:
                                        _stream(stream)))
         return {"dr": dr, "bs": bs, "reg": reg, "hist": hist, "t": self.t}
 
+    def registers(self, stream=None):
+        """(reg (m,) uint8, hist (33,) uint64) of the last closed window, without the DRs."""
+        reg = np.empty(self.m, dtype=np.uint8)
+        hist = np.empty(NBINS, dtype=np.uint64)
+        _check(lib().vbdr_export_state(self._h, None, None, reg.ctypes.data, hist.ctypes.data, _stream(stream)))
+        return reg, hist
+
     def load_state(self, state: dict, stream=None):
         dr = np.ascontiguousarray(state["dr"], dtype=np.uint8)
         reg = np.ascontiguousarray(state["reg"], dtype=np.uint8)
