@@ -4,11 +4,16 @@
 One step = one time slice of the line-rate workload: scan its 2^26 (aip, bip)
 pairs into the BDR pool (m = 2^26, g = 1024), advance the window (k = 60),
 and estimate every host active in the window (of 2^20 hosts).  Pairs and
-host lists are resident in HBM before timing starts.
+host lists are resident in HBM before timing starts.  The timed steps are
+slices k .. k+K-1 by default: the window is full and the pool has aged
+through k untimed slices (its steady state).  A secondary figure
+(`young_pool`) times slices W .. W+K-1 of a fresh pool.
 
-    python bench.py [--steps K] [--warmup W] [--layout small|fast]
+    python bench.py [--steps K] [--warmup W] [--layout small|fast|packed]
+                    [--workload line_rate|tiny|batched|stress]
 
 Prints one JSON line.  value = IP pairs per second through whole steps.
+Under `rocprofv3 --selected-regions` only the timed steps are profiled.
 """
 import argparse
 import hashlib
@@ -115,6 +120,31 @@ def cpu_baseline(w, layout, slice0, hosts_sample, n_active, Lc=0):
                       f"whole step (scan x{w.pairs_per_slice // S}, estimate x{n_active / len(hosts_sample):.0f})",
             "seconds": {"create": round(t_create, 3), "scan": round(t_scan, 3), "advance": round(t_adv, 3),
                         "estimate": round(t_est, 3)}}
+
+
+def scan_roofline(w, layout, ms):
+    b = algorithmic_bytes("scan", w, layout, 0, 0)
+    rate = b / (ms * 1e-3) / 1e9
+    return {"achieved": round(rate, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(rate / HBM_PEAK_GBS, 4)}
+
+
+def roctx():
+    """The region markers of rocprofv3 (rocprofiler-sdk's roctx), or None.
+    Under `rocprofv3 --selected-regions` only the code between
+    roctxProfilerResume(0) and roctxProfilerPause(0) is profiled: the timed
+    steps, not the pool's aging or the warm-up."""
+    import ctypes
+    base = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    for name in ("librocprofiler-sdk-roctx.so.1", os.path.join(base, "librocprofiler-sdk-roctx.so.1")):
+        try:
+            lib = ctypes.CDLL(name)
+        except OSError:
+            continue
+        for fn in (lib.roctxProfilerPause, lib.roctxProfilerResume):
+            fn.argtypes = [ctypes.c_uint64]
+            fn.restype = ctypes.c_int
+        return lib
+    return None
 
 
 def learned_accuracy():
@@ -252,6 +282,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--overlap", action="store_true",
                     help="scan each slice on a second stream while the previous window is estimated")
+    ap.add_argument("--first-slice", type=int, default=None,
+                    help="first timed slice (default: k, or later if the young-pool steps need room); the "
+                         "slices before it age the pool untimed")
+    ap.add_argument("--no-young", action="store_true",
+                    help="skip the secondary measurement on the young pool (slices warmup..warmup+steps-1)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -271,37 +306,56 @@ def main():
         return run_stress(args)
     w = synth.LINE_RATE if args.workload == "line_rate" else synth.TINY
     K, W = args.steps, args.warmup
-    n_slices = W + K
-    if n_slices > w.slices:
-        raise SystemExit(f"at most {w.slices} slices in this workload")
+    young = not args.no_young
+    # first timed slice of the steady-state measurement: the window of k slices
+    # is full from the close of slice k - 1 on; the pool before it is aged by
+    # untimed slices (the stream is counter-based and stationary, so slices
+    # past the workload's nominal count are the same workload)
+    S0 = args.first_slice if args.first_slice is not None else max(w.k, (W + K if young else 0) + W)
+    if S0 < W or (young and S0 < 2 * W + K):
+        raise SystemExit("--first-slice leaves no room for the warm-up (and the young-pool steps)")
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-
-    # ---- inputs: generated on the host, resident in HBM before timing
-    st = synth.Stream(w)
-    hosts_all = st.aip
-    slices_dev, active_dev, n_active = [], [], []
-    window = []
-    buf = np.empty((w.pairs_per_slice, 2), dtype=np.uint32)
-    slice0 = None
-    t0 = time.time()
-    for t in range(n_slices):
-        counts = np.zeros(w.hosts, dtype=np.uint32)
-        st.slice(t, host_pairs=counts, out=buf)
-        if t == W:
-            slice0 = buf.copy() if not args.no_cpu_baseline else None
-        slices_dev.append(vbdr.to_device_u32(buf.reshape(-1), dev))
-        window.append(counts > 0)
-        window = window[-w.k:]
-        act = np.nonzero(np.logical_or.reduce(window))[0]
-        active_dev.append(vbdr.to_device_u32(hosts_all[act], dev))
-        n_active.append(len(act))
-        log(f"slice {t}: generated and copied ({time.time() - t0:.1f}s), {len(act)} active hosts")
-    outs = [torch.empty(n, dtype=torch.float32, device=dev) for n in n_active]
+    rtx = roctx()
 
     Lc = args.packed_lc if args.layout == "packed" else 0
     sk = vbdr.Sketch(w.m, w.g, w.k, w.seed, args.layout, Lc=Lc)
     L = sk.Lc
+    info = sk.info()
+
+    # ---- inputs: generated on the host; the slices of timed and warm-up steps
+    # are resident in HBM before their timing starts, aging slices are scanned
+    # as they are generated
+    st = synth.Stream(w)
+    hosts_all = st.aip
+    resident = {}  # slice -> (pairs, active hosts, their count)
+    in_window = np.zeros(w.hosts, dtype=np.int32)  # slices of the last k with pairs of the host
+    window = []
+    buf = np.empty((w.pairs_per_slice, 2), dtype=np.uint32)
+    slice0 = None
+    n_apply = 3 if info.scan_deferred else 0  # extra slices for the record-apply measurement
+    t0 = time.time()
+
+    def generate(t, keep):
+        nonlocal slice0
+        counts = np.zeros(w.hosts, dtype=np.uint32)
+        st.slice(t, host_pairs=counts, out=buf)
+        act = counts > 0
+        in_window[act] += 1
+        window.append(act)
+        if len(window) > w.k:
+            in_window[window.pop(0)] -= 1
+        pd = vbdr.to_device_u32(buf.reshape(-1), dev)
+        if t == S0 and not args.no_cpu_baseline:
+            slice0 = buf.copy()
+        if keep:
+            hosts = np.nonzero(in_window)[0]
+            resident[t] = (pd, vbdr.to_device_u32(hosts_all[hosts], dev), len(hosts))
+        return pd
+
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream() if args.overlap else main
+    adv_done = [None]
 
     # Slice i's scan only needs slice i-1's advance (which drains the record
     # runs), not its estimate: with --overlap the scan runs on a second stream
@@ -309,16 +363,13 @@ def main():
     # the advance then waits for both.  Measured 1 % faster at the line-rate
     # workload (the two compete for the memory system), so the default keeps
     # one stream and per-stage times that are not stretched by the overlap.
-    main = torch.cuda.current_stream()
-    side = torch.cuda.Stream() if args.overlap else main
-    adv_done = [None]
-
-    def step(i, e=None):
+    def step(i, out, e=None):
+        pairs, hosts, _ = resident[i]
         if side is not main and adv_done[0] is not None:
             side.wait_event(adv_done[0])
         if e:
             e[0].record(side)
-        sk.scan_slice(slices_dev[i], stream=side)
+        sk.scan_slice(pairs, stream=side)
         if e:
             e[1].record(side)
         if side is not main:
@@ -332,31 +383,88 @@ def main():
             e[3].record(main)
         adv_done[0] = torch.cuda.Event()
         adv_done[0].record(main)
-        sk.estimate(active_dev[i], outs[i], stream=main)
+        sk.estimate(hosts, out, stream=main)
         if e:
             e[4].record(main)
 
-    for i in range(W):
-        step(i)
-    torch.cuda.synchronize()
-    log(f"warmup done ({W} steps)")
+    def measure(first, profile=False):
+        """W warm-up steps, then K timed steps from slice `first` on."""
+        outs = {i: torch.empty(resident[i][2], dtype=torch.float32, device=dev) for i in range(first - W, first + K)}
+        for i in range(first - W, first):
+            step(i, outs[i])
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
+        if profile and rtx:
+            rtx.roctxProfilerResume(0)
+        t_start = time.perf_counter()
+        for j in range(K):
+            step(first + j, outs[first + j], ev[j])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        if profile and rtx:
+            rtx.roctxProfilerPause(0)
+        kms = {"scan": [], "advance": [], "estimate": []}
+        for e in ev:
+            kms["scan"].append(e[0].elapsed_time(e[1]))
+            kms["advance"].append(e[2].elapsed_time(e[3]))
+            kms["estimate"].append(e[3].elapsed_time(e[4]))
+        for i in range(first - W, first + K):
+            del resident[i]
+        return elapsed, kms, [resident_n[i] for i in range(first, first + K)]
 
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
+    resident_n = {}
+    n_first = 0
+    res_young = None
+    if young:
+        for t in range(W + K):
+            generate(t, True)
+            resident_n[t] = resident[t][2]
+        el, kms_y, act_y = measure(W)
+        res_young = {"first_timed_slice": W, "ms_per_step": el * 1e3 / K,
+                     "kernel_ms": {k_: round(float(np.mean(v)), 4) for k_, v in kms_y.items()},
+                     "active_hosts_per_step": int(np.mean(act_y))}
+        log(f"young pool (slices {W}..{W + K - 1}): {el * 1e3 / K:.3f} ms/step")
+        n_first = W + K
+    for t in range(n_first, S0 + K + n_apply):
+        keep = t >= S0 - W
+        pd = generate(t, keep)
+        if keep:
+            resident_n[t] = resident[t][2]
+        else:  # aging: the state only, no estimate
+            sk.scan_slice(pd)
+            sk.advance_slice()
+        del pd
+        if t % 8 == 0 or keep:
+            log(f"slice {t}: generated ({time.time() - t0:.1f}s), {int(np.count_nonzero(in_window))} hosts in window"
+                + ("" if keep else " (aging)"))
     torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for j in range(K):
-        step(W + j, ev[j])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    log(f"timed {K} steps in {elapsed:.3f}s")
+    elapsed, kms, timed_active = measure(S0, profile=True)
+    log(f"timed {K} steps from slice {S0} in {elapsed:.3f}s")
 
-    kms = {"scan": [], "advance": [], "estimate": []}
-    for e in ev:
-        kms["scan"].append(e[0].elapsed_time(e[1]))
-        kms["advance"].append(e[2].elapsed_time(e[3]))
-        kms["estimate"].append(e[3].elapsed_time(e[4]))
-    avg = {k: float(np.mean(v)) for k, v in kms.items()}
-    timed_active = n_active[W:]
+    # The deferred scan's updates are applied by the next advance, from LDS:
+    # that share of the advance belongs to the scan stage.  Measured on the
+    # aged pool as the advance after a full slice's records minus the advance
+    # after an empty slice, alternating.
+    apply_ms = None
+    if n_apply:
+        ea = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(n_apply)]
+        for j in range(n_apply):
+            pairs = resident[S0 + K + j][0]
+            sk.scan_slice(pairs)
+            ea[j][0].record()
+            sk.advance_slice()
+            ea[j][1].record()
+            ea[j][2].record()
+            sk.advance_slice()
+            ea[j][3].record()
+        torch.cuda.synchronize()
+        with_rec = [e[0].elapsed_time(e[1]) for e in ea]
+        empty = [e[2].elapsed_time(e[3]) for e in ea]
+        apply_ms = max(float(np.mean(with_rec) - np.mean(empty)), 0.0)
+        log(f"advance with records {np.mean(with_rec):.4f} ms, after an empty slice {np.mean(empty):.4f} ms")
+        resident.clear()
+
+    avg = {k_: float(np.mean(v)) for k_, v in kms.items()}
     ms_per_step = elapsed * 1e3 / K
     value = w.pairs_per_slice * K / elapsed
 
@@ -395,18 +503,24 @@ def main():
                    "hosts": w.hosts, "m": w.m,
                    "g": w.g, "k": w.k, "layout": args.layout, "active_hosts_per_step": int(units),
                    **({"Lc": sk.Lc, "dr_bits": sk.dr_bits} if args.layout == "packed" else {}),
-                   "state_bytes": int(info.state_bytes)},
+                   "first_timed_slice": S0, "window_full": S0 >= w.k - 1,
+                   "state_bytes": int(info.state_bytes), "window_state_bytes": int(info.window_state_bytes),
+                   "workspace_bytes": int(info.workspace_bytes)},
         "hosts_per_s": float(np.sum(timed_active) / (np.sum(kms["estimate"]) * 1e-3)),
         "scan_pairs_per_s": w.pairs_per_slice / (avg["scan"] * 1e-3),
         # the scan step against the HBM peak: algorithmic bytes per pair (pair + state update)
-        "scan_roofline": {"achieved": round(algorithmic_bytes("scan", w, args.layout, L, units, sk.dr_bits)
-                                            / (avg["scan"] * 1e-3) / 1e9, 2),
-                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": round(algorithmic_bytes("scan", w, args.layout, L, units, sk.dr_bits)
-                                        / (avg["scan"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "scan_roofline": scan_roofline(w, args.layout, avg["scan"]),
         "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
         "roofline": roofline,
     }
+    if apply_ms is not None:
+        # deferred scans: the scan stage is the record-writing kernel plus the
+        # advance's share that applies the records
+        res["scan_apply_ms"] = round(apply_ms, 4)
+        res["scan_with_apply_pairs_per_s"] = w.pairs_per_slice / ((avg["scan"] + apply_ms) * 1e-3)
+        res["scan_with_apply_roofline"] = scan_roofline(w, args.layout, avg["scan"] + apply_ms)
+    if res_young:
+        res["young_pool"] = res_young
     acc = learned_accuracy()
     if acc:
         res["accuracy"] = acc
@@ -414,13 +528,17 @@ def main():
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
+        if rtx:
+            rtx.roctxProfilerResume(0)
         dst.copy_(src)
         torch.cuda.synchronize()
+        if rtx:
+            rtx.roctxProfilerPause(0)
         res["calibration_copy_bytes"] = src.numel() * 4
         del src, dst
     if not args.no_cpu_baseline:
         rng = np.random.default_rng(0)
-        act_last = hosts_all[np.nonzero(np.logical_or.reduce(window))[0]]
+        act_last = hosts_all[np.nonzero(in_window)[0]]
         sample = rng.choice(act_last, size=min(2048, len(act_last)), replace=False)
         log("timing the CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(w, args.layout, slice0, sample, int(units), Lc)

@@ -82,12 +82,16 @@ typedef struct vbdr_info {
     int32_t layout;       /* enum vbdr_layout */
     uint32_t A0, A1;      /* hash seeds derived from hash_seed */
     uint64_t t;           /* slices closed so far */
-    uint64_t state_bytes; /* device bytes held by the sketch */
+    uint64_t state_bytes; /* device bytes held by the sketch: window_state_bytes + workspace_bytes */
     int32_t est_parts;    /* pool ranges of the estimate's XCD-partitioned gathers (1 = direct) */
     int32_t scan_deferred; /* 1 when scans defer their updates to the advance (scan_defer = 1) */
     uint32_t Lc;          /* recorders per BDR (L except for the packed layout) */
     uint32_t dr_bits;     /* bits per DR: 8, or z for the packed layout */
     int32_t est_tiled;    /* 1 when plain estimates take the LDS-tiled path (est_binned = 3, eligible pool) */
+    uint64_t window_state_bytes; /* the window's state: DRs (byte planes or packed bit-planes), bsLBP1
+                                    bit-planes, registers (bytes and nibbles), saturation masks, pool
+                                    histogram, seeds, PCSA runs (Sec. 4.2 Table 1 counts the DRs) */
+    uint64_t workspace_bytes;    /* scratch of the hot path: deferred scan records, estimate workspaces */
 } vbdr_info;
 
 /*
@@ -212,7 +216,7 @@ int vbdr_export_now(vbdr_sketch *sk, uint8_t *now_dev, void *stream);
 int vbdr_import_now(vbdr_sketch *sk, const uint8_t *now_dev, void *stream);
 int vbdr_now_max(const uint8_t *a_dev, const uint8_t *b_dev, uint8_t *out_dev, uint64_t n, void *stream);
 
-/* Parameters and slice counter of a sketch.  Host only, no device work. *//* Parameters and slice counter of a sketch.  Host only, no device work. */
+/* Parameters and slice counter of a sketch.  Host only, no device work. */
 int vbdr_sketch_info(const vbdr_sketch *sk, vbdr_info *out);
 
 /*

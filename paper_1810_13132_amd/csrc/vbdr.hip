@@ -869,7 +869,7 @@ __global__ __launch_bounds__(kEstBlock) void k_estimate_part(const uint32_t* __r
                                                              const uint8_t* __restrict__ reg4, uint32_t parts,
                                                              uint32_t part_shift,
                                                              unsigned long long* __restrict__ part_u,
-                                                             uint32_t* __restrict__ part_v,
+                                                             uint32_t* __restrict__ part_v, uint32_t pstride,
                                                              uint32_t* __restrict__ hout) {
   extern __shared__ uint32_t s1_lds[];
   __shared__ uint32_t lh[kEstWaves][kBins];
@@ -904,8 +904,8 @@ __global__ __launch_bounds__(kEstBlock) void k_estimate_part(const uint32_t* __r
       U = wave_sum_u64(U);
       V = (uint32_t)wave_sum_u64(V);
       if (lane == 0) {
-        part_u[(uint64_t)x * kPartChunk + h] = U;
-        part_v[(uint64_t)x * kPartChunk + h] = V;
+        part_u[(uint64_t)x * pstride + h] = U;
+        part_v[(uint64_t)x * pstride + h] = V;
       }
     }
   }
@@ -914,7 +914,7 @@ __global__ __launch_bounds__(kEstBlock) void k_estimate_part(const uint32_t* __r
 __global__ __launch_bounds__(256) void k_estimate_final(uint32_t nh, uint32_t g, uint32_t m, uint32_t parts,
                                                         const unsigned long long* __restrict__ hist,
                                                         const unsigned long long* __restrict__ part_u,
-                                                        const uint32_t* __restrict__ part_v,
+                                                        const uint32_t* __restrict__ part_v, uint32_t pstride,
                                                         const unsigned long long* __restrict__ ovf_u,
                                                         const uint32_t* __restrict__ ovf_v, float* __restrict__ out) {
   __shared__ double em_sh;
@@ -928,8 +928,8 @@ __global__ __launch_bounds__(256) void k_estimate_final(uint32_t nh, uint32_t g,
   if (h >= nh) return;
   uint64_t U = 0, V = 0;
   for (uint32_t x = 0; x < parts; ++x) {
-    U += part_u[(uint64_t)x * kPartChunk + h];
-    V += part_v[(uint64_t)x * kPartChunk + h];
+    U += part_u[(uint64_t)x * pstride + h];
+    V += part_v[(uint64_t)x * pstride + h];
   }
   if (ovf_u) {
     U += ovf_u[h];
@@ -1665,7 +1665,8 @@ int vbdr_hist_pass(vbdr_sketch* sk, const uint32_t* hosts_dev, uint32_t nh, hipS
     const uint32_t tiles = (uint32_t)(want < cap ? want : (cap ? cap : 1));
     auto kern = stage ? k_estimate_part<true, true> : k_estimate_part<false, true>;
     hipLaunchKernelGGL(kern, dim3(tiles * parts), dim3(kEstBlock), lds, st, hosts_dev, nh, sk->s1, sk->g,
-                       (uint32_t)sk->m, sk->reg, sk->reg4, parts, shift, sk->part_u, sk->part_v, sk->hist_ws);
+                       (uint32_t)sk->m, sk->reg, sk->reg4, parts, shift, sk->part_u, sk->part_v, kPartChunk,
+                       sk->hist_ws);
     VBDR_LAUNCHED("k_estimate_part(hist)");
   } else {
     const uint32_t grid = grid_cap(sk, (nh + kEstWaves - 1) / kEstWaves, sk->tune.est_blocks_per_cu);
@@ -1807,9 +1808,10 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
                 (unsigned long long)(dr_bytes + seen_bytes + sk->mstride * 3 / 2 + part_bytes));
       break;
     }
-    sk->bytes = dr_bytes + bits_bytes + seen_bytes + sk->mstride * 3 / 2 + 64 * sizeof(unsigned long long) + (uint64_t)g * 4 +
-                part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 + def_bytes +
-                (sk->sat ? sk->wstride * 4 : 0);
+    sk->state_only = dr_bytes + bits_bytes + seen_bytes + sk->mstride * 3 / 2 + 64 * sizeof(unsigned long long) +
+                     (uint64_t)g * 4 + (sk->sat ? sk->wstride * 4 : 0);
+    sk->bytes = sk->state_only + part_bytes + (uint64_t)sk->parts * kLearnChunk * kBins * 4 + (uint64_t)kLearnChunk * 4 +
+                def_bytes;
     sk->bin_ok = bin_bytes != 0;  // allocated when the variant is selected (vbdr_sketch_set_tuning)
     sk->est_ok = est_bytes != 0;
     if (!lean && m >= kPartMinM && sk->mstride <= (1ull << 26) && g >= 64 && g <= kStageMaxG) {
@@ -1849,6 +1851,51 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
     return rc;
   }
   *out = sk;
+  return VBDR_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// The XCD-partitioned estimate: hosts in chunks of pstride, per-range partial
+// sums in part_u / part_v ([parts][pstride] each), then the FP64 epilogue.
+int estimate_partitioned(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, float* out_dev,
+                         unsigned long long* part_u, uint32_t* part_v, uint32_t pstride, hipStream_t st) {
+  const bool stage = sk->g <= kStageMaxG;
+  const size_t lds = stage ? (size_t)sk->g * 4 : 0;
+  const uint32_t parts = (uint32_t)(sk->parts == 8 ? sk->tune.est_parts : sk->parts);
+  const uint32_t shift = parts == 8 ? 29u : 30u;
+  auto kern = stage ? k_estimate_part<true, false> : k_estimate_part<false, false>;
+  for (uint64_t c = 0; c < n_hosts; c += pstride) {
+    const uint32_t nh = (uint32_t)(n_hosts - c < pstride ? n_hosts - c : pstride);
+    const uint64_t want = (nh + kEstWaves - 1) / kEstWaves;
+    const uint64_t cap = (uint64_t)sk->n_cu * sk->tune.est_blocks_per_cu / parts;
+    const uint32_t tiles = (uint32_t)(want < cap ? want : (cap ? cap : 1));
+    hipLaunchKernelGGL(kern, dim3(tiles * parts), dim3(kEstBlock), lds, st, hosts_dev + c, nh, sk->s1, sk->g,
+                       (uint32_t)sk->m, sk->reg, sk->reg4, parts, shift, part_u, part_v, pstride, nullptr);
+    VBDR_LAUNCHED("k_estimate_part");
+    hipLaunchKernelGGL(k_estimate_final, dim3((nh + 255) / 256), dim3(256), 0, st, nh, sk->g, (uint32_t)sk->m, parts,
+                       sk->hist, part_u, part_v, pstride, (const unsigned long long*)nullptr, (const uint32_t*)nullptr,
+                       out_dev + c);
+    VBDR_LAUNCHED("k_estimate_final");
+  }
+  return VBDR_OK;
+}
+
+// The direct estimate: one wave per host gathers from the whole register
+// array; optional raw E_s and per-host histograms.
+int estimate_direct(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, float* out_dev, double* raw_es_dev,
+                    uint32_t* hist_dev, hipStream_t st) {
+  const bool stage = sk->g <= kStageMaxG;
+  const bool extra = raw_es_dev || hist_dev;
+  const size_t lds = stage ? (size_t)sk->g * 4 : 0;
+  const uint32_t grid = grid_cap(sk, (n_hosts + kEstWaves - 1) / kEstWaves, sk->tune.est_blocks_per_cu);
+  auto kern = stage ? (extra ? k_estimate<true, true> : k_estimate<true, false>)
+                    : (extra ? k_estimate<false, true> : k_estimate<false, false>);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kEstBlock), lds, st, hosts_dev, n_hosts, sk->s1, sk->g, (uint32_t)sk->m,
+                     sk->reg, sk->hist, out_dev, raw_es_dev, hist_dev);
+  VBDR_LAUNCHED("k_estimate");
   return VBDR_OK;
 }
 
@@ -1986,6 +2033,8 @@ int vbdr_sketch_info(const vbdr_sketch* sk, vbdr_info* out) {
   out->Lc = sk->Lc;
   out->dr_bits = sk->z;
   out->est_tiled = sk->tl_rec != nullptr && sk->tune.est_binned == 3;
+  out->window_state_bytes = sk->state_only;
+  out->workspace_bytes = sk->bytes - sk->state_only;
   return VBDR_OK;
 }
 
@@ -2103,9 +2152,7 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
   if (n_hosts >= (1ull << 40)) return vbdr_fail(VBDR_EINVAL, "n_hosts too large");
   if (int rc = vbdr_check_device(sk)) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const bool stage = sk->g <= kStageMaxG;
   const bool extra = raw_es_dev || hist_dev;
-  const size_t lds = stage ? (size_t)sk->g * 4 : 0;
   if (sk->tl_rec && sk->tune.est_binned == 3 && !extra && n_hosts < (1ull << 32)) {
     uint32_t B = sk->tl_B;
     if (sk->tune.est_bin_hosts && sk->tune.est_bin_hosts < B)
@@ -2167,42 +2214,20 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
                          sk->est_slots, sk->est_cnt, sk->part_u, sk->part_v);
       VBDR_LAUNCHED("k_est_gather");
       hipLaunchKernelGGL(k_estimate_final, dim3((nh + 255) / 256), dim3(256), 0, st, nh, sk->g, (uint32_t)sk->m, 8u,
-                         sk->hist, sk->part_u, sk->part_v, sk->ovf_u, sk->ovf_v, out_dev + c);
+                         sk->hist, sk->part_u, sk->part_v, kPartChunk, sk->ovf_u, sk->ovf_v, out_dev + c);
       VBDR_LAUNCHED("k_estimate_final");
     }
     return VBDR_OK;
   }
-  if (sk->parts > 1 && !extra) {
-    const uint32_t parts = (uint32_t)(sk->parts == 8 ? sk->tune.est_parts : sk->parts);
-    const uint32_t shift = parts == 8 ? 29u : 30u;
-    auto kern = stage ? k_estimate_part<true, false> : k_estimate_part<false, false>;
-    for (uint64_t c = 0; c < n_hosts; c += kPartChunk) {
-      const uint32_t nh = (uint32_t)(n_hosts - c < kPartChunk ? n_hosts - c : kPartChunk);
-      const uint64_t want = (nh + kEstWaves - 1) / kEstWaves;
-      const uint64_t cap = (uint64_t)sk->n_cu * sk->tune.est_blocks_per_cu / parts;
-      const uint32_t tiles = (uint32_t)(want < cap ? want : (cap ? cap : 1));
-      hipLaunchKernelGGL(kern, dim3(tiles * parts), dim3(kEstBlock), lds, st, hosts_dev + c, nh, sk->s1, sk->g,
-                         (uint32_t)sk->m, sk->reg, sk->reg4, parts, shift, sk->part_u, sk->part_v, nullptr);
-      VBDR_LAUNCHED("k_estimate_part");
-      hipLaunchKernelGGL(k_estimate_final, dim3((nh + 255) / 256), dim3(256), 0, st, nh, sk->g, (uint32_t)sk->m,
-                         parts, sk->hist, sk->part_u, sk->part_v, (const unsigned long long*)nullptr,
-                         (const uint32_t*)nullptr, out_dev + c);
-      VBDR_LAUNCHED("k_estimate_final");
-    }
-    return VBDR_OK;
-  }
-  const uint32_t grid = grid_cap(sk, (n_hosts + kEstWaves - 1) / kEstWaves, sk->tune.est_blocks_per_cu);
-  auto kern = stage ? (extra ? k_estimate<true, true> : k_estimate<true, false>)
-                    : (extra ? k_estimate<false, true> : k_estimate<false, false>);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kEstBlock), lds, st, hosts_dev, n_hosts, sk->s1, sk->g, (uint32_t)sk->m,
-                     sk->reg, sk->hist, out_dev, raw_es_dev, hist_dev);
-  VBDR_LAUNCHED("k_estimate");
-  return VBDR_OK;
+  if (sk->parts > 1 && !extra)
+    return estimate_partitioned(sk, hosts_dev, n_hosts, out_dev, sk->part_u, sk->part_v, kPartChunk, st);
+  return estimate_direct(sk, hosts_dev, n_hosts, out_dev, raw_es_dev, hist_dev, st);
 }
 
 int vbdr_estimate(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, float* out_dev, void* stream) {
   return vbdr_estimate_ex(sk, hosts_dev, n_hosts, out_dev, nullptr, nullptr, stream);
 }
+
 
 int vbdr_enable_pcsa(vbdr_sketch* sk, int on) {
   if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
@@ -2218,11 +2243,13 @@ int vbdr_enable_pcsa(vbdr_sketch* sk, int on) {
       return vbdr_fail(VBDR_ENOMEM, "device allocation of %llu bytes failed", (unsigned long long)sk->mstride + 8);
     }
     sk->bytes += sk->mstride + 8;
+    sk->state_only += sk->mstride + 8;
   } else if (!on && sk->preg) {
     (void)hipFree(sk->preg);
     (void)hipFree(sk->psum);
     sk->preg = nullptr, sk->psum = nullptr;
     sk->bytes -= sk->mstride + 8;
+    sk->state_only -= sk->mstride + 8;
   }
   sk->pcsa_valid = false;
   return VBDR_OK;

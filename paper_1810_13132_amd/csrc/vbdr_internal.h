@@ -64,7 +64,8 @@ struct vbdr_sketch {
   uint8_t* preg;                  // small layout, on request: PCSA run of each BDR, last closed window
   unsigned long long* psum;       // sum of preg over the pool
   bool pcsa_valid;                // preg was written by an advance since it was enabled
-  uint64_t bytes;
+  uint64_t bytes;                 // device bytes held: the window state plus every workspace
+  uint64_t state_only;            // of which the window state: DRs, bsLBP1, registers, masks, seeds, PCSA runs
   vbdr_tuning tune;
 };
 

@@ -34,7 +34,8 @@ class Info(C.Structure):
     _fields_ = [("m", C.c_uint64), ("g", C.c_uint32), ("b", C.c_uint32), ("L", C.c_uint32), ("k", C.c_uint32),
                 ("layout", C.c_int32), ("A0", C.c_uint32), ("A1", C.c_uint32), ("t", C.c_uint64),
                 ("state_bytes", C.c_uint64), ("est_parts", C.c_int32), ("scan_deferred", C.c_int32),
-                ("Lc", C.c_uint32), ("dr_bits", C.c_uint32), ("est_tiled", C.c_int32)]
+                ("Lc", C.c_uint32), ("dr_bits", C.c_uint32), ("est_tiled", C.c_int32),
+                ("window_state_bytes", C.c_uint64), ("workspace_bytes", C.c_uint64)]
 
 
 class Tuning(C.Structure):
