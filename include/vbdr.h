@@ -152,6 +152,24 @@ int vbdr_estimate_ex(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_host
                      double *raw_es_dev, uint32_t *hist_dev, void *stream);
 
 /*
+ * vbdr_estimate for callers that cannot allocate device memory or touch the
+ * sketch's estimate workspaces: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments and the same
+ * results as vbdr_estimate, bit for bit.  Pools of 2^22 BDRs and more take
+ * the XCD-partitioned estimate with its per-range partial sums in a static
+ * device array of the library (6 MiB; each device the library runs on holds
+ * its own until the process ends), 65536 hosts per pass; smaller pools take
+ * the direct estimate, which needs no scratch memory.  The array's device
+ * address is looked up on the first call on each device; no call allocates.
+ * Every call on one device shares that device's array: two calls that
+ * overlap in time on one device (any sketches, any streams) race and give
+ * wrong results, so order them.  Nothing needs clearing between calls
+ * (every partial sum a pass reads is written by that pass).  n_hosts < 2^40.
+ */
+int vbdr_estimate_noalloc(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_hosts, float *out_dev,
+                          void *stream);
+
+/*
  * Other estimators on the same pool: the text after Alg. 5 (Sec. 4.1) and
  * Sec. 5 name PCSA and LogLog as users of the recorder pool.
  *   VBDR_EST_HLL     the HyperLogLog estimate of vbdr_estimate;

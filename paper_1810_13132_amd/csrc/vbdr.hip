@@ -21,6 +21,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2228,6 +2229,63 @@ int vbdr_estimate(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, 
   return vbdr_estimate_ex(sk, hosts_dev, n_hosts, out_dev, nullptr, nullptr, stream);
 }
 
+}  // extern "C"
+
+// ------------------------------------------------ estimate without allocation
+// The partitioned estimate's per-range partial sums for callers that cannot
+// allocate: [8 ranges][kNoAllocHosts] 64-bit harmonic sums, then
+// [8 ranges][kNoAllocHosts] 32-bit zero counts, in a static device array
+// that every device holds at its own address until the process ends.  Host
+// code never passes the array's name to a kernel: it takes the device
+// address from hipGetSymbolAddress, once per device.
+constexpr uint32_t kNoAllocHosts = 1u << 16;
+constexpr uint64_t kNoAllocBytes = 8ull * kNoAllocHosts * (8 + 4);  // 6 MiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];  // device address of `scratch` on each device, once looked up
+
+// Device address of the static scratch on `device`, which must be current.
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return vbdr_fail(VBDR_EINVAL, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return vbdr_fail(VBDR_EHIP, "hipGetSymbolAddress of the static scratch failed on device %d: %s", device,
+                       hipGetErrorString(e));
+    }
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return VBDR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int vbdr_estimate_noalloc(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts, float* out_dev, void* stream) {
+  if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");
+  if (n_hosts == 0) return VBDR_OK;
+  if (!hosts_dev || !out_dev) return vbdr_fail(VBDR_EINVAL, "hosts_dev and out_dev must not be NULL");
+  if (n_hosts >= (1ull << 40)) return vbdr_fail(VBDR_EINVAL, "n_hosts too large");
+  if (int rc = vbdr_check_device(sk)) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (sk->parts <= 1) return estimate_direct(sk, hosts_dev, n_hosts, out_dev, nullptr, nullptr, st);
+  const uint32_t parts = (uint32_t)(sk->parts == 8 ? sk->tune.est_parts : sk->parts);
+  if ((uint64_t)parts * kNoAllocHosts * (8 + 4) > kNoAllocBytes)
+    return vbdr_fail(VBDR_EINVAL, "%u pool ranges need more than the %llu bytes of static scratch", parts,
+                     (unsigned long long)kNoAllocBytes);
+  void* base = nullptr;
+  if (int rc = scratch_address(sk->device, &base)) return rc;
+  auto* part_u = static_cast<unsigned long long*>(base);
+  auto* part_v = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(base) + 8ull * kNoAllocHosts * 8);
+  return estimate_partitioned(sk, hosts_dev, n_hosts, out_dev, part_u, part_v, kNoAllocHosts, st);
+}
 
 int vbdr_enable_pcsa(vbdr_sketch* sk, int on) {
   if (!sk) return vbdr_fail(VBDR_EINVAL, "sketch is NULL");

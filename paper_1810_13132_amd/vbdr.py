@@ -64,7 +64,7 @@ EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_creat
            "vbdr_trainer_params", "vbdr_batch_create", "vbdr_batch_destroy", "vbdr_batch_sketch",
            "vbdr_batch_set_tuning", "vbdr_batch_get_tuning", "vbdr_batch_step", "vbdr_select_hosts",
            "vbdr_export_now", "vbdr_import_now", "vbdr_now_max", "vbdr_enable_pcsa", "vbdr_estimate_kind",
-           "vbdr_export_pcsa", "vbdr_test_fail_alloc"]
+           "vbdr_export_pcsa", "vbdr_test_fail_alloc", "vbdr_estimate_noalloc"]
 VOID_EXPORTS = ("vbdr_sketch_destroy", "vbdr_last_error", "vbdr_mlp_destroy", "vbdr_trainer_destroy",
                 "vbdr_batch_destroy", "vbdr_batch_sketch")
 MLP_IN, MLP_PARAMS = 67, 8577
@@ -89,6 +89,7 @@ def lib():
         L.vbdr_advance_slice.argtypes = [vp, vp]
         L.vbdr_estimate.argtypes = [vp, vp, u64, vp, vp]
         L.vbdr_estimate_ex.argtypes = [vp, vp, u64, vp, vp, vp, vp]
+        L.vbdr_estimate_noalloc.argtypes = [vp, vp, u64, vp, vp]
         L.vbdr_sketch_info.argtypes = [vp, C.POINTER(Info)]
         L.vbdr_export_state.argtypes = [vp, vp, vp, vp, vp, vp]
         L.vbdr_import_state.argtypes = [vp, vp, vp, vp, vp, u64, vp]
@@ -266,6 +267,17 @@ class Sketch:
         if n:
             _check(lib().vbdr_estimate(self._h, _dev_ptr(hosts, _U32, "hosts"), n,
                                        _dev_ptr(out, (torch.float32,), "out"), _stream(stream)))
+        return out
+
+    def estimate_noalloc(self, hosts: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """vbdr_estimate with the library's static scratch instead of the sketch's
+        workspaces; out (n float32, device) is the caller's."""
+        n = hosts.numel()
+        if out.numel() != n:
+            raise ValueError("out must hold one float per host")
+        if n:
+            _check(lib().vbdr_estimate_noalloc(self._h, _dev_ptr(hosts, _U32, "hosts"), n,
+                                               _dev_ptr(out, (torch.float32,), "out"), _stream(stream)))
         return out
 
     def estimate_ex(self, hosts: torch.Tensor, stream=None):
