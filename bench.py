@@ -13,7 +13,8 @@ through k untimed slices (its steady state).  A secondary figure
                     [--workload line_rate|tiny|batched|stress]
 
 Prints one JSON line.  value = IP pairs per second through whole steps.
-Under `rocprofv3 --selected-regions` only the timed steps are profiled.
+The aging slices scan and advance only, so under a profiler every estimate
+launch belongs to a full-window step (warm-up or timed).
 """
 import argparse
 import hashlib
@@ -128,25 +129,6 @@ def scan_roofline(w, layout, ms):
     return {"achieved": round(rate, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(rate / HBM_PEAK_GBS, 4)}
 
 
-def roctx():
-    """The region markers of rocprofv3 (rocprofiler-sdk's roctx), or None.
-    Under `rocprofv3 --selected-regions` only the code between
-    roctxProfilerResume(0) and roctxProfilerPause(0) is profiled: the timed
-    steps, not the pool's aging or the warm-up."""
-    import ctypes
-    base = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
-    for name in ("librocprofiler-sdk-roctx.so.1", os.path.join(base, "librocprofiler-sdk-roctx.so.1")):
-        try:
-            lib = ctypes.CDLL(name)
-        except OSError:
-            continue
-        for fn in (lib.roctxProfilerPause, lib.roctxProfilerResume):
-            fn.argtypes = [ctypes.c_uint64]
-            fn.restype = ctypes.c_int
-        return lib
-    return None
-
-
 def learned_accuracy():
     """Plain vs learned RMS relative error on one evaluation stream of the tiny
     workload (the shape the network is trained on), and both estimators'
@@ -178,7 +160,7 @@ def run_batched(args):
     hosts = [vbdr.to_device_u32(st.aip) for st in streams]
     outs = [torch.empty(h.numel(), dtype=torch.float32, device="cuda") for h in hosts]
     scratch = vbdr.Batch(params)
-    best, timings = autotune.tune(scratch, pairs[0], hosts, outs, reps=2)
+    best, timings = autotune.tune(scratch, pairs[:min(4, len(pairs))], hosts, outs, reps=1)
     scratch.close()
     log(f"autotuned: {best}")
     bt = vbdr.Batch(params)
@@ -316,7 +298,6 @@ def main():
         raise SystemExit("--first-slice leaves no room for the warm-up (and the young-pool steps)")
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    rtx = roctx()
 
     Lc = args.packed_lc if args.layout == "packed" else 0
     sk = vbdr.Sketch(w.m, w.g, w.k, w.seed, args.layout, Lc=Lc)
@@ -387,22 +368,18 @@ def main():
         if e:
             e[4].record(main)
 
-    def measure(first, profile=False):
+    def measure(first):
         """W warm-up steps, then K timed steps from slice `first` on."""
         outs = {i: torch.empty(resident[i][2], dtype=torch.float32, device=dev) for i in range(first - W, first + K)}
         for i in range(first - W, first):
             step(i, outs[i])
         torch.cuda.synchronize()
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
-        if profile and rtx:
-            rtx.roctxProfilerResume(0)
         t_start = time.perf_counter()
         for j in range(K):
             step(first + j, outs[first + j], ev[j])
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
-        if profile and rtx:
-            rtx.roctxProfilerPause(0)
         kms = {"scan": [], "advance": [], "estimate": []}
         for e in ev:
             kms["scan"].append(e[0].elapsed_time(e[1]))
@@ -438,7 +415,7 @@ def main():
             log(f"slice {t}: generated ({time.time() - t0:.1f}s), {int(np.count_nonzero(in_window))} hosts in window"
                 + ("" if keep else " (aging)"))
     torch.cuda.synchronize()
-    elapsed, kms, timed_active = measure(S0, profile=True)
+    elapsed, kms, timed_active = measure(S0)
     log(f"timed {K} steps from slice {S0} in {elapsed:.3f}s")
 
     # The deferred scan's updates are applied by the next advance, from LDS:
@@ -528,12 +505,8 @@ def main():
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        if rtx:
-            rtx.roctxProfilerResume(0)
         dst.copy_(src)
         torch.cuda.synchronize()
-        if rtx:
-            rtx.roctxProfilerPause(0)
         res["calibration_copy_bytes"] = src.numel() * 4
         del src, dst
     if not args.no_cpu_baseline:

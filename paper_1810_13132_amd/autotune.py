@@ -1,8 +1,8 @@
 """Launch-shape autotuner for batched steps.
 
 Times whole batch steps for each candidate (scan tile, estimate tile,
-workgroups per CU) on the caller's inputs with HIP events and keeps the
-fastest.  Tuning runs real steps, so it should be given a scratch batch with
+workgroups per CU) on the caller's inputs (one slice or several) with HIP
+events and keeps the fastest.  Tuning runs real steps, so it should be given a scratch batch with
 the production shapes (or accept that the timed steps advance the windows).
 Results can be cached in a JSON file keyed by the device and a batch
 signature (per-sketch m, g, k, layout and log2 buckets of the step sizes).
@@ -25,15 +25,20 @@ def signature(params, n_pairs, n_hosts) -> str:
 
 
 def time_steps(batch, pairs, hosts, outs, reps: int) -> float:
-    batch.step(pairs, hosts, outs)  # warm (and capture the graph)
+    """ms per step over reps passes through the given slices; pairs is one
+    step's per-sketch pair tensors or a list of such steps (slices whose
+    record runs and plane occupancy differ time differently)."""
+    steps = pairs if pairs and isinstance(pairs[0], (list, tuple)) else [pairs]
+    batch.step(steps[0], hosts, outs)  # warm (and capture the graph)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(reps):
-        batch.step(pairs, hosts, outs)
+        for step in steps:
+            batch.step(step, hosts, outs)
     b.record()
     b.synchronize()
-    return a.elapsed_time(b) / reps
+    return a.elapsed_time(b) / (reps * len(steps))
 
 
 def tune(batch, pairs, hosts, outs, candidates=None, reps: int = 3, cache_path: str = None, key: str = None):

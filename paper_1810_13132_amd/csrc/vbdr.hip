@@ -419,6 +419,83 @@ __device__ __forceinline__ void apply_record(uint32_t rec, uint8_t* dr, uint64_t
   }
 }
 
+// One chunk of kDeferChunk pairs from c0 on: records (pidx << 5 | LBP1-1),
+// counted and ranked per tile in LDS, sorted by tile, appended to the tile
+// runs (one 64-bit atomic per (chunk, tile)); records past a run's capacity
+// are applied directly and flag the direct update.  LDS: cnt[tiles],
+// start[tiles], sorted[kDeferChunk]; s1 points to LDS when staged.
+template <bool FAST>
+__device__ __forceinline__ void scan_defer_chunk(const u32x2* __restrict__ pairs, uint64_t n, uint64_t c0,
+                                                 const uint32_t* s1, uint32_t b, uint32_t A1, uint32_t m,
+                                                 uint32_t tiles, uint32_t cap, uint32_t* __restrict__ recs,
+                                                 unsigned long long* __restrict__ fill, uint8_t* __restrict__ dr,
+                                                 uint64_t mstride, uint32_t* __restrict__ seen, uint64_t wstride,
+                                                 uint32_t Lc, uint32_t* __restrict__ bits, uint32_t z, uint32_t* lds,
+                                                 uint32_t* wsum) {
+  uint32_t* cnt = lds;
+  uint32_t* start = lds + tiles;
+  uint32_t* sorted = lds + 2 * tiles;
+  for (uint32_t t = threadIdx.x; t < tiles; t += kDeferBlock) cnt[t] = 0;
+  __syncthreads();
+  // records and their ranks within the tile (< kDeferChunk, 16 bits each)
+  uint32_t rec[kDeferPer], rank[kDeferPer / 2];
+#pragma unroll
+  for (int u0 = 0; u0 < kDeferPer; u0 += 8) {
+    u32x2 p[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const uint64_t i = c0 + (uint64_t)(u0 + v) * kDeferBlock + threadIdx.x;
+      p[v] = i < n ? __builtin_nontemporal_load(pairs + i) : u32x2{0u, 0u};
+    }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int u = u0 + v;
+      const uint64_t i = c0 + (uint64_t)u * kDeferBlock + threadIdx.x;
+      uint32_t r = 0;
+      if (i < n) {
+        uint32_t vidx, rho;
+        bip_map(p[v].y, A1, b, vidx, rho);
+        const uint32_t pidx = reduce_m(mm3(p[v].x, s1[vidx]), m);
+        rec[u] = (pidx << 5) | ((rho < Lc ? rho : Lc) - 1);  // LBP1 above Lc is recorded at Lc
+        r = atomicAdd(&cnt[pidx / kDeferTile], 1u);
+      }
+      if (u & 1) rank[u >> 1] |= r << 16;
+      else rank[u >> 1] = r;
+    }
+  }
+  __syncthreads();
+  block_exclusive_scan(cnt, start, tiles, wsum);
+  // one run segment per (chunk, tile); cnt[t] becomes the segment's run offset
+  for (uint32_t t = threadIdx.x; t < tiles; t += kDeferBlock) {
+    const uint32_t c = cnt[t];
+    if (c) {
+      const unsigned long long at = atomicAdd(fill + t, (unsigned long long)c);
+      cnt[t] = at < cap ? (uint32_t)at : cap;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kDeferPer; ++u) {
+    const uint64_t i = c0 + (uint64_t)u * kDeferBlock + threadIdx.x;
+    if (i < n) sorted[start[(rec[u] >> 5) / kDeferTile] + ((rank[u >> 1] >> (16 * (u & 1))) & 0xFFFFu)] = rec[u];
+  }
+  __syncthreads();
+  const uint32_t total = n - c0 < kDeferChunk ? (uint32_t)(n - c0) : kDeferChunk;
+  bool direct = false;
+  for (uint32_t j = threadIdx.x; j < total; j += kDeferBlock) {
+    const uint32_t r = sorted[j];
+    const uint32_t t = (r >> 5) / kDeferTile;
+    const uint32_t pos = cnt[t] + (j - start[t]);
+    if (pos < cap) {
+      recs[(uint64_t)t * cap + pos] = r;
+    } else {
+      apply_record<FAST>(r, dr, mstride, seen, wstride, bits, z);
+      direct = true;
+    }
+  }
+  if (direct) fill[tiles] = 1ull;  // fast: the advance reads bsLBP1; small: its saturation masks are stale
+  __syncthreads();
+}
+
 // LDS: cnt[tiles], start[tiles], sorted[kDeferChunk], then s1 if staged.
 template <bool FAST, bool STAGE>
 __global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restrict__ pairs, uint64_t n,
@@ -431,76 +508,15 @@ __global__ __launch_bounds__(kDeferBlock) void k_scan_defer(const u32x2* __restr
                                                             uint32_t Lc, uint32_t* __restrict__ bits, uint32_t z) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t wsum[kDeferBlock / 64];
-  uint32_t* cnt = lds;
-  uint32_t* start = lds + tiles;
-  uint32_t* sorted = lds + 2 * tiles;
   // the seeds from LDS when staged (a pointer that may point to either makes
   // every seed read a flat load, waited for one at a time)
-  uint32_t* s1l = sorted + kDeferChunk;
+  uint32_t* s1l = lds + 2 * tiles + kDeferChunk;
   if (STAGE)
     for (uint32_t i = threadIdx.x; i < g; i += kDeferBlock) s1l[i] = s1g[i];
   (void)stage;
-  for (uint64_t c0 = (uint64_t)blockIdx.x * kDeferChunk; c0 < n; c0 += (uint64_t)gridDim.x * kDeferChunk) {
-    for (uint32_t t = threadIdx.x; t < tiles; t += kDeferBlock) cnt[t] = 0;
-    __syncthreads();
-    // records and their ranks within the tile (< kDeferChunk, 16 bits each)
-    uint32_t rec[kDeferPer], rank[kDeferPer / 2];
-#pragma unroll
-    for (int u0 = 0; u0 < kDeferPer; u0 += 8) {
-      u32x2 p[8];
-#pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const uint64_t i = c0 + (uint64_t)(u0 + v) * kDeferBlock + threadIdx.x;
-        p[v] = i < n ? __builtin_nontemporal_load(pairs + i) : u32x2{0u, 0u};
-      }
-#pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const int u = u0 + v;
-        const uint64_t i = c0 + (uint64_t)u * kDeferBlock + threadIdx.x;
-        uint32_t r = 0;
-        if (i < n) {
-          uint32_t vidx, rho;
-          bip_map(p[v].y, A1, b, vidx, rho);
-          const uint32_t pidx = reduce_m(mm3(p[v].x, STAGE ? s1l[vidx] : s1g[vidx]), m);
-          rec[u] = (pidx << 5) | ((rho < Lc ? rho : Lc) - 1);  // LBP1 above Lc is recorded at Lc
-          r = atomicAdd(&cnt[pidx / kDeferTile], 1u);
-        }
-        if (u & 1) rank[u >> 1] |= r << 16;
-        else rank[u >> 1] = r;
-      }
-    }
-    __syncthreads();
-    block_exclusive_scan(cnt, start, tiles, wsum);
-    // one run segment per (chunk, tile); cnt[t] becomes the segment's run offset
-    for (uint32_t t = threadIdx.x; t < tiles; t += kDeferBlock) {
-      const uint32_t c = cnt[t];
-      if (c) {
-        const unsigned long long at = atomicAdd(fill + t, (unsigned long long)c);
-        cnt[t] = at < cap ? (uint32_t)at : cap;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kDeferPer; ++u) {
-      const uint64_t i = c0 + (uint64_t)u * kDeferBlock + threadIdx.x;
-      if (i < n) sorted[start[(rec[u] >> 5) / kDeferTile] + ((rank[u >> 1] >> (16 * (u & 1))) & 0xFFFFu)] = rec[u];
-    }
-    __syncthreads();
-    const uint32_t total = n - c0 < kDeferChunk ? (uint32_t)(n - c0) : kDeferChunk;
-    bool direct = false;
-    for (uint32_t j = threadIdx.x; j < total; j += kDeferBlock) {
-      const uint32_t r = sorted[j];
-      const uint32_t t = (r >> 5) / kDeferTile;
-      const uint32_t pos = cnt[t] + (j - start[t]);
-      if (pos < cap) {
-        recs[(uint64_t)t * cap + pos] = r;
-      } else {
-        apply_record<FAST>(r, dr, mstride, seen, wstride, bits, z);
-        direct = true;
-      }
-    }
-    if (direct) fill[tiles] = 1ull;  // fast: the advance reads bsLBP1; small: its saturation masks are stale
-    __syncthreads();
-  }
+  for (uint64_t c0 = (uint64_t)blockIdx.x * kDeferChunk; c0 < n; c0 += (uint64_t)gridDim.x * kDeferChunk)
+    scan_defer_chunk<FAST>(pairs, n, c0, STAGE ? s1l : s1g, b, A1, m, tiles, cap, recs, fill, dr, mstride, seen,
+                           wstride, Lc, bits, z, lds, wsum);
 }
 
 // OR a tile's n records into its LDS bit-planes (plane LBP1-1, bit = BDR in
@@ -531,23 +547,19 @@ __device__ __forceinline__ void records_to_planes(const uint32_t* __restrict__ r
   }
 }
 
-// One workgroup per tile; LDS: L planes of kDeferWords bit words.
+// The deferred advance of one tile by one workgroup: the tile's records
+// become L planes of kDeferWords bit words in LDS (pm), then every thread
+// slides 32 BDRs; lh holds the wave register histograms.
 template <bool FAST>
-__global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restrict__ dr, uint64_t mstride,
-                                                               uint32_t* __restrict__ seen, uint64_t wstride,
-                                                               uint8_t* __restrict__ reg, uint8_t* __restrict__ reg4,
-                                                               uint64_t m, uint32_t L, uint32_t thr,
-                                                               unsigned long long* __restrict__ hist,
-                                                               const uint32_t* __restrict__ recs,
-                                                               unsigned long long* __restrict__ fill, uint32_t cap,
-                                                               uint32_t tiles, uint8_t* __restrict__ preg,
-                                                               unsigned long long* __restrict__ psum,
-                                                               uint32_t* __restrict__ sat) {
-  extern __shared__ uint32_t pm[];
-  // four copies of each wave's register histogram (lane & 3): registers crowd a
-  // few values, and lanes adding to one LDS word are served one at a time
-  __shared__ uint32_t lh[kDeferBlock / 64][kHistCopies][kBins];
-  const uint32_t tile = blockIdx.x;
+__device__ __forceinline__ void advance_defer_tile(uint32_t tile, uint8_t* __restrict__ dr, uint64_t mstride,
+                                                   uint32_t* __restrict__ seen, uint64_t wstride,
+                                                   uint8_t* __restrict__ reg, uint8_t* __restrict__ reg4, uint64_t m,
+                                                   uint32_t L, uint32_t thr, unsigned long long* __restrict__ hist,
+                                                   const uint32_t* __restrict__ recs,
+                                                   unsigned long long* __restrict__ fill, uint32_t cap,
+                                                   uint32_t tiles, uint8_t* __restrict__ preg,
+                                                   unsigned long long* __restrict__ psum, uint32_t* __restrict__ sat,
+                                                   uint32_t* pm, uint32_t (*lh)[kHistCopies][kBins]) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (uint32_t i = threadIdx.x; i < L * kDeferWords; i += kDeferBlock) pm[i] = 0;
   for (int i = lane; i < kHistCopies * kBins; i += 64) (&lh[wave][0][0])[i] = 0;
@@ -588,6 +600,89 @@ __global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restri
       for (int q = 0; q < kHistCopies; ++q) c += lh[w][q][threadIdx.x];
     if (c) atomicAdd(hist + threadIdx.x, (unsigned long long)c);
   }
+}
+
+// One workgroup per tile; LDS: L planes of kDeferWords bit words.
+template <bool FAST>
+__global__ __launch_bounds__(kDeferBlock) void k_advance_defer(uint8_t* __restrict__ dr, uint64_t mstride,
+                                                               uint32_t* __restrict__ seen, uint64_t wstride,
+                                                               uint8_t* __restrict__ reg, uint8_t* __restrict__ reg4,
+                                                               uint64_t m, uint32_t L, uint32_t thr,
+                                                               unsigned long long* __restrict__ hist,
+                                                               const uint32_t* __restrict__ recs,
+                                                               unsigned long long* __restrict__ fill, uint32_t cap,
+                                                               uint32_t tiles, uint8_t* __restrict__ preg,
+                                                               unsigned long long* __restrict__ psum,
+                                                               uint32_t* __restrict__ sat) {
+  extern __shared__ uint32_t pm[];
+  // four copies of each wave's register histogram (lane & 3): registers crowd a
+  // few values, and lanes adding to one LDS word are served one at a time
+  __shared__ uint32_t lh[kDeferBlock / 64][kHistCopies][kBins];
+  advance_defer_tile<FAST>(blockIdx.x, dr, mstride, seen, wstride, reg, reg4, m, L, thr, hist, recs, fill, cap, tiles,
+                           preg, psum, sat, pm, lh);
+}
+
+// ------------------------------------------- batches: members with record runs
+// Batch members whose pools take deferred scans (2^22..2^26 BDRs) are scanned
+// and advanced by these two kernels instead of the batch's direct-update
+// ones: every deferred member's chunks of kDeferChunk pairs in one persistent
+// launch (items strided over the grid), then every member's tiles in one
+// launch (one workgroup per tile).  Inputs come from the device table.
+
+// Last member s whose first item is <= item (members without items share
+// their successor's first item).
+__device__ __forceinline__ uint32_t defer_member(const uint32_t* first, uint32_t S, uint32_t item) {
+  uint32_t lo = 0, hi = S - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// LDS: cnt[max tiles], start[max tiles], sorted[kDeferChunk].
+__global__ __launch_bounds__(kDeferBlock) void k_batch_scan_defer(const DeferItem* __restrict__ it,
+                                                                  const DeferHdr* __restrict__ hdr, uint32_t S) {
+  extern __shared__ uint32_t lds[];
+  __shared__ uint32_t wsum[kDeferBlock / 64];
+  __shared__ uint32_t first[kMaxDeferMembers];
+  for (uint32_t s = threadIdx.x; s < S; s += kDeferBlock) first[s] = it[s].scan_item0;
+  __syncthreads();
+  const uint32_t total = hdr->scan_total;
+  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const DeferItem& D = it[defer_member(first, S, item)];
+    const uint64_t c0 = (uint64_t)(item - D.scan_item0) * kDeferChunk;
+    const u32x2* pairs = reinterpret_cast<const u32x2*>(D.pairs);
+    if (D.layout == VBDR_LAYOUT_FAST)
+      scan_defer_chunk<true>(pairs, D.n_pairs, c0, D.s1, D.b, D.A1, (uint32_t)D.m, D.tiles, D.cap, D.recs, D.fill,
+                             D.dr, D.mstride, D.seen, D.wstride, D.L, nullptr, 0u, lds, wsum);
+    else
+      scan_defer_chunk<false>(pairs, D.n_pairs, c0, D.s1, D.b, D.A1, (uint32_t)D.m, D.tiles, D.cap, D.recs, D.fill,
+                              D.dr, D.mstride, D.seen, D.wstride, D.L, nullptr, 0u, lds, wsum);
+  }
+}
+
+// One workgroup per tile of every member; LDS: max L planes of kDeferWords words.
+__global__ __launch_bounds__(kDeferBlock) void k_batch_advance_defer(const DeferItem* __restrict__ it, uint32_t S) {
+  extern __shared__ uint32_t pm[];
+  __shared__ uint32_t lh[kDeferBlock / 64][kHistCopies][kBins];
+  __shared__ uint32_t first[kMaxDeferMembers];
+  for (uint32_t s = threadIdx.x; s < S; s += kDeferBlock) first[s] = it[s].adv_item0;
+  __syncthreads();
+  const DeferItem& D = it[defer_member(first, S, blockIdx.x)];
+  const uint32_t tile = blockIdx.x - D.adv_item0;
+  if (D.layout == VBDR_LAYOUT_FAST)
+    advance_defer_tile<true>(tile, D.dr, D.mstride, D.seen, D.wstride, D.reg, D.reg4, D.m, D.L, D.thr, D.hist, D.recs,
+                             D.fill, D.cap, D.tiles, nullptr, nullptr, D.sat, pm, lh);
+  else
+    advance_defer_tile<false>(tile, D.dr, D.mstride, D.seen, D.wstride, D.reg, D.reg4, D.m, D.L, D.thr, D.hist,
+                              D.recs, D.fill, D.cap, D.tiles, nullptr, nullptr, D.sat, pm, lh);
+}
+
+// After every tile has read it: clear each member's direct-update flag.
+__global__ void k_batch_defer_flag(const DeferItem* __restrict__ it, uint32_t S) {
+  for (uint32_t s = threadIdx.x; s < S; s += blockDim.x) it[s].fill[it[s].tiles] = 0ull;
 }
 
 // Packed layout (Table 1's recorder sizes): DR r of BDR p is a z-bit counter
@@ -1263,10 +1358,14 @@ __global__ void k_est_tile_clear(uint32_t* __restrict__ a, uint64_t na, uint32_t
 // tile nt, and entries beyond a bucket's capacity go to a spare last slot, so
 // that the append is branch-free.  LDS: cnt[nt + 1], cntc[nt], base[nt],
 // kmix[64], bucket[nt + 1][capb + 1], s1[g].
+// POW2: m = 2^(32 - mshift), so H(x, m, A) is the hash shifted right (the
+// multiply-shift map of a power of two) instead of a high multiply.
+template <bool POW2>
 __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_est_tile_bin(
     const uint32_t* __restrict__ hosts, uint32_t nh, const uint32_t* __restrict__ s1g, uint32_t g, uint32_t lg,
-    uint32_t m, uint32_t shift, uint32_t nt, uint32_t capb, uint32_t cap, uint32_t* __restrict__ recs,
-    uint32_t* __restrict__ fill, const uint8_t* __restrict__ reg, unsigned long long* __restrict__ ovf) {
+    uint32_t m, uint32_t mshift, uint32_t shift, uint32_t nt, uint32_t capb, uint32_t cap,
+    uint32_t* __restrict__ recs, uint32_t* __restrict__ fill, const uint8_t* __restrict__ reg,
+    unsigned long long* __restrict__ ovf) {
   extern __shared__ uint32_t lds[];
   constexpr uint32_t kCopyWaves = kTileBinBlock / 64 - 1;
   const uint32_t hpc = tile_chunk_hosts(lg);  // divides kTileSub
@@ -1308,21 +1407,30 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
     uint32_t tx = threadIdx.x;
     asm volatile("" : "+v"(tx));
     uint32_t pv[kTilePer], qv[kTilePer];
+    auto pool_index = [&](uint32_t h) -> uint32_t { return POW2 ? h >> mshift : reduce_m(h, m); };
+    // every pair of a full chunk is valid: no per-pair select (uniform branch)
+    const bool whole = npairs == kTileChunk;
     if (lg <= kTileBinLog) {  // one seed per thread; hosts (tx >> lg) + u * (kTileBinBlock >> lg)
       const uint32_t sv = s1l[tx & (g - 1)];
       const uint32_t* kp = kmix + (tx >> lg);
       const uint32_t kst = kTileBinBlock >> lg;
+      if (whole) {
 #pragma unroll
-      for (int u = 0; u < kTilePer; ++u) {  // branch-free: kmix is zero past the chunk's hosts
-        const uint32_t p = reduce_m(mm3_seeded(kp[(u * kst) & 63u], sv), m);
-        pv[u] = (uint32_t)u * kTileBinBlock + tx < npairs ? p : ~0u;
+        for (int u = 0; u < kTilePer; ++u) pv[u] = pool_index(mm3_seeded(kp[(u * kst) & 63u], sv));
+      } else {
+#pragma unroll
+        for (int u = 0; u < kTilePer; ++u) {  // branch-free: kmix is zero past the chunk's hosts
+          const uint32_t p = pool_index(mm3_seeded(kp[(u * kst) & 63u], sv));
+          pv[u] = (uint32_t)u * kTileBinBlock + tx < npairs ? p : ~0u;
+        }
       }
     } else {  // one host for g / kTileBinBlock consecutive u
       const uint32_t gw = g >> kTileBinLog, hs = lg - kTileBinLog;
 #pragma unroll
       for (int u = 0; u < kTilePer; ++u) {
-        const uint32_t p = reduce_m(mm3_seeded(kmix[(uint32_t)u >> hs], s1l[(((uint32_t)u & (gw - 1)) << kTileBinLog) + tx]), m);
-        pv[u] = (uint32_t)u * kTileBinBlock + tx < npairs ? p : ~0u;
+        const uint32_t p =
+            pool_index(mm3_seeded(kmix[(uint32_t)u >> hs], s1l[(((uint32_t)u & (gw - 1)) << kTileBinLog) + tx]));
+        pv[u] = whole || (uint32_t)u * kTileBinBlock + tx < npairs ? p : ~0u;
       }
     }
 #pragma unroll
@@ -1467,8 +1575,12 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     // the loop, so that no load in it waits behind the prefetch.  ~0u pads a
     // run to whole quads (and marks prefetch slots past its end).
     uint32_t wide = 0;
+    // a prefetched quad slot that holds only padding in every lane of the
+    // wave (runs average 8 records per thread of PRE) is skipped as a whole
+    const uint32_t wave0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
+      if (4 * (wave0 + (uint32_t)q * kDeferBlock) >= n) break;
       uint32_t nib[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -1646,6 +1758,35 @@ int defer_flush(vbdr_sketch* sk, hipStream_t st) {
 
 }  // namespace
 
+void vbdr_defer_member(const vbdr_sketch* sk, DeferItem* d) {
+  std::memset(d, 0, sizeof(*d));
+  d->s1 = sk->s1, d->dr = sk->dr, d->seen = sk->seen, d->reg = sk->reg, d->reg4 = sk->reg4, d->hist = sk->hist;
+  d->recs = sk->def_rec, d->fill = sk->def_fill, d->sat = sk->sat;
+  d->mstride = sk->mstride, d->wstride = sk->wstride, d->m = sk->m;
+  d->b = sk->b, d->A1 = sk->A1, d->tiles = sk->def_tiles, d->cap = sk->def_cap, d->L = sk->L, d->thr = sk->k - 1;
+  d->layout = (uint32_t)sk->layout;
+}
+
+uint32_t vbdr_defer_chunk_pairs() { return kDeferChunk; }
+
+int vbdr_launch_batch_defer(const DeferItem* items_dev, const DeferHdr* hdr_dev, uint32_t S, uint32_t max_tiles,
+                            uint32_t max_L, uint32_t adv_total, uint32_t grid, int phase, hipStream_t st) {
+  if (S == 0) return VBDR_OK;
+  if (S > kMaxDeferMembers) return vbdr_fail(VBDR_EINVAL, "more than %u members with record runs", kMaxDeferMembers);
+  if (phase == 0) {
+    hipLaunchKernelGGL(k_batch_scan_defer, dim3(grid), dim3(kDeferBlock), (size_t)(2 * max_tiles + kDeferChunk) * 4,
+                       st, items_dev, hdr_dev, S);
+    VBDR_LAUNCHED("k_batch_scan_defer");
+  } else {
+    hipLaunchKernelGGL(k_batch_advance_defer, dim3(adv_total), dim3(kDeferBlock), (size_t)max_L * kDeferWords * 4, st,
+                       items_dev, S);
+    VBDR_LAUNCHED("k_batch_advance_defer");
+    hipLaunchKernelGGL(k_batch_defer_flag, dim3(1), dim3(256), 0, st, items_dev, S);
+    VBDR_LAUNCHED("k_batch_defer_flag");
+  }
+  return VBDR_OK;
+}
+
 int vbdr_check_device(const vbdr_sketch* sk) {
   int cur = -1;
   VBDR_HIP(hipGetDevice(&cur));
@@ -1712,8 +1853,10 @@ int alloc_tiled(vbdr_sketch* sk) {
   return VBDR_OK;
 }
 
-int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, bool lean, uint32_t Lc,
-                  vbdr_sketch** out) {
+// lean: no estimate workspaces (sketches of a batch); defer_ok: the record
+// runs of deferred scans all the same (lean batch members with large pools).
+int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, bool lean, bool defer_ok,
+                  uint32_t Lc, vbdr_sketch** out) {
   if (!out) return vbdr_fail(VBDR_EINVAL, "out is NULL");
   *out = nullptr;
   if (g < 2 || g > 65536u || (g & (g - 1))) return vbdr_fail(VBDR_EINVAL, "g=%u must be a power of two in [2, 65536]", g);
@@ -1769,7 +1912,7 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
         (!lean && layout != VBDR_LAYOUT_PACKED && sk->parts == 8 && m <= kBinMaxM) ? 8ull * kBinCap * 4 : 0;
     // deferred scan records: kDeferSlots per BDR, for 2^22 <= m and 2^26 tile-rounded BDRs at most
     uint64_t def_bytes = 0;
-    if (!lean && (m >= kPartMinM || layout == VBDR_LAYOUT_PACKED) && sk->mstride <= (1ull << 26)) {
+    if ((!lean || defer_ok) && (m >= kPartMinM || layout == VBDR_LAYOUT_PACKED) && sk->mstride <= (1ull << 26)) {
       const uint32_t tiles = (uint32_t)((sk->mstride + kDeferTile - 1) / kDeferTile);
       if (defer_scan_lds(tiles) + 1024 <= (size_t)lds_max && (size_t)(33 - 1) * kDeferWords * 4 + 4096 <= (size_t)lds_max) {
         sk->def_tiles = tiles;
@@ -1902,20 +2045,21 @@ int estimate_direct(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_hosts
 
 }  // namespace
 
-int vbdr_sketch_create_lean(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out) {
+int vbdr_sketch_create_lean(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, bool defer,
+                            vbdr_sketch** out) {
   if (layout == VBDR_LAYOUT_PACKED) return vbdr_fail(VBDR_EINVAL, "batches hold fast and small layouts only");
-  return create_sketch(m, g, k, hash_seed, layout, true, 0, out);
+  return create_sketch(m, g, k, hash_seed, layout, true, defer, 0, out);
 }
 
 extern "C" {
 
 int vbdr_sketch_create_layout(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out) {
   if (layout == VBDR_LAYOUT_PACKED) return vbdr_fail(VBDR_EINVAL, "create a packed sketch with vbdr_sketch_create_packed");
-  return create_sketch(m, g, k, hash_seed, layout, false, 0, out);
+  return create_sketch(m, g, k, hash_seed, layout, false, false, 0, out);
 }
 
 int vbdr_sketch_create_packed(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, uint32_t Lc, vbdr_sketch** out) {
-  return create_sketch(m, g, k, hash_seed, VBDR_LAYOUT_PACKED, false, Lc, out);
+  return create_sketch(m, g, k, hash_seed, VBDR_LAYOUT_PACKED, false, false, Lc, out);
 }
 
 int vbdr_sketch_create(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, vbdr_sketch** out) {
@@ -2177,9 +2321,12 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
       // eight workgroups (one per XCD) per unit of per_xcd; an XCD owns every eighth sub-block
       const uint64_t xcd_chunks = (uint64_t)((nsb + 7) / 8) * (kTileSub / hpc);
       const uint32_t per_xcd = grid_cap(sk, xcd_chunks * 8, 1) / 8;  // one workgroup per CU (LDS)
-      hipLaunchKernelGGL(k_est_tile_bin, dim3(8 * (per_xcd ? per_xcd : 1)), dim3(kTileBinBlock), lds1, st,
-                         hosts_dev + c, nh, sk->s1, g, lg, (uint32_t)sk->m, sk->tl_shift, nt, capb, cap, sk->tl_rec,
-                         sk->tl_fill, sk->reg, sk->tl_ovf);
+      const bool pow2 = (sk->m & (sk->m - 1)) == 0;
+      uint32_t mshift = 32;
+      while (pow2 && (1ull << (32 - mshift)) < sk->m) --mshift;
+      hipLaunchKernelGGL(pow2 ? k_est_tile_bin<true> : k_est_tile_bin<false>, dim3(8 * (per_xcd ? per_xcd : 1)),
+                         dim3(kTileBinBlock), lds1, st, hosts_dev + c, nh, sk->s1, g, lg, (uint32_t)sk->m, mshift,
+                         sk->tl_shift, nt, capb, cap, sk->tl_rec, sk->tl_fill, sk->reg, sk->tl_ovf);
       VBDR_LAUNCHED("k_est_tile_bin");
       // prefetch depth: the whole run when runs are near their expected length
       const auto gather = cap <= 12u * kDeferBlock ? k_est_tile_gather<12> : k_est_tile_gather<20>;

@@ -1,10 +1,13 @@
 // Many independent sketches (uneven streams, pools, windows, g, layouts)
 // advanced per slice by three persistent work-queue kernels -- scan, advance,
-// estimate -- that pull (sketch, tile) items from device counters.  Each
-// sketch's per-slice inputs live in a device descriptor table refreshed by one
-// host-to-device copy per step, so the kernel sequence is captured once into a
-// hipGraph and replayed.  Every block leaves its loop when the queue is
-// drained, so a launch always completes.
+// estimate -- that pull (sketch, tile) items from device counters.  Members
+// with pools of 2^22..2^26 BDRs instead write sorted record runs in their scan
+// and apply them in their advance, as a single sketch does (two more kernels
+// over all such members, in vbdr.hip).  Each sketch's per-slice inputs live in
+// a device descriptor table refreshed by one host-to-device copy per step, so
+// the kernel sequence is captured once into a hipGraph and replayed.  Every
+// block leaves its loop when the queue is drained, so a launch always
+// completes.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -188,21 +191,42 @@ struct vbdr_batch {
   hipGraph_t graph;
   hipGraphExec_t exec;
   vbdr_batch_tuning tune;
+  // members with deferred scans: index in the deferred table, or ~0u
+  std::vector<uint32_t> defer_of;
+  uint32_t n_defer, defer_max_tiles, defer_max_L, defer_tiles;
 };
 
 namespace {
 
-size_t table_bytes(uint32_t S) { return sizeof(BatchDesc) * S + sizeof(BatchHdr); }
+// Device table: [S] BatchDesc, BatchHdr, [n_defer] DeferItem, DeferHdr.
+size_t table_bytes(uint32_t S, uint32_t n_defer) {
+  return sizeof(BatchDesc) * S + sizeof(BatchHdr) + sizeof(DeferItem) * n_defer + sizeof(DeferHdr);
+}
+DeferItem* defer_items(uint8_t* table, uint32_t S) {
+  return reinterpret_cast<DeferItem*>(table + sizeof(BatchDesc) * S + sizeof(BatchHdr));
+}
+DeferHdr* defer_hdr(uint8_t* table, uint32_t S, uint32_t n_defer) {
+  return reinterpret_cast<DeferHdr*>(table + sizeof(BatchDesc) * S + sizeof(BatchHdr) + sizeof(DeferItem) * n_defer);
+}
 
 int launch_step_kernels(vbdr_batch* bt) {
   const uint32_t grid = (uint32_t)bt->n_cu * bt->tune.blocks_per_cu;
   hipLaunchKernelGGL(k_batch_scan, dim3(grid), dim3(kBBlock), 0, bt->st, bt->desc_dev, bt->hdr_dev, bt->S,
                      bt->tune.scan_tile);
   VBDR_LAUNCHED("k_batch_scan");
+  uint8_t* table = reinterpret_cast<uint8_t*>(bt->desc_dev);
+  DeferItem* ditems = defer_items(table, bt->S);
+  DeferHdr* dhdr = defer_hdr(table, bt->S, bt->n_defer);
+  if (int rc = vbdr_launch_batch_defer(ditems, dhdr, bt->n_defer, bt->defer_max_tiles, bt->defer_max_L,
+                                       bt->defer_tiles, (uint32_t)bt->n_cu, 0, bt->st))
+    return rc;
   hipLaunchKernelGGL(k_batch_hist_reset, dim3(bt->S), dim3(64), 0, bt->st, bt->desc_dev);
   VBDR_LAUNCHED("k_batch_hist_reset");
   hipLaunchKernelGGL(k_batch_advance, dim3(grid), dim3(kBBlock), 0, bt->st, bt->desc_dev, bt->hdr_dev, bt->S);
   VBDR_LAUNCHED("k_batch_advance");
+  if (int rc = vbdr_launch_batch_defer(ditems, dhdr, bt->n_defer, bt->defer_max_tiles, bt->defer_max_L,
+                                       bt->defer_tiles, (uint32_t)bt->n_cu, 1, bt->st))
+    return rc;
   hipLaunchKernelGGL(k_batch_estimate, dim3(grid), dim3(kBBlock), 0, bt->st, bt->desc_dev, bt->hdr_dev, bt->S,
                      bt->tune.est_tile);
   VBDR_LAUNCHED("k_batch_estimate");
@@ -241,11 +265,20 @@ int vbdr_batch_create(uint32_t n_sketches, const vbdr_batch_params* params, vbdr
     for (uint32_t i = 0; i < n_sketches; ++i) {
       vbdr_sketch* s = nullptr;
       const vbdr_batch_params& p = params[i];
-      if ((rc = vbdr_sketch_create_lean(p.m, p.g, p.k, p.hash_seed, p.layout, &s)) != VBDR_OK) break;
+      if ((rc = vbdr_sketch_create_lean(p.m, p.g, p.k, p.hash_seed, p.layout, true, &s)) != VBDR_OK) break;
       bt->sk.push_back(s);
+      // members with record runs scan and advance through the deferred kernels
+      if (s->def_rec) {
+        bt->defer_of.push_back(bt->n_defer++);
+        bt->defer_max_tiles = bt->defer_max_tiles > s->def_tiles ? bt->defer_max_tiles : s->def_tiles;
+        bt->defer_max_L = bt->defer_max_L > s->L ? bt->defer_max_L : s->L;
+        bt->defer_tiles += s->def_tiles;
+      } else {
+        bt->defer_of.push_back(~0u);
+      }
     }
     if (rc != VBDR_OK) break;
-    const size_t tb = table_bytes(n_sketches);
+    const size_t tb = table_bytes(n_sketches, bt->n_defer);
     if (vbdr_malloc(&bt->desc_dev, tb) != hipSuccess || hipHostMalloc(&bt->staging[0], tb) != hipSuccess ||
         hipHostMalloc(&bt->staging[1], tb) != hipSuccess) {
       rc = vbdr_fail(VBDR_ENOMEM, "batch table allocation failed");
@@ -336,9 +369,21 @@ int vbdr_batch_step(vbdr_batch* bt, const uint32_t* const* pairs_dev, const uint
   VBDR_HIP(hipEventSynchronize(bt->staged[buf]));
   BatchDesc* desc = reinterpret_cast<BatchDesc*>(bt->staging[buf]);
   BatchHdr* hdr = reinterpret_cast<BatchHdr*>(bt->staging[buf] + sizeof(BatchDesc) * S);
-  uint32_t si = 0, ai = 0, ei = 0;
+  DeferItem* ditems = defer_items(bt->staging[buf], S);
+  DeferHdr* dhdr = defer_hdr(bt->staging[buf], S, bt->n_defer);
+  const uint32_t chunk = vbdr_defer_chunk_pairs();
+  uint32_t si = 0, ai = 0, ei = 0, dsi = 0, dai = 0;
   for (uint32_t s = 0; s < S; ++s) {
     const vbdr_sketch* k = bt->sk[s];
+    const uint32_t di = bt->defer_of[s];
+    if (di != ~0u) {  // scanned and advanced by the deferred kernels: no items in the direct ones
+      DeferItem& I = ditems[di];
+      vbdr_defer_member(k, &I);
+      I.pairs = pairs_dev[s], I.n_pairs = n_pairs[s];
+      I.scan_item0 = dsi, I.adv_item0 = dai;
+      dsi += (uint32_t)((n_pairs[s] + chunk - 1) / chunk);
+      dai += k->def_tiles;
+    }
     BatchDesc& D = desc[s];
     D.dr = k->dr, D.seen = k->seen, D.reg = k->reg, D.reg4 = k->reg4, D.hist = k->hist, D.s1 = k->s1;
     D.mstride = k->mstride, D.wstride = k->wstride;
@@ -347,17 +392,21 @@ int vbdr_batch_step(vbdr_batch* bt, const uint32_t* const* pairs_dev, const uint
     D.pairs = pairs_dev[s], D.n_pairs = n_pairs[s];
     D.hosts = hosts_dev[s], D.n_hosts = n_hosts[s], D.out = out_dev[s];
     D.scan_item0 = si, D.adv_item0 = ai, D.est_item0 = ei, D.pad = 0;
-    si += (uint32_t)((n_pairs[s] + bt->tune.scan_tile - 1) / bt->tune.scan_tile);
-    ai += (uint32_t)(k->mstride / kAdvTile);
+    if (di == ~0u) {
+      si += (uint32_t)((n_pairs[s] + bt->tune.scan_tile - 1) / bt->tune.scan_tile);
+      ai += (uint32_t)(k->mstride / kAdvTile);
+    }
     ei += (uint32_t)((n_hosts[s] + bt->tune.est_tile - 1) / bt->tune.est_tile);
   }
   std::memset(hdr, 0, sizeof(*hdr));
   hdr->scan_total = si, hdr->adv_total = ai, hdr->est_total = ei;
+  std::memset(dhdr, 0, sizeof(*dhdr));
+  dhdr->scan_total = dsi;
   // order after the caller's stream, run on the batch stream, order the caller after it
   hipStream_t user = reinterpret_cast<hipStream_t>(stream);
   VBDR_HIP(hipEventRecord(bt->ev_in, user));
   VBDR_HIP(hipStreamWaitEvent(bt->st, bt->ev_in, 0));
-  VBDR_HIP(hipMemcpyAsync(bt->desc_dev, bt->staging[buf], table_bytes(S), hipMemcpyHostToDevice, bt->st));
+  VBDR_HIP(hipMemcpyAsync(bt->desc_dev, bt->staging[buf], table_bytes(S, bt->n_defer), hipMemcpyHostToDevice, bt->st));
   VBDR_HIP(hipEventRecord(bt->staged[buf], bt->st));
   if (bt->tune.use_graph) {
     if (!bt->exec) {

@@ -69,8 +69,46 @@ struct vbdr_sketch {
   vbdr_tuning tune;
 };
 
-// vbdr_sketch_create_layout without the optional large-pool workspaces.
-int vbdr_sketch_create_lean(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, vbdr_sketch** out);
+// vbdr_sketch_create_layout without the optional large-pool workspaces;
+// with defer, pools of 2^22..2^26 BDRs keep the record runs of deferred scans.
+int vbdr_sketch_create_lean(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int layout, bool defer,
+                            vbdr_sketch** out);
+
+// A batch member whose scans defer their updates, as the batch's deferred
+// scan and advance kernels read it from device memory.  pairs, n_pairs and
+// scan_item0 change every step; the rest is the sketch's.
+constexpr uint32_t kMaxDeferMembers = 256;
+struct DeferItem {
+  const uint32_t* pairs;
+  uint64_t n_pairs;
+  const uint32_t* s1;
+  uint8_t* dr;
+  uint32_t* seen;
+  uint8_t* reg;
+  uint8_t* reg4;
+  unsigned long long* hist;
+  uint32_t* recs;
+  unsigned long long* fill;
+  uint32_t* sat;
+  uint64_t mstride, wstride, m;
+  uint32_t b, A1, tiles, cap, L, thr, layout;
+  uint32_t scan_item0;  // first scan item (chunk) of the member this step
+  uint32_t adv_item0;   // first advance item (tile) of the member
+  uint32_t pad;
+};
+struct DeferHdr {
+  uint32_t scan_total;  // scan items of the step
+  uint32_t pad[3];
+};
+
+// The sketch's fields of its DeferItem (pairs, n_pairs and the item offsets zero).
+void vbdr_defer_member(const vbdr_sketch* sk, DeferItem* d);
+// Pairs per scan item of a deferred member.
+uint32_t vbdr_defer_chunk_pairs();
+// Phase 0: the deferred members' scans (grid workgroups over hdr->scan_total
+// items); phase 1: their advances (adv_total tiles) and the flag reset.
+int vbdr_launch_batch_defer(const DeferItem* items_dev, const DeferHdr* hdr_dev, uint32_t S, uint32_t max_tiles,
+                            uint32_t max_L, uint32_t adv_total, uint32_t grid, int phase, hipStream_t st);
 
 constexpr uint64_t kPackedMaxM = 1ull << 26;  // packed pools: records' tiles must fit the deferred scan's LDS
 

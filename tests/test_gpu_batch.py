@@ -76,11 +76,13 @@ def test_batch_matches_single_sketches(V, use_graph):
 
 def test_batch_matches_oracle(V):
     from oracle import oracle as O
-    params = PARAMS[:4]
-    sizes = [4000, 900, 20000, 3000]
+    params = PARAMS
+    sizes = [4000, 900, 20000, 3000, 50000]
     steps = _streams(2, 3, sizes)
     hosts = _hosts(steps)
     bt = V.Batch(params)
+    # the member with 2^22 + 3 BDRs writes record runs and applies them in its advance
+    assert [sk.info().scan_deferred for sk in bt.sketches] == [0, 0, 0, 0, 1]
     osks = [O.Sketch(p["m"], p["g"], p["k"], p["hash_seed"], O.GFAST if p["layout"] == "fast" else O.GSMALL)
             for p in params]
     hd = [V.to_device_u32(h) for h in hosts]
@@ -121,3 +123,40 @@ def test_retuning_recaptures_and_autotuner(V):
     best, timings = autotune.tune(a, pd, hd, outs_a, candidates=[(2048, 16, 4), (8192, 64, 8)], reps=1)
     assert len(timings) == 2 and best["scan_tile"] in (2048, 8192)
     assert a.get_tuning()["scan_tile"] == best["scan_tile"]
+
+
+@pytest.mark.parametrize("layout", ["fast", "small"])
+def test_batch_deferred_member_overflow(V, layout):
+    """A member with record runs gets more records than its runs hold (about
+    2.1 per BDR in a slice of 9e6 pairs; runs hold 2): the rest is applied by
+    the scan directly and the next advance reads every plane.  Against the
+    oracle after every step, and against the same sketch stepped alone."""
+    from oracle import oracle as O
+    params = [dict(m=(1 << 22) + 3, g=256, k=3, hash_seed=9, layout=layout),
+              dict(m=5000, g=64, k=2, hash_seed=10, layout="small")]
+    rng = np.random.default_rng(11)
+    aips = rng.integers(0, 2**32, 3000, dtype=np.uint64).astype(np.uint32)
+    sizes = [[9_000_000, 1000], [30000, 0], [0, 500], [70000, 2000]]
+    bt = V.Batch(params)
+    single = V.Sketch(**params[0])
+    osk = O.Sketch(params[0]["m"], params[0]["g"], params[0]["k"], 9, O.GFAST if layout == "fast" else O.GSMALL)
+    hosts = [aips, aips[:100]]
+    hd = [V.to_device_u32(h) for h in hosts]
+    for sz in sizes:
+        step = [np.stack([aips[rng.integers(0, len(aips), n)],
+                          rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
+                for n in sz]
+        pd = [V.to_device_u32(p.reshape(-1)) for p in step]
+        outs = [torch.empty(len(h), dtype=torch.float32, device="cuda") for h in hosts]
+        bt.step(pd, hd, outs)
+        single.scan_slice(pd[0])
+        single.advance_slice()
+        osk.scan(step[0])
+        osk.advance()
+        assert torch.equal(outs[0], single.estimate(hd[0]))
+        sb, so = bt.sketches[0].state(), osk.state()
+        for key in ("dr", "reg", "hist"):
+            assert np.array_equal(sb[key], so[key]), key
+        ss = single.state()
+        for key in ("dr", "bs", "reg", "hist"):
+            assert np.array_equal(sb[key], ss[key]), key

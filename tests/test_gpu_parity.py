@@ -283,13 +283,15 @@ def test_two_stream_schedule_matches_one_stream(V):
         assert np.array_equal(sa[key], sb[key]), key
 
 
-@pytest.mark.parametrize("g", [64, 2048, 8192])
-def test_tiled_estimate_edge_g(V, O, g):
+@pytest.mark.parametrize("g,m", [(64, 1 << 22), (2048, (1 << 22) + 12345), (8192, 1 << 22), (1024, (1 << 23) + 3)])
+def test_tiled_estimate_edge_g(V, O, g, m):
     """The tiled estimate at the ends of its g range: g = 64 (chunks of 64
     hosts, half a chunk of pairs per thread unused), g = 2048 and 8192 (one
-    host spans several pair slots of every thread).  Bit-identical to the
-    partitioned and the direct gathers, and within the bar of the oracle."""
-    m, k, seed = 1 << 22, 2, 3
+    host spans several pair slots of every thread), on power-of-two pools
+    (the pool index a shift of the hash) and others (a high multiply).
+    Bit-identical to the partitioned and the direct gathers, and within the
+    bar of the oracle."""
+    k, seed = 2, 3
     rng = np.random.default_rng(g)
     aips = rng.integers(0, 2**32, 1500, dtype=np.uint64).astype(np.uint32)
     sk = V.Sketch(m, g, k, seed, "small")
