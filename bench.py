@@ -130,18 +130,23 @@ def scan_roofline(w, layout, ms):
 
 
 def learned_accuracy():
-    """Plain vs learned RMS relative error on one evaluation stream of the tiny
-    workload (the shape the network is trained on), and both estimators'
-    hosts/s there; None when no trained weights are present."""
-    import torch
-    from paper_1810_13132_amd import learn, vbdr
-    if not os.path.exists(learn.DEFAULT_WEIGHTS):
-        return None
-    params, lo, hi, meta = learn.load()
-    res = learn.evaluate(params, lo, hi, eval_seeds=range(100, 101))
-    res["workload"] = "tiny (2^12 hosts, 2^20 pairs/slice, m=2^18, g=256, k=4), eval seed 100"
-    res["trained_on"] = meta.get("train_seeds")
-    return res
+    """Plain vs learned RMS relative error, and both estimators' hosts/s, on
+    the evaluation streams (seeds 100..109) of each workload shape a network
+    was trained on: the tiny workload (all ten seeds) and the mid workload
+    (seeds 100..102); None when no trained weights are present."""
+    from paper_1810_13132_amd import learn, synth
+    out = {}
+    for name, path, w, seeds in (("tiny", learn.DEFAULT_WEIGHTS, synth.TINY, range(100, 110)),
+                                 ("mid", learn.MID_WEIGHTS, synth.MID, range(100, 103))):
+        if not os.path.exists(path):
+            continue
+        params, lo, hi, meta = learn.load(path)
+        res = learn.evaluate(params, lo, hi, eval_seeds=seeds, w=w)
+        res["workload"] = (f"{w.name} ({w.hosts} hosts, {w.pairs_per_slice} pairs/slice, m={w.m}, g={w.g}, "
+                           f"k={w.k}), eval seeds {min(seeds)}..{max(seeds)}")
+        res["trained_on"] = meta.get("train_seeds")
+        out[name] = res
+    return out or None
 
 
 def run_batched(args):
@@ -192,13 +197,16 @@ def run_stress(args):
     """Skewed contention: 16 planted superspreaders (10^6..10^7 opposite hosts)
     among 2^24 hosts, 2^27 pairs per slice into m = 2^24 BDRs (g = 2048,
     k = 128).  Each step estimates the superspreaders plus 2^16 sampled
-    background hosts; errors are reported per group over the slices seen."""
+    background hosts; errors are reported per group over the window of the
+    last timed step.  The timed steps start at slice k (first_slice): the
+    slices before it fill the window untimed (scan and advance only)."""
     import numpy as np
     import torch
     from paper_1810_13132_amd import learn, synth, vbdr
     torch.cuda.set_device(0)
     w = synth.STRESS
     K, W = args.steps, args.warmup
+    S0 = args.first_slice if args.first_slice is not None else max(w.k, W)
     st = synth.Stream(w)
     rng = np.random.default_rng(5)
     heavy = np.arange(w.n_heavy)
@@ -210,13 +218,22 @@ def run_stress(args):
     out = torch.empty(len(sel), dtype=torch.float32, device="cuda")
     seen_keys = []
     times = []
-    for t in range(W + K):
+    t0 = time.time()
+    for t in range(S0 + K):
         pd = vbdr.to_device_u32(st.slice(t).reshape(-1))
         p = pd.view(-1, 2).to(torch.int64) & 0xFFFFFFFF
         keep = torch.isin(p[:, 0], host_keys)
         seen_keys.append(torch.unique((p[keep, 0] << 32) | p[keep, 1]))
+        seen_keys = seen_keys[-w.k:]
         del p, keep
         torch.cuda.synchronize()
+        if t < S0 - W:  # aging: the state only
+            sk.scan_slice(pd)
+            sk.advance_slice()
+            if t % 8 == 0:
+                log(f"stress slice {t} (aging, {time.time() - t0:.0f}s)")
+            del pd
+            continue
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         sk.scan_slice(pd)
@@ -224,9 +241,9 @@ def run_stress(args):
         sk.estimate(hosts, out)
         b.record()
         b.synchronize()
-        if t >= W:
+        if t >= S0:
             times.append(a.elapsed_time(b))
-        log(f"stress slice {t}: {times[-1] if t >= W else a.elapsed_time(b):.2f} ms")
+        log(f"stress slice {t}: {a.elapsed_time(b):.2f} ms" + ("" if t >= S0 else " (warm-up)"))
         del pd
     truth = learn.window_truth(seen_keys[-w.k:], host_keys)
     est = out.to(torch.float64)
@@ -242,13 +259,14 @@ def run_stress(args):
            "warmup": W, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "u32", "data": "synthetic",
            "config": {"workload": "stress", "hosts": w.hosts, "pairs_per_slice": w.pairs_per_slice, "m": w.m,
-                      "g": w.g, "k": w.k, "layout": args.layout, "estimated_hosts": len(sel)},
+                      "g": w.g, "k": w.k, "layout": args.layout, "estimated_hosts": len(sel),
+                      "first_timed_slice": S0, "window_full": S0 >= w.k - 1},
            "rms_rel_superspreaders": learn.rms_rel(est[:w.n_heavy], truth[:w.n_heavy]),
            "rms_rel_background": learn.rms_rel(est[w.n_heavy:], truth[w.n_heavy:]),
            "detection": detect,
            "superspreader_truth": [int(v) for v in truth[:w.n_heavy].cpu()],
            "superspreader_estimate": [float(v) for v in est[:w.n_heavy].cpu()],
-           "slices_in_window": min(W + K, w.k)}
+           "slices_in_window": min(S0 + K, w.k)}
     print(json.dumps(res), flush=True)
 
 

@@ -425,6 +425,14 @@ void vbdr_batch_destroy(vbdr_batch *bt); /* NULL-safe; also frees its sketches *
  * owned by the batch.  NULL (and vbdr_last_error set) if i is out of range. */
 vbdr_sketch *vbdr_batch_sketch(vbdr_batch *bt, uint32_t i);
 
+/* Learned estimates for member i from the next step on (vbdr_estimate_learned
+ * semantics: the plain estimate where features leave the model's envelope);
+ * mlp = NULL returns the member to plain estimates.  The model stays the
+ * caller's and must outlive the steps that use it; it must live on the
+ * batch's device.  The member's learned estimate runs after the step's
+ * persistent kernels, on the batch's stream.  Waits for steps in flight. */
+int vbdr_batch_set_mlp(vbdr_batch *bt, uint32_t i, const vbdr_mlp *mlp);
+
 int vbdr_batch_set_tuning(vbdr_batch *bt, const vbdr_batch_tuning *tuning);
 int vbdr_batch_get_tuning(const vbdr_batch *bt, vbdr_batch_tuning *tuning);
 

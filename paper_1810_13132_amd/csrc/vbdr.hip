@@ -1323,15 +1323,12 @@ __device__ __forceinline__ unsigned long long sum_term(uint32_t r) {
   return (1ull << (32 - r)) | (r == 0 ? (1ull << 48) : 0ull);
 }
 
-// A (tile, host) sum U + V << 48 in 32 bits: V << 27 | U >> 18.  Exact when
-// every register was below 15 (terms 2^(32-r) are multiples of 2^18), V <= 30
-// and U >> 18 < 2^27; otherwise the sum goes to the host's overflow sum and
-// the entry is 0.
-__device__ __forceinline__ uint32_t pack_part(unsigned long long a, unsigned long long* ovf_h) {
-  const unsigned long long U = a & ((1ull << 48) - 1), V = a >> 48;
-  if ((U & ((1ull << 18) - 1)) == 0 && V <= 30 && (U >> 18) < (1ull << 27))
-    return (uint32_t)(V << 27 | U >> 18);
-  atomicAdd(ovf_h, a);
+// A (tile, host) sum U + V << 48 in 32 bits, from U in units of 2^18 (Us)
+// and the zero count V: V << 27 | Us.  Exact while Us < 2^27 and V <= 30;
+// otherwise the sum goes to the host's overflow sum and the entry is 0.
+__device__ __forceinline__ uint32_t pack_part32(uint32_t Us, uint32_t V, unsigned long long* ovf_h) {
+  if (V <= 30 && Us < (1u << 27)) return V << 27 | Us;
+  atomicAdd(ovf_h, ((unsigned long long)Us << 18) + ((unsigned long long)V << 48));
   return 0u;
 }
 
@@ -1408,40 +1405,54 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
     asm volatile("" : "+v"(tx));
     uint32_t pv[kTilePer], qv[kTilePer];
     auto pool_index = [&](uint32_t h) -> uint32_t { return POW2 ? h >> mshift : reduce_m(h, m); };
-    // every pair of a full chunk is valid: no per-pair select (uniform branch)
-    const bool whole = npairs == kTileChunk;
-    if (lg <= kTileBinLog) {  // one seed per thread; hosts (tx >> lg) + u * (kTileBinBlock >> lg)
-      const uint32_t sv = s1l[tx & (g - 1)];
-      const uint32_t* kp = kmix + (tx >> lg);
-      const uint32_t kst = kTileBinBlock >> lg;
-      if (whole) {
+    const bool whole = npairs == kTileChunk;  // a full chunk: no pair is padding
+    bool full = false;
+    if (lg == kTileBinLog && whole) {
+      // g = kTileBinBlock: pair u of every lane is (host u of the chunk,
+      // virtual index tx), so the host keys are uniform and sit in registers
+      const uint32_t sv = s1l[tx];
+      uint32_t km[kTilePer];
 #pragma unroll
-        for (int u = 0; u < kTilePer; ++u) pv[u] = pool_index(mm3_seeded(kp[(u * kst) & 63u], sv));
-      } else {
+      for (int u = 0; u < kTilePer; ++u) km[u] = kmix[u];
+#pragma unroll
+      for (int u = 0; u < kTilePer; ++u) pv[u] = pool_index(mm3_seeded(km[u], sv));
+#pragma unroll
+      for (int u = 0; u < kTilePer; ++u) qv[u] = atomicAdd(&cnt[pv[u] >> shift], 1u);
+#pragma unroll
+      for (int u = 0; u < kTilePer; ++u) {
+        const uint32_t p = pv[u];
+        bucket[__umul24(p >> shift, bstride) + (qv[u] < capb ? qv[u] : capb)] =
+            ((p & tmask) << kTileSlotBits) | (slot0 + (uint32_t)u);
+        full |= qv[u] >= capb;
+      }
+    } else {
+      if (lg <= kTileBinLog) {  // one seed per thread; hosts (tx >> lg) + u * (kTileBinBlock >> lg)
+        const uint32_t sv = s1l[tx & (g - 1)];
+        const uint32_t* kp = kmix + (tx >> lg);
+        const uint32_t kst = kTileBinBlock >> lg;
 #pragma unroll
         for (int u = 0; u < kTilePer; ++u) {  // branch-free: kmix is zero past the chunk's hosts
           const uint32_t p = pool_index(mm3_seeded(kp[(u * kst) & 63u], sv));
-          pv[u] = (uint32_t)u * kTileBinBlock + tx < npairs ? p : ~0u;
+          pv[u] = whole || (uint32_t)u * kTileBinBlock + tx < npairs ? p : ~0u;
+        }
+      } else {  // one host for g / kTileBinBlock consecutive u
+        const uint32_t gw = g >> kTileBinLog, hs = lg - kTileBinLog;
+#pragma unroll
+        for (int u = 0; u < kTilePer; ++u) {
+          const uint32_t p =
+              pool_index(mm3_seeded(kmix[(uint32_t)u >> hs], s1l[(((uint32_t)u & (gw - 1)) << kTileBinLog) + tx]));
+          pv[u] = whole || (uint32_t)u * kTileBinBlock + tx < npairs ? p : ~0u;
         }
       }
-    } else {  // one host for g / kTileBinBlock consecutive u
-      const uint32_t gw = g >> kTileBinLog, hs = lg - kTileBinLog;
+#pragma unroll
+      for (int u = 0; u < kTilePer; ++u) qv[u] = atomicAdd(&cnt[pv[u] != ~0u ? pv[u] >> shift : nt], 1u);
 #pragma unroll
       for (int u = 0; u < kTilePer; ++u) {
-        const uint32_t p =
-            pool_index(mm3_seeded(kmix[(uint32_t)u >> hs], s1l[(((uint32_t)u & (gw - 1)) << kTileBinLog) + tx]));
-        pv[u] = whole || (uint32_t)u * kTileBinBlock + tx < npairs ? p : ~0u;
+        const uint32_t p = pv[u], hl = ((uint32_t)u * kTileBinBlock + tx) >> lg;
+        const uint32_t t = p != ~0u ? p >> shift : nt;
+        bucket[__umul24(t, bstride) + (qv[u] < capb ? qv[u] : capb)] = ((p & tmask) << kTileSlotBits) | (slot0 + hl);
+        full |= p != ~0u && qv[u] >= capb;
       }
-    }
-#pragma unroll
-    for (int u = 0; u < kTilePer; ++u) qv[u] = atomicAdd(&cnt[pv[u] != ~0u ? pv[u] >> shift : nt], 1u);
-    bool full = false;
-#pragma unroll
-    for (int u = 0; u < kTilePer; ++u) {
-      const uint32_t p = pv[u], hl = ((uint32_t)u * kTileBinBlock + tx) >> lg;
-      const uint32_t t = p != ~0u ? p >> shift : nt;
-      bucket[__umul24(t, bstride) + (qv[u] < capb ? qv[u] : capb)] = ((p & tmask) << kTileSlotBits) | (slot0 + hl);
-      full |= p != ~0u && qv[u] >= capb;
     }
     if (full) {  // rare: entries beyond a bucket's capacity are gathered directly
 #pragma unroll
@@ -1502,7 +1513,12 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
 }
 
 // Pass 2: one workgroup per tile.  LDS: the tile's TR/2 nibble bytes (dynamic)
-// and two buffers of per-host sums (static): 160 KiB for tiles of 2^18.
+// and two buffers of per-host sums (static): 160 KiB for tiles of 2^18.  A
+// host's sum over one tile and sub-block is kept in 32 bits, exactly: the
+// nibble path's registers r < 15 add 2^(32-r) = 2^18 * 2^(14-r), and at most
+// g <= 8192 records add at most 2^13 * 2^14 < 2^32 in units of 2^18; zero
+// registers are counted apart.  Registers of 15 and more go straight to the
+// host's 64-bit overflow sum.
 template <int PRE>
 __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* __restrict__ reg4,
                                                                  const uint8_t* __restrict__ reg, uint64_t mstride,
@@ -1512,9 +1528,9 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
                                                                  uint32_t* __restrict__ part, uint32_t B,
                                                                  unsigned long long* __restrict__ ovf) {
   extern __shared__ uint32_t tile_w[];
-  // per-host sums, double-buffered: one barrier per sub-block
-  __shared__ unsigned long long acc2[2][kTileSub];
-  for (uint32_t q = threadIdx.x; q < 2 * kTileSub; q += kDeferBlock) (&acc2[0][0])[q] = 0;
+  // per-host sums in units of 2^18 and zero counts, double-buffered: one barrier per sub-block
+  __shared__ uint32_t accu2[2][kTileSub], accv2[2][kTileSub];
+  for (uint32_t q = threadIdx.x; q < 2 * kTileSub; q += kDeferBlock) (&accu2[0][0])[q] = 0, (&accv2[0][0])[q] = 0;
   const uint32_t t = blockIdx.x;
   const uint64_t tbase = (uint64_t)t << shift;
   const uint64_t nbytes = ((tbase + (1ull << shift) < mstride ? tbase + (1ull << shift) : mstride) - tbase) / 2;
@@ -1555,7 +1571,15 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     }
   }
   for (uint32_t sbk = 0; sbk < nsb; ++sbk) {
-    unsigned long long* acc = acc2[sbk & 1];
+    uint32_t* accu = accu2[sbk & 1];
+    uint32_t* accv = accv2[sbk & 1];
+    unsigned long long* ovf_sb = ovf + (uint64_t)sbk * kTileSub;
+    // the record of a register below 15 at host slot q: 2^(14-r) (and a zero count)
+    auto gather = [&](uint32_t rec, uint32_t nib) {
+      const uint32_t q = rec & (kTileSub - 1);
+      atomicAdd(&accu[q], 1u << (14 - nib));
+      if (nib == 0) atomicAdd(&accv[q], 1u);
+    };
     u32x4 cur[PQ];
     const uint32_t n = n_nxt;
 #pragma unroll
@@ -1591,7 +1615,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         if (nib[e] < 15u)
-          atomicAdd(&acc[cur[q][e] & (kTileSub - 1)], sum_term(nib[e]));
+          gather(cur[q][e], nib[e]);
         else if (nib[e] == 15u)
           wide |= 1u << (4 * q + e);
       }
@@ -1603,7 +1627,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
       const uint32_t off = rec >> kTileSlotBits;
       const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
       if (nib < 15u)
-        atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(nib));
+        gather(rec, nib);
       else
         wide_long = true;
     }
@@ -1612,7 +1636,7 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
       for (int u = 0; u < PRE; ++u)
         if ((wide >> u) & 1u) {
           const uint32_t rec = cur[u >> 2][u & 3];
-          atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(reg[tbase + (rec >> kTileSlotBits)]));
+          atomicAdd(ovf_sb + (rec & (kTileSub - 1)), sum_term(reg[tbase + (rec >> kTileSlotBits)]));
         }
     }
     if (wide_long) {
@@ -1621,14 +1645,14 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
         if (rec == ~0u) continue;
         const uint32_t off = rec >> kTileSlotBits;
         if (((tl[off >> 1] >> ((off & 1u) << 2)) & 15u) == 15u)
-          atomicAdd(&acc[rec & (kTileSub - 1)], sum_term(reg[tbase + off]));
+          atomicAdd(ovf_sb + (rec & (kTileSub - 1)), sum_term(reg[tbase + off]));
       }
     }
     __syncthreads();
     for (uint32_t q = threadIdx.x; q < kTileSub; q += kDeferBlock) {
       const uint32_t h = sbk * kTileSub + q;
-      part[(uint64_t)t * B + h] = pack_part(acc[q], ovf + h);
-      acc[q] = 0;  // gathered into again two sub-blocks on, after the next barrier
+      part[(uint64_t)t * B + h] = pack_part32(accu[q], accv[q], ovf + h);
+      accu[q] = 0, accv[q] = 0;  // gathered into again two sub-blocks on, after the next barrier
     }
   }
 }

@@ -194,6 +194,8 @@ struct vbdr_batch {
   // members with deferred scans: index in the deferred table, or ~0u
   std::vector<uint32_t> defer_of;
   uint32_t n_defer, defer_max_tiles, defer_max_L, defer_tiles;
+  // learned estimators by member (NULL: plain), owned by the caller
+  std::vector<const vbdr_mlp*> mlp;
 };
 
 namespace {
@@ -268,6 +270,7 @@ int vbdr_batch_create(uint32_t n_sketches, const vbdr_batch_params* params, vbdr
       if ((rc = vbdr_sketch_create_lean(p.m, p.g, p.k, p.hash_seed, p.layout, true, &s)) != VBDR_OK) break;
       bt->sk.push_back(s);
       // members with record runs scan and advance through the deferred kernels
+      bt->mlp.push_back(nullptr);
       if (s->def_rec) {
         bt->defer_of.push_back(bt->n_defer++);
         bt->defer_max_tiles = bt->defer_max_tiles > s->def_tiles ? bt->defer_max_tiles : s->def_tiles;
@@ -316,6 +319,13 @@ void vbdr_batch_destroy(vbdr_batch* bt) {
   if (bt->ev_out) (void)hipEventDestroy(bt->ev_out);
   if (bt->st) (void)hipStreamDestroy(bt->st);
   delete bt;
+}
+
+int vbdr_batch_set_mlp(vbdr_batch* bt, uint32_t i, const vbdr_mlp* mlp) {
+  if (!bt || i >= bt->S) return vbdr_fail(VBDR_EINVAL, "no sketch %u in this batch", i);
+  VBDR_HIP(hipStreamSynchronize(bt->st));  // steps already enqueued keep the estimator they were given
+  bt->mlp[i] = mlp;
+  return VBDR_OK;
 }
 
 vbdr_sketch* vbdr_batch_sketch(vbdr_batch* bt, uint32_t i) {
@@ -392,11 +402,13 @@ int vbdr_batch_step(vbdr_batch* bt, const uint32_t* const* pairs_dev, const uint
     D.pairs = pairs_dev[s], D.n_pairs = n_pairs[s];
     D.hosts = hosts_dev[s], D.n_hosts = n_hosts[s], D.out = out_dev[s];
     D.scan_item0 = si, D.adv_item0 = ai, D.est_item0 = ei, D.pad = 0;
+    // members with a learned estimator are estimated after the step's kernels
+    const uint64_t n_plain = bt->mlp[s] ? 0 : n_hosts[s];
     if (di == ~0u) {
       si += (uint32_t)((n_pairs[s] + bt->tune.scan_tile - 1) / bt->tune.scan_tile);
       ai += (uint32_t)(k->mstride / kAdvTile);
     }
-    ei += (uint32_t)((n_hosts[s] + bt->tune.est_tile - 1) / bt->tune.est_tile);
+    ei += (uint32_t)((n_plain + bt->tune.est_tile - 1) / bt->tune.est_tile);
   }
   std::memset(hdr, 0, sizeof(*hdr));
   hdr->scan_total = si, hdr->adv_total = ai, hdr->est_total = ei;
@@ -423,6 +435,10 @@ int vbdr_batch_step(vbdr_batch* bt, const uint32_t* const* pairs_dev, const uint
   } else if (int rc = launch_step_kernels(bt)) {
     return rc;
   }
+  for (uint32_t s = 0; s < S; ++s)
+    if (bt->mlp[s] && n_hosts[s])
+      if (int rc = vbdr_estimate_learned(bt->sk[s], bt->mlp[s], hosts_dev[s], n_hosts[s], out_dev[s], nullptr, bt->st))
+        return rc;
   VBDR_HIP(hipEventRecord(bt->ev_out, bt->st));
   VBDR_HIP(hipStreamWaitEvent(user, bt->ev_out, 0));
   for (vbdr_sketch* k : bt->sk) k->t++;

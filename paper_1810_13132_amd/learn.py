@@ -1,14 +1,19 @@
 """Train and evaluate the learned estimator (GPU).
 
 Samples are (features, ln(1 + n)) of every host after every slice once the
-window is full, on streams shaped like the tiny workload (2^12 hosts, 2^20
-pairs per slice, 12 slices, m = 2^18, g = 256, k = 4): training seeds 0..99
-(10^6 samples drawn from the 3,686,400), evaluation seeds 100..109.  Features
-come from the library's own scan / advance / feature kernels; the truth is the
-exact distinct count of the window's pairs (Definition 1), computed on the
-device with sort-unique.  Training runs the library's float32 Adam kernels.
+window is full, on streams of one workload shape: by default the tiny workload
+(2^12 hosts, 2^20 pairs per slice, 12 slices, m = 2^18, g = 256, k = 4):
+training seeds 0..99 (10^6 samples drawn from the 3,686,400), evaluation seeds
+100..109.  With --workload mid: the mid workload (2^14 hosts, 2^22 pairs per
+slice, 24 slices, m = 2^20, g = 512, k = 16), training seeds 0..39, the same
+evaluation seeds.  Features come from the library's own scan / advance /
+feature kernels; the truth is the exact distinct count of the window's pairs
+(Definition 1), computed on the device with sort-unique.  Training runs the
+library's float32 Adam kernels.
 
     python -m paper_1810_13132_amd.learn --out paper_1810_13132_amd/weights/mlp_tiny.npz
+    python -m paper_1810_13132_amd.learn --workload mid --train-seeds 40 \
+        --out paper_1810_13132_amd/weights/mlp_mid.npz
 """
 import argparse
 import json
@@ -24,6 +29,8 @@ from paper_1810_13132_amd import synth, vbdr
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(PKG, "weights", "mlp_tiny.npz")
+MID_WEIGHTS = os.path.join(PKG, "weights", "mlp_mid.npz")
+WORKLOADS = {"tiny": synth.TINY, "mid": synth.MID}
 
 
 def log(*a):
@@ -89,11 +96,11 @@ def init_params(seed: int):
     return np.concatenate(parts).astype(np.float32)
 
 
-def train(train_seeds=range(100), n_samples=10**6, epochs=30, batch=4096, lr=3e-3, seed=0):
+def train(train_seeds=range(100), n_samples=10**6, epochs=30, batch=4096, lr=3e-3, seed=0, w=synth.TINY):
     t0 = time.time()
     feats, targets = [], []
     for s in train_seeds:
-        for rec in stream_samples(s):
+        for rec in stream_samples(s, w):
             feats.append(rec["feats"])
             targets.append(torch.log1p(rec["truth"].to(torch.float32)))
         if s % 10 == 9:
@@ -121,14 +128,14 @@ def train(train_seeds=range(100), n_samples=10**6, epochs=30, batch=4096, lr=3e-
             step += 1
         log(f"epoch {ep}: mean batch loss {float(loss.cpu()[0]) / steps_per_epoch:.5f} ({time.time() - t0:.1f}s)")
     return tr.params(), lo, hi, {"samples": int(len(Y)), "epochs": epochs, "batch": batch, "lr": lr,
-                                 "train_seeds": [min(train_seeds), max(train_seeds)]}
+                                 "train_seeds": [min(train_seeds), max(train_seeds)], "workload": w.name}
 
 
-def evaluate(params, lo, hi, eval_seeds=range(100, 110)):
+def evaluate(params, lo, hi, eval_seeds=range(100, 110), w=synth.TINY):
     mlp = vbdr.MLP(params, lo, hi)
     ests, truths, plains, fbs = [], [], [], []
     for s in eval_seeds:
-        for rec in stream_samples(s, mlp=mlp):
+        for rec in stream_samples(s, w, mlp=mlp):
             ests.append(rec["learned"])
             plains.append(rec["plain"])
             truths.append(rec["truth"])
@@ -137,14 +144,14 @@ def evaluate(params, lo, hi, eval_seeds=range(100, 110)):
     res = {"samples": int(len(truth)), "samples_n_ge_1": int((truth >= 1).sum()),
            "rms_rel_plain": rms_rel(plain, truth), "rms_rel_learned": rms_rel(est, truth),
            "fallback_frac": float(fb.float().mean()), "eval_seeds": [min(eval_seeds), max(eval_seeds)]}
-    # estimation throughput on the same sketch shape, all 2^12 hosts, plain vs learned
-    w = synth.TINY
+    # estimation throughput on the same sketch shape with a full window, the
+    # stream's hosts repeated to 2^18 estimates per launch, plain vs learned
     st = synth.Stream(w.scaled(seed=min(eval_seeds)))
     sk = vbdr.Sketch(w.m, w.g, w.k, 0, "fast")
     for t in range(w.k):
         sk.scan_slice(vbdr.to_device_u32(st.slice(t).reshape(-1)))
         sk.advance_slice()
-    hosts = vbdr.to_device_u32(np.tile(st.aip, 64))  # 2^18 estimates per launch
+    hosts = vbdr.to_device_u32(np.tile(st.aip, max(1, (1 << 18) // w.hosts)))
     out = torch.empty(hosts.numel(), dtype=torch.float32, device="cuda")
 
     def rate(fn):
@@ -170,17 +177,21 @@ def load(path=DEFAULT_WEIGHTS):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--workload", default="tiny", choices=sorted(WORKLOADS))
+    ap.add_argument("--out", default=None)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--train-seeds", type=int, default=100)
     ap.add_argument("--samples", type=int, default=10**6)
     ap.add_argument("--eval-only", action="store_true")
     args = ap.parse_args()
+    w = WORKLOADS[args.workload]
+    if args.out is None:
+        args.out = DEFAULT_WEIGHTS if args.workload == "tiny" else MID_WEIGHTS
     if args.eval_only:
         params, lo, hi, meta = load(args.out)
     else:
-        params, lo, hi, meta = train(range(args.train_seeds), args.samples, args.epochs)
-    res = evaluate(params, lo, hi)
+        params, lo, hi, meta = train(range(args.train_seeds), args.samples, args.epochs, w=w)
+    res = evaluate(params, lo, hi, w=w)
     meta["eval"] = res
     if not args.eval_only:
         os.makedirs(os.path.dirname(args.out), exist_ok=True)

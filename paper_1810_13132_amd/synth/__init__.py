@@ -8,6 +8,9 @@ stream model is described in synth.c.  Workload presets:
                    per slice, 12 slices; sketch m=2^18, g=256, k=4.
 * ``LINE_RATE`` -- 2^20 hosts, Zipf(1.2) on 1..10^6, 2^26 pairs per slice,
                    64 slices; sketch m=2^26, g=1024, k=60.
+* ``MID``       -- 2^14 hosts, Zipf(1.1) on 1..10^4, 2^22 pairs per slice,
+                   24 slices; sketch m=2^20, g=512, k=16 (the size of a
+                   typical member of the batched workload).
 * ``STRESS``    -- 2^24 hosts, 16 planted heavy hosts with 10^6..10^7
                    opposite hosts, Zipf(1.5) on 1..10^4 elsewhere, 2^27
                    pairs per slice; sketch m=2^24, g=2048, k=128.
@@ -87,6 +90,8 @@ TINY = Workload("tiny", seed=0, hosts=1 << 12, zipf_s=1.1, nmax=10**4, pairs_per
                 slices=12, m=1 << 18, g=256, k=4)
 LINE_RATE = Workload("line_rate", seed=1, hosts=1 << 20, zipf_s=1.2, nmax=10**6,
                      pairs_per_slice=1 << 26, slices=64, m=1 << 26, g=1024, k=60)
+MID = Workload("mid", seed=3, hosts=1 << 14, zipf_s=1.1, nmax=10**4, pairs_per_slice=1 << 22,
+               slices=24, m=1 << 20, g=512, k=16)
 STRESS = Workload("stress", seed=5, hosts=1 << 24, zipf_s=1.5, nmax=10**4, pairs_per_slice=1 << 27,
                   slices=144, m=1 << 24, g=2048, k=128, n_heavy=16)
 

@@ -64,7 +64,8 @@ EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_creat
            "vbdr_trainer_params", "vbdr_batch_create", "vbdr_batch_destroy", "vbdr_batch_sketch",
            "vbdr_batch_set_tuning", "vbdr_batch_get_tuning", "vbdr_batch_step", "vbdr_select_hosts",
            "vbdr_export_now", "vbdr_import_now", "vbdr_now_max", "vbdr_enable_pcsa", "vbdr_estimate_kind",
-           "vbdr_export_pcsa", "vbdr_test_fail_alloc", "vbdr_estimate_noalloc"]
+           "vbdr_export_pcsa", "vbdr_test_fail_alloc", "vbdr_estimate_noalloc",
+           "vbdr_batch_set_mlp"]
 VOID_EXPORTS = ("vbdr_sketch_destroy", "vbdr_last_error", "vbdr_mlp_destroy", "vbdr_trainer_destroy",
                 "vbdr_batch_destroy", "vbdr_batch_sketch")
 MLP_IN, MLP_PARAMS = 67, 8577
@@ -109,6 +110,7 @@ def lib():
         L.vbdr_batch_destroy.argtypes = [vp]
         L.vbdr_batch_sketch.argtypes = [vp, u32]
         L.vbdr_batch_set_tuning.argtypes = [vp, C.POINTER(BatchTuning)]
+        L.vbdr_batch_set_mlp.argtypes = [vp, u32, vp]
         L.vbdr_batch_get_tuning.argtypes = [vp, C.POINTER(BatchTuning)]
         L.vbdr_select_hosts.argtypes = [vp, vp, u64, C.c_float, vp, vp, u64, vp, vp]
         L.vbdr_export_now.argtypes = [vp, vp, vp]
@@ -499,6 +501,10 @@ class Batch:
     def set_tuning(self, scan_tile=8192, est_tile=64, blocks_per_cu=8, use_graph=True):
         t = BatchTuning(scan_tile, est_tile, blocks_per_cu, 1 if use_graph else 0)
         _check(lib().vbdr_batch_set_tuning(self._h, C.byref(t)))
+
+    def set_mlp(self, i: int, mlp: "MLP" = None):
+        """Learned estimates for sketch i (None: plain); keep `mlp` alive while steps use it."""
+        _check(lib().vbdr_batch_set_mlp(self._h, i, None if mlp is None else mlp._h))
 
     def get_tuning(self) -> dict:
         t = BatchTuning()

@@ -160,3 +160,38 @@ def test_batch_deferred_member_overflow(V, layout):
         ss = single.state()
         for key in ("dr", "bs", "reg", "hist"):
             assert np.array_equal(sb[key], ss[key]), key
+
+
+def test_batch_learned_members(V):
+    """Members with a learned estimator (vbdr_batch_set_mlp) get the learned
+    estimates of the same sketch stepped alone (bit for bit); the others keep
+    their plain estimates; removing the model returns the member to plain."""
+    rng = np.random.default_rng(21)
+    params = [dict(m=70001, g=128, k=4, hash_seed=1, layout="fast"),
+              dict(m=1 << 18, g=256, k=4, hash_seed=2, layout="small"),
+              dict(m=(1 << 22) + 3, g=256, k=8, hash_seed=5, layout="fast")]
+    w = rng.standard_normal(V.MLP_PARAMS).astype(np.float32) * 0.1
+    mlp = V.MLP(w)  # no envelope: every host takes the network's estimate
+    bt = V.Batch(params)
+    bt.set_mlp(1, mlp)
+    bt.set_mlp(2, mlp)
+    singles = [V.Sketch(**p) for p in params]
+    sizes = [20000, 60000, 90000]
+    aips = [rng.integers(0, 2**32, 300, dtype=np.uint64).astype(np.uint32) for _ in params]
+    hd = [V.to_device_u32(a) for a in aips]
+    for t in range(5):
+        if t == 4:
+            bt.set_mlp(2, None)
+        pd = [V.to_device_u32(np.stack([a[rng.integers(0, len(a), n)],
+                                        rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1)
+                              .astype(np.uint32).reshape(-1)) for a, n in zip(aips, sizes)]
+        outs = [torch.empty(len(a), dtype=torch.float32, device="cuda") for a in aips]
+        bt.step(pd, hd, outs)
+        for i, sk in enumerate(singles):
+            sk.scan_slice(pd[i])
+            sk.advance_slice()
+        assert torch.equal(outs[0], singles[0].estimate(hd[0]))
+        assert torch.equal(outs[1], singles[1].estimate_learned(mlp, hd[1]))
+        ref2 = singles[2].estimate(hd[2]) if t == 4 else singles[2].estimate_learned(mlp, hd[2])
+        assert torch.equal(outs[2], ref2), t
+        assert not torch.equal(outs[1], singles[1].estimate(hd[1]))
