@@ -7,10 +7,11 @@
  * check and the CPU-baseline leg of the benchmark may load this library.
  * It shares no code, header or table with the HIP library.
  *
- * Every routine follows the paper's steps in the paper's order, written for
- * clarity rather than speed: getPhyIdx recomputes its seed hash on every
- * call, GetLBP1BDR walks the recorder vector from the top, and the scan
- * touches one pair at a time.  Integer state is exact; estimates are FP64.
+ * Every routine computes what the paper defines, written for clarity rather
+ * than speed: the pool index of a virtual recorder is rehashed on every
+ * call, a register is found by looking at every recorder of its BDR, and
+ * the scan records one pair at a time.  Integer state is exact; estimates
+ * are FP64.
  *
  * Readings of the paper taken here (the paper is silent or garbled):
  *  - The pool size is called m (the paper reuses the letter z for it and for
@@ -133,9 +134,6 @@ uint64_t vbdro_splitmix64(uint64_t *s)
     return z ^ (z >> 31);
 }
 
-/* LB(x, i): the left i bits of the 32-bit x (Sec. 4.1). */
-static uint32_t LB(uint32_t x, uint32_t i) { return i == 0 ? 0u : x >> (32 - i); }
-
 /* LBP1 of the (32-b)-bit string held in the top bits of w (Sec. 3, the
  * HyperLogLog rho): the position, counted from 1 at the left, of the
  * leftmost 1 bit; (32-b)+1 when all 32-b bits are 0. */
@@ -248,23 +246,23 @@ void vbdro_destroy(vbdro_sketch *s)
     free(s->drv), free(s->reg), free(s->now), free(s->bs), free(s->preg), free(s);
 }
 
-/* DR operations of Sec. 3. */
-static void SetDR(uint8_t *dr) { *dr = 0; }
-static void SlideDR(const vbdro_sketch *s, uint8_t *dr)
-{
-    if (*dr < s->sat)
-        (*dr)++;
-}
-static int IsActiveDR(uint8_t dr, uint32_t k) { return dr < k; }
+/* Distance recorders (Sec. 3).  A recorder holds how many slices ago its
+ * LBP1 was last seen: 0 in the slice that sets it, one more for every slice
+ * that closes, held at the saturation value.  It counts as active (the LBP1
+ * lies in the window of the last k slices) while it is below k. */
+static int dr_active(const vbdro_sketch *s, uint8_t dr) { return dr < s->k; }
+static uint8_t dr_aged(const vbdro_sketch *s, uint8_t dr) { return dr < s->sat ? (uint8_t)(dr + 1) : dr; }
 
-static uint8_t *DRV(vbdro_sketch *s, uint64_t p) { return s->drv + p * (s->L + 1); }
+/* The recorders of BDR p, indexed by LBP1 (entry 0 unused). */
+static uint8_t *recorders(vbdro_sketch *s, uint64_t p) { return s->drv + p * (s->L + 1); }
 
-/* Alg. 3 getPhyIdx: seed s1 from the virtual index, then hash the host
- * into the pool of m BDRs. */
+/* Where virtual recorder i of host aip lives in the pool (Sec. 4.1): the
+ * index i, hashed with A0, is the seed under which aip is hashed into
+ * [0, m).  Recomputed on every call, as plain as it can be. */
 static uint32_t phy_idx(uint64_t m, uint32_t A0, uint32_t aip, uint32_t i)
 {
-    uint32_t s1 = vbdro_H(i, 1ull << 32, A0);
-    return vbdro_H(aip, m, s1);
+    uint32_t seed = vbdro_H(i, 1ull << 32, A0);
+    return vbdro_H(aip, m, seed);
 }
 
 uint32_t vbdro_phy_idx(const vbdro_sketch *s, uint32_t aip, uint32_t i)
@@ -272,21 +270,26 @@ uint32_t vbdro_phy_idx(const vbdro_sketch *s, uint32_t aip, uint32_t i)
     return phy_idx(s->m, s->A0, aip, i);
 }
 
-/* Steps shared by Alg. 4, 7 and 9: from a pair to (pidx, LBP1). */
-static void map_pair(const vbdro_sketch *s, uint32_t aip, uint32_t bip, uint32_t *pidx, uint32_t *r)
+/* The BDR a pair touches and the LBP1 it records (Sec. 4.1).  One hash of
+ * bip under A1 gives both: its top b bits name one of the host's g virtual
+ * recorders, and the LBP1 is the 1-based rank of the leftmost 1 among its
+ * other 32-b bits, 33-b when they are all 0.  Moving those bits to the top
+ * and putting a 1 just below them turns that into one leading-zero count
+ * (b >= 1, as g >= 2). */
+static void pair_target(const vbdro_sketch *s, uint32_t aip, uint32_t bip, uint32_t *pidx, uint32_t *rho)
 {
-    uint32_t bh = vbdro_H(bip, 1ull << 32, s->A1);
-    uint32_t vidx = LB(bh, s->b);
-    bh = bh << s->b;
-    *pidx = vbdro_phy_idx(s, aip, vidx);
-    *r = vbdro_lbp1(bh, s->b);
+    uint32_t h = vbdro_H(bip, 1ull << 32, s->A1);
+    uint32_t virt = h >> (32 - s->b);
+    uint32_t rest = (h << s->b) | (1u << (s->b - 1));
+    *rho = (uint32_t)__builtin_clz(rest) + 1;
+    *pidx = phy_idx(s->m, s->A0, aip, virt);
 }
 
 void vbdro_pair_map(const vbdro_sketch *s, const uint32_t *pairs, uint64_t n, uint32_t *pidx, uint8_t *rho)
 {
     for (uint64_t j = 0; j < n; j++) {
         uint32_t p, r;
-        map_pair(s, pairs[2 * j], pairs[2 * j + 1], &p, &r);
+        pair_target(s, pairs[2 * j], pairs[2 * j + 1], &p, &r);
         pidx[j] = p;
         rho[j] = (uint8_t)r;
     }
@@ -310,78 +313,83 @@ int vbdro_map_pairs(uint64_t m, uint32_t g, uint64_t hash_seed, const uint32_t *
     return 0;
 }
 
-/* Scan the pairs of the open slice: Alg. 4 (serial), Alg. 7 (fast GPU
- * layout), Alg. 9 (small GPU layout), one pair at a time. */
+/* Record the pairs of the open slice, one at a time (Sec. 3 and 4.1-4.2).
+ * What is kept until the slice closes depends on the layout: the largest
+ * LBP1 per BDR (serial), a bitmap of the LBP1 values seen (fast GPU
+ * layout), or the recorder of each LBP1 seen, zeroed at once (small GPU
+ * layouts; the packed one keeps Lc recorders, higher LBP1 values landing
+ * on recorder Lc). */
 void vbdro_scan(vbdro_sketch *s, const uint32_t *pairs, uint64_t n)
 {
     for (uint64_t j = 0; j < n; j++) {
         uint32_t p, r;
-        map_pair(s, pairs[2 * j], pairs[2 * j + 1], &p, &r);
-        if (s->layout == VBDRO_SERIAL) {
+        pair_target(s, pairs[2 * j], pairs[2 * j + 1], &p, &r);
+        switch (s->layout) {
+        case VBDRO_SERIAL:
             if (r > s->now[p])
                 s->now[p] = (uint8_t)r;
-        } else if (s->layout == VBDRO_GFAST) {
+            break;
+        case VBDRO_GFAST:
             s->bs[p] |= 1u << (r - 1);
-        } else {
-            SetDR(&DRV(s, p)[r < s->Lc ? r : s->Lc]);
+            break;
+        default:
+            recorders(s, p)[r < s->Lc ? r : s->Lc] = 0;
         }
     }
 }
 
-/* Alg. 2 GetLBP1BDR: the largest LBP1 whose DR is active, else 0. */
-static uint32_t GetLBP1BDR(vbdro_sketch *s, uint64_t p)
+/* The register of BDR p over the window (Sec. 3): the largest LBP1 whose
+ * recorder is active, 0 if none is. */
+static uint32_t window_register(vbdro_sketch *s, uint64_t p)
 {
-    uint8_t *v = DRV(s, p);
-    for (uint32_t lbp1 = s->Lc; lbp1 >= 1; lbp1--)
-        if (IsActiveDR(v[lbp1], s->k))
-            return lbp1;
-    return 0;
+    const uint8_t *v = recorders(s, p);
+    uint32_t reg = 0;
+    for (uint32_t r = 1; r <= s->Lc; r++)
+        if (dr_active(s, v[r]))
+            reg = r;
+    return reg;
 }
 
-/* PCSA reading of a recorder vector: the number of consecutive active DRs
- * from LBP1 1 upwards, i.e. the index of the lowest unset bitmap bit. */
-static uint32_t PcsaRun(vbdro_sketch *s, uint64_t p)
+/* The PCSA reading of BDR p (the recorders as a bitmap of the LBP1 values
+ * seen in the window): how many LBP1 values from 1 up are all active. */
+static uint32_t pcsa_run(vbdro_sketch *s, uint64_t p)
 {
-    uint8_t *v = DRV(s, p);
-    uint32_t r = 0;
-    while (r < s->Lc && IsActiveDR(v[r + 1], s->k))
-        r++;
-    return r;
+    const uint8_t *v = recorders(s, p);
+    uint32_t run = 0;
+    while (run < s->Lc && dr_active(s, v[run + 1]))
+        run++;
+    return run;
 }
 
-/* Close the open slice. */
+/* Close the open slice.  In the serial and fast layouts every recorder ages
+ * by one slice and then the slice's own largest LBP1 (the kept maximum, or
+ * the highest bit of the bitmap) is recorded at 0, after which the window
+ * is read.  The small layouts zeroed their recorders during the scan, so
+ * the closing window is read first and the ageing for the next slice
+ * comes after it (Sec. 4.2).  Then the pool's register histogram. */
 void vbdro_advance(vbdro_sketch *s)
 {
     for (uint64_t p = 0; p < s->m; p++) {
-        uint8_t *v = DRV(s, p);
-        if (s->layout == VBDRO_SERIAL) {
-            /* Alg. 1 EndSliceUpdateBDR, then nowLBP1 starts the next slice at 0. */
-            for (uint32_t i = 1; i <= s->L; i++)
-                SlideDR(s, &v[i]);
-            if (s->now[p] > 0)
-                SetDR(&v[s->now[p]]);
-            s->now[p] = 0;
-            s->reg[p] = (uint8_t)GetLBP1BDR(s, p);
-        } else if (s->layout == VBDRO_GFAST) {
-            /* Alg. 6 EndSliceUpdateBDRGpu: the slice's LBP1 is the highest
-             * set bit of bsLBP1; bsLBP1 is reset for the next slice. */
-            for (uint32_t i = 1; i <= s->L; i++)
-                SlideDR(s, &v[i]);
-            uint32_t lbp1 = 0;
-            for (uint32_t i = 1; i <= s->L; i++)
-                if ((s->bs[p] >> (i - 1)) & 1u)
-                    lbp1 = i;
-            if (lbp1 > 0)
-                SetDR(&v[lbp1]);
-            s->bs[p] = 0;
-            s->reg[p] = (uint8_t)GetLBP1BDR(s, p);
+        uint8_t *v = recorders(s, p);
+        if (s->layout == VBDRO_SERIAL || s->layout == VBDRO_GFAST) {
+            uint32_t top;
+            if (s->layout == VBDRO_SERIAL) {
+                top = s->now[p];
+                s->now[p] = 0;
+            } else {
+                top = s->bs[p] ? 32u - (uint32_t)__builtin_clz(s->bs[p]) : 0u;
+                s->bs[p] = 0;
+            }
+            for (uint32_t r = 1; r <= s->L; r++)
+                v[r] = dr_aged(s, v[r]);
+            if (top > 0)
+                v[top] = 0;
+            s->reg[p] = (uint8_t)window_register(s, p);
         } else {
-            /* Small layout: read the closed window first (Alg. 2), then
-             * Alg. 8 BeginSliceUpdateDRV for the next slice. */
-            s->reg[p] = (uint8_t)GetLBP1BDR(s, p);
-            s->preg[p] = (uint8_t)PcsaRun(s, p);
-            for (uint32_t i = 1; i <= s->L; i++)
-                SlideDR(s, &v[i]);
+            s->reg[p] = (uint8_t)window_register(s, p);
+            s->preg[p] = (uint8_t)pcsa_run(s, p);
+            for (uint32_t r = 1; r <= s->L; r++)
+                v[r] = dr_aged(s, v[r]);
         }
     }
     memset(s->pool_hist, 0, sizeof(s->pool_hist));
@@ -431,7 +439,7 @@ static void estimate_hosts(uint64_t m, uint32_t g, uint32_t A0, const uint8_t *r
         memset(hist, 0, sizeof(hist));
         for (uint32_t i = 0; i < g; i++) {
             uint32_t pidx = phy_idx(m, A0, hosts[h], i);
-            hist[reg[pidx]]++; /* the register GetLBP1BDR gave at the close */
+            hist[reg[pidx]]++; /* the BDR's register at the close */
         }
         double Es = vbdro_hll_from_hist(hist, (double)g);
         double nh = ((double)m * Es - (double)g * Em) / ((double)m - (double)g);
