@@ -1291,10 +1291,10 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ est, c
 // 1-byte gathers.  Tiled: the pool's nibble registers are cut into nt <= 256
 // tiles of TR = 2^shift registers (at most 128 KiB of nibbles), one per
 // workgroup, held in LDS.  Per block of B hosts:
-//   pass 1 hashes every (host, i) once and appends the record
-//          (offset in tile << 11 | host slot in its sub-block of 2048) to the
-//          run of (sub-block, tile), sorted by tile in LDS as in the deferred
-//          scan;
+//   pass 1 hashes every (host, i) once and appends a record of the
+//          register's offset in its tile and the host's slot in its
+//          sub-block of 2048 (tile_rec) to the run of (sub-block, tile),
+//          sorted by tile in LDS as in the deferred scan;
 //   pass 2 runs tile t on one workgroup: it loads the tile into LDS once and,
 //          sub-block by sub-block, gathers the runs' registers from LDS into
 //          per-host sums (U + V << 48, exact integers) and writes them out;
@@ -1302,7 +1302,22 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ est, c
 //          the FP64 epilogue of the other estimates.
 // Every gather is an LDS read; memory sees only streaming records and sums.
 constexpr uint32_t kTileSlotBits = 11;
-constexpr uint32_t kTileSub = 1u << kTileSlotBits;  // hosts per sub-block (slot bits of a record)
+constexpr uint32_t kTileSub = 1u << kTileSlotBits;  // hosts per sub-block
+// A record: bit 31 the nibble of the register's byte (offset & 1), bits
+// 17..28 the host's slot in its sub-block plus one (12 bits), bits 0..16 the
+// byte (offset >> 1; tiles hold at most 2^18 registers), bits 29..30 zero,
+// so that record >> 29 is the nibble's bit shift.  Padding is the record 0
+// (slot field 0, offset 0): pass 2 gathers it like any record, into an
+// accumulator that is never read, and its bounded loads return it past the
+// end of a run.
+constexpr uint32_t kTilePad = 0u;
+__device__ __forceinline__ uint32_t tile_rec(uint32_t off, uint32_t slot) {
+  return (off << 31) | ((slot + 1u) << 17) | (off >> 1);
+}
+__device__ __forceinline__ uint32_t tile_rec_acc(uint32_t rec) { return (rec >> 17) & 0xFFFu; }  // slot + 1; 0 for padding
+__device__ __forceinline__ uint32_t tile_rec_slot(uint32_t rec) { return tile_rec_acc(rec) - 1u; }
+__device__ __forceinline__ uint32_t tile_rec_off(uint32_t rec) { return ((rec & 0x1FFFFu) << 1) | (rec >> 31); }
+constexpr uint32_t kBufferRsrcWord3 = 0x00020000u;  // raw buffer resource, gfx9 family
 constexpr uint32_t kTileMaxShift = 18;    // 2^18 registers = 128 KiB of nibbles
 constexpr int kTileBinLog = 10;
 constexpr int kTileBinBlock = 1 << kTileBinLog;  // pass 1 workgroup
@@ -1421,8 +1436,7 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
       for (int u = 0; u < kTilePer; ++u) {
         const uint32_t p = pv[u];
-        bucket[__umul24(p >> shift, bstride) + (qv[u] < capb ? qv[u] : capb)] =
-            ((p & tmask) << kTileSlotBits) | (slot0 + (uint32_t)u);
+        bucket[__umul24(p >> shift, bstride) + (qv[u] < capb ? qv[u] : capb)] = tile_rec(p & tmask, slot0 + (uint32_t)u);
         full |= qv[u] >= capb;
       }
     } else {
@@ -1450,7 +1464,7 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
       for (int u = 0; u < kTilePer; ++u) {
         const uint32_t p = pv[u], hl = ((uint32_t)u * kTileBinBlock + tx) >> lg;
         const uint32_t t = p != ~0u ? p >> shift : nt;
-        bucket[__umul24(t, bstride) + (qv[u] < capb ? qv[u] : capb)] = ((p & tmask) << kTileSlotBits) | (slot0 + hl);
+        bucket[__umul24(t, bstride) + (qv[u] < capb ? qv[u] : capb)] = tile_rec(p & tmask, slot0 + hl);
         full |= p != ~0u && qv[u] >= capb;
       }
     }
@@ -1485,23 +1499,23 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
       kmix[lane] = host_of(c0n) ? mm3_key(hnext) : 0u;
     }
     __syncthreads();
-    if (wave != 0) {  // 16 lanes per bucket, four records (16 bytes) per lane; the tail quad padded with ~0u
+    if (wave != 0) {  // 16 lanes per bucket, four records (16 bytes) per lane; the tail quad padded
       const uint32_t ql = lane & 15;
       for (uint32_t t = 4 * (wave - 1) + (lane >> 4); t < nt; t += 4 * kCopyWaves) {
         const uint32_t c = cntc[t], b0 = base[t];
         uint32_t* run = recs + ((uint64_t)sb * nt + t) * cap;
         for (uint32_t i = 4 * ql; i < c; i += 64) {
           uint4 v = *reinterpret_cast<const uint4*>(bucket + t * bstride + i);
-          if (i + 1 >= c) v.y = ~0u;
-          if (i + 2 >= c) v.z = ~0u;
-          if (i + 3 >= c) v.w = ~0u;
+          if (i + 1 >= c) v.y = kTilePad;
+          if (i + 2 >= c) v.z = kTilePad;
+          if (i + 3 >= c) v.w = kTilePad;
           if (b0 + i < cap) {  // cap and b0 are multiples of 4: the quad fits whole
             *reinterpret_cast<uint4*>(run + b0 + i) = v;
           } else {  // run full: gather directly
             const uint32_t r4[4] = {v.x, v.y, v.z, v.w};
             for (int j = 0; j < 4; ++j)
-              if (r4[j] != ~0u)
-                atomicAdd(ovf_sb + (r4[j] & (kTileSub - 1)), sum_term(reg[((uint64_t)t << shift) + (r4[j] >> kTileSlotBits)]));
+              if (r4[j] != kTilePad)
+                atomicAdd(ovf_sb + tile_rec_slot(r4[j]), sum_term(reg[((uint64_t)t << shift) + tile_rec_off(r4[j])]));
           }
         }
       }
@@ -1512,13 +1526,24 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
   }
 }
 
-// Pass 2: one workgroup per tile.  LDS: the tile's TR/2 nibble bytes (dynamic)
-// and two buffers of per-host sums (static): 160 KiB for tiles of 2^18.  A
+// Pass 2: one workgroup per tile.  LDS (dynamic, tile_gather_lds): the
+// tile's TR/2 nibble bytes at address 0, then two buffers of per-host sums
+// and zero counts: 152 KiB for tiles of 2^18.  A
 // host's sum over one tile and sub-block is kept in 32 bits, exactly: the
 // nibble path's registers r < 15 add 2^(32-r) = 2^18 * 2^(14-r), and at most
-// g <= 8192 records add at most 2^13 * 2^14 < 2^32 in units of 2^18; zero
-// registers are counted apart.  Registers of 15 and more go straight to the
-// host's 64-bit overflow sum.
+// g <= 8192 records add at most 2^13 * 2^14 < 2^32 in units of 2^18.  Zero
+// registers are counted apart, two hosts' 16-bit counts to a word (at most g
+// per host).  Registers of 15 and more add 2^14 >> 15 = 0 here and go to the
+// host's 64-bit overflow sum instead, through the tile's list of wide
+// records (wide, gathered by k_est_tile_wide after this pass), so that no
+// global load here waits behind the prefetched runs; a record past the
+// list's capacity is gathered at once.  Every record, padding included,
+// takes the same branch-free steps (a byte read, a nibble extract, one LDS
+// add); zero and wide registers take a branch that a wave skips unless one
+// of its lanes holds one.  Runs are prefetched two sub-blocks ahead.
+constexpr uint32_t kTileAccU = kTileSub + 1, kTileAccV = kTileSub / 2;
+inline size_t tile_gather_lds(uint32_t shift) { return ((size_t)1 << shift) / 2 + 8 * (size_t)(kTileAccU + kTileAccV) + 16; }
+constexpr uint64_t kTileWideTotal = 1ull << 24;  // wide-list entries over all tiles (8 bytes each)
 template <int PRE>
 __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* __restrict__ reg4,
                                                                  const uint8_t* __restrict__ reg, uint64_t mstride,
@@ -1526,12 +1551,18 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
                                                                  uint32_t cap, const uint32_t* __restrict__ recs,
                                                                  const uint32_t* __restrict__ fill,
                                                                  uint32_t* __restrict__ part, uint32_t B,
-                                                                 unsigned long long* __restrict__ ovf) {
+                                                                 unsigned long long* __restrict__ ovf,
+                                                                 uint2* __restrict__ wide, uint32_t wcap,
+                                                                 uint32_t* __restrict__ wcnt) {
   extern __shared__ uint32_t tile_w[];
-  // per-host sums in units of 2^18 and zero counts, double-buffered: one barrier per sub-block
-  __shared__ uint32_t accu2[2][kTileSub], accv2[2][kTileSub];
-  for (uint32_t q = threadIdx.x; q < 2 * kTileSub; q += kDeferBlock) (&accu2[0][0])[q] = 0, (&accv2[0][0])[q] = 0;
+  // per-host sums in units of 2^18 (host slot s at s + 1; 0 takes the
+  // padding) and zero counts, double-buffered (one barrier per sub-block)
+  uint32_t* accu2 = tile_w + (1u << shift) / 8;
+  uint32_t* accv2 = accu2 + 2 * kTileAccU;
+  uint32_t* wide_n = accv2 + 2 * kTileAccV;  // entries in this tile's wide list
+  for (uint32_t q = threadIdx.x; q < 2 * (kTileAccU + kTileAccV) + 1; q += kDeferBlock) accu2[q] = 0;
   const uint32_t t = blockIdx.x;
+  wide += (uint64_t)t * wcap;
   const uint64_t tbase = (uint64_t)t << shift;
   const uint64_t nbytes = ((tbase + (1ull << shift) < mstride ? tbase + (1ull << shift) : mstride) - tbase) / 2;
   const uint32_t* src = reinterpret_cast<const uint32_t*>(reg4 + tbase / 2);
@@ -1548,112 +1579,130 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
     const uint32_t f = sb < nsb ? fill[sb * nt + t] : 0u;
     fr[q] = f < cap ? f : cap;
   }
-  auto run_len = [&](uint32_t sb) -> uint32_t {
+  auto run_len = [&](uint32_t sb) -> uint32_t {  // four reads of lanes and a scalar select: no temporary VGPR
+    const int l = (int)(sb & 63);
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)fr[0], l), b = (uint32_t)__builtin_amdgcn_readlane((int)fr[1], l),
+                   c = (uint32_t)__builtin_amdgcn_readlane((int)fr[2], l), d = (uint32_t)__builtin_amdgcn_readlane((int)fr[3], l);
     const uint32_t q = sb >> 6;
-    const uint32_t v = q == 0 ? fr[0] : q == 1 ? fr[1] : q == 2 ? fr[2] : fr[3];
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(sb & 63));
+    return q == 0 ? a : q == 1 ? b : q == 2 ? c : d;
   };
   // the first PRE * kDeferBlock records of every run (all of it, for runs of
-  // the expected length) are loaded one sub-block ahead, as whole quads: quad
+  // the expected length) are loaded two sub-blocks ahead, as whole quads: quad
   // threadIdx.x + q * kDeferBlock of the run (runs hold whole quads).  One
   // 16-byte load per quad instead of four 4-byte loads: pass 2 -3 % at g =
   // 1024, -16 % at g = 2048.
   static_assert(PRE % 4 == 0, "the prefetch holds whole quads");
   constexpr int PQ = PRE / 4;
-  u32x4 nxt[PQ];
-  uint32_t n_nxt;
-  {
-    n_nxt = run_len(0);
+  // three buffers of prefetched quads, each in fixed registers: sub-block
+  // sbk is gathered from one while the next two sub-blocks' runs load into
+  // the others (a rotation by copies would wait for the loads just issued)
+  u32x4 ra[PQ], rb[PQ], rc[PQ];
+  // bounded buffer loads, without branches (so that a use waits only for
+  // its own loads): quads past a run's length, and the runs of sub-blocks
+  // past the last, read as padding (0)
+  auto load_run = [&](uint32_t sb, u32x4(&dst)[PQ]) __attribute__((always_inline)) {
+    const bool in = sb < nsb;
+    const uint32_t len = in ? run_len(sb) : 0u;
+    const uint32_t* r = recs + ((uint64_t)(in ? sb : 0u) * nt + t) * cap;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(r), (short)0, (int)(len * 4), (int)kBufferRsrcWord3);
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
-      const uint32_t j = 4 * (threadIdx.x + q * kDeferBlock);
-      nxt[q] = j < n_nxt ? *reinterpret_cast<const u32x4*>(recs + (uint64_t)t * cap + j) : u32x4{~0u, ~0u, ~0u, ~0u};
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(16 * (threadIdx.x + q * kDeferBlock)), 0, 0);
+      dst[q] = u32x4{v[0], v[1], v[2], v[3]};
     }
-  }
-  for (uint32_t sbk = 0; sbk < nsb; ++sbk) {
-    uint32_t* accu = accu2[sbk & 1];
-    uint32_t* accv = accv2[sbk & 1];
+  };
+  // gathers sub-block sbk from cur, then starts the load of sub-block sbk + 2 into nxt2
+  auto sub_block = [&](uint32_t sbk, u32x4(&cur)[PQ], u32x4(&nxt2)[PQ]) __attribute__((always_inline)) {
+    uint32_t* accu = accu2 + (sbk & 1) * kTileAccU;
+    uint32_t* accv = accv2 + (sbk & 1) * kTileAccV;
     unsigned long long* ovf_sb = ovf + (uint64_t)sbk * kTileSub;
-    // the record of a register below 15 at host slot q: 2^(14-r) (and a zero count)
-    auto gather = [&](uint32_t rec, uint32_t nib) {
-      const uint32_t q = rec & (kTileSub - 1);
-      atomicAdd(&accu[q], 1u << (14 - nib));
-      if (nib == 0) atomicAdd(&accv[q], 1u);
+    const uint32_t n = run_len(sbk);
+    // one record: the register's term 2^(14-r) added to its host (0 for
+    // r >= 15), given the byte that holds its nibble; returns the nibble
+    auto gather = [&](uint32_t rec, uint32_t byte) -> uint32_t {
+      const uint32_t nib = __builtin_amdgcn_ubfe(byte, rec >> 29, 4);
+      atomicAdd(&accu[tile_rec_acc(rec)], 0x4000u >> nib);
+      return nib;
     };
-    u32x4 cur[PQ];
-    const uint32_t n = n_nxt;
-#pragma unroll
-    for (int q = 0; q < PQ; ++q) cur[q] = nxt[q];
-    if (sbk + 1 < nsb) {
-      n_nxt = run_len(sbk + 1);
-      const uint32_t* nrun = recs + ((uint64_t)(sbk + 1) * nt + t) * cap;
-#pragma unroll
-      for (int q = 0; q < PQ; ++q) {
-        const uint32_t j = 4 * (threadIdx.x + q * kDeferBlock);
-        nxt[q] = j < n_nxt ? *reinterpret_cast<const u32x4*>(nrun + j) : u32x4{~0u, ~0u, ~0u, ~0u};
+    // zero count of a record's host (nib == 0), or its wide register (nib
+    // == 15) put on the wide list; padding is skipped
+    auto rare = [&](uint32_t rec, uint32_t nib) {
+      if (rec == kTilePad) return;
+      const uint32_t q = tile_rec_slot(rec);
+      if (nib == 0) {
+        atomicAdd(&accv[q >> 1], 1u << ((q & 1u) << 4));
+      } else if (nib == 15) {
+        const uint32_t at = atomicAdd(wide_n, 1u);
+        if (at < wcap)
+          wide[at] = make_uint2(sbk, rec);
+        else
+          atomicAdd(ovf_sb + q, sum_term(reg[tbase + tile_rec_off(rec)]));
       }
-    }
+    };
+    load_run(sbk + 2, nxt2);
     if (sbk == 0) __syncthreads();  // the tile and the zeroed accumulators
     const uint32_t* run = recs + ((uint64_t)sbk * nt + t) * cap;
-    // Registers of 15 and more (nibble 15) are read from the byte array after
-    // the loop, so that no load in it waits behind the prefetch.  ~0u pads a
-    // run to whole quads (and marks prefetch slots past its end).
-    uint32_t wide = 0;
     // a prefetched quad slot that holds only padding in every lane of the
     // wave (runs average 8 records per thread of PRE) is skipped as a whole
     const uint32_t wave0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
       if (4 * (wave0 + (uint32_t)q * kDeferBlock) >= n) break;
-      uint32_t nib[4];
+      const uint32_t r4[4] = {cur[q][0], cur[q][1], cur[q][2], cur[q][3]};
+      uint32_t by[4], nib[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t off = cur[q][e] != ~0u ? cur[q][e] >> kTileSlotBits : 0u;  // padding reads offset 0
-        const uint32_t v = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
-        nib[e] = cur[q][e] != ~0u ? v : 16u;
-      }
+      for (int e = 0; e < 4; ++e) by[e] = tl[r4[e] & 0x1FFFFu];  // the four reads issue before any add
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (nib[e] < 15u)
-          gather(cur[q][e], nib[e]);
-        else if (nib[e] == 15u)
-          wide |= 1u << (4 * q + e);
+      for (int e = 0; e < 4; ++e) nib[e] = gather(r4[e], by[e]);
+      bool any = false;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) any |= nib[e] == 0u || nib[e] == 15u;
+      if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rare(r4[e], nib[e]);
       }
     }
-    bool wide_long = false;
     for (uint32_t j = threadIdx.x + PRE * kDeferBlock; j < n; j += kDeferBlock) {  // runs longer than expected
       const uint32_t rec = run[j];
-      if (rec == ~0u) continue;
-      const uint32_t off = rec >> kTileSlotBits;
-      const uint32_t nib = (tl[off >> 1] >> ((off & 1u) << 2)) & 15u;
-      if (nib < 15u)
-        gather(rec, nib);
-      else
-        wide_long = true;
-    }
-    if (wide) {
-#pragma unroll
-      for (int u = 0; u < PRE; ++u)
-        if ((wide >> u) & 1u) {
-          const uint32_t rec = cur[u >> 2][u & 3];
-          atomicAdd(ovf_sb + (rec & (kTileSub - 1)), sum_term(reg[tbase + (rec >> kTileSlotBits)]));
-        }
-    }
-    if (wide_long) {
-      for (uint32_t j = threadIdx.x + PRE * kDeferBlock; j < n; j += kDeferBlock) {
-        const uint32_t rec = run[j];
-        if (rec == ~0u) continue;
-        const uint32_t off = rec >> kTileSlotBits;
-        if (((tl[off >> 1] >> ((off & 1u) << 2)) & 15u) == 15u)
-          atomicAdd(ovf_sb + (rec & (kTileSub - 1)), sum_term(reg[tbase + off]));
-      }
+      rare(rec, gather(rec, tl[rec & 0x1FFFFu]));
     }
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < kTileSub; q += kDeferBlock) {
-      const uint32_t h = sbk * kTileSub + q;
-      part[(uint64_t)t * B + h] = pack_part32(accu[q], accv[q], ovf + h);
-      accu[q] = 0, accv[q] = 0;  // gathered into again two sub-blocks on, after the next barrier
+    {  // thread w packs hosts 2w and 2w + 1 (one zero-count word) and clears
+       // them for the sub-block two on, after the next barrier (the spare
+       // slot is never read)
+      static_assert(kDeferBlock == kTileSub / 2, "one zero-count word per thread");
+      const uint32_t w = threadIdx.x, v = accv[w], h = sbk * kTileSub + 2 * w;
+      uint2 pr;
+      pr.x = pack_part32(accu[2 * w + 1], v & 0xFFFFu, ovf + h);
+      pr.y = pack_part32(accu[2 * w + 2], v >> 16, ovf + h + 1);
+      *reinterpret_cast<uint2*>(part + (uint64_t)t * B + h) = pr;
+      accu[2 * w + 1] = 0, accu[2 * w + 2] = 0, accv[w] = 0;
     }
+  };
+  load_run(0, ra);
+  load_run(1, rb);
+  for (uint32_t sbk = 0; sbk < nsb; sbk += 3) {
+    sub_block(sbk, ra, rc);
+    if (sbk + 1 < nsb) sub_block(sbk + 1, rb, ra);
+    if (sbk + 2 < nsb) sub_block(sbk + 2, rc, rb);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) wcnt[t] = *wide_n < wcap ? *wide_n : wcap;
+}
+
+// After pass 2: the registers of 15 and more that pass 2 listed, read from
+// the byte array and added to their hosts' overflow sums.  Grid (x, nt).
+__global__ __launch_bounds__(256) void k_est_tile_wide(const uint2* __restrict__ wide, uint32_t wcap,
+                                                       const uint32_t* __restrict__ wcnt,
+                                                       const uint8_t* __restrict__ reg, uint32_t shift,
+                                                       unsigned long long* __restrict__ ovf) {
+  const uint32_t t = blockIdx.y, n = wcnt[t];
+  const uint2* w = wide + (uint64_t)t * wcap;
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const uint2 e = w[i];
+    atomicAdd(ovf + (uint64_t)e.x * kTileSub + tile_rec_slot(e.y),
+              sum_term(reg[((uint64_t)t << shift) + tile_rec_off(e.y)]));
   }
 }
 
@@ -1865,15 +1914,19 @@ int alloc_tiled(vbdr_sketch* sk) {
   const uint64_t nsb = sk->tl_B / kTileSub;
   const uint64_t rec_b = nsb * sk->tl_nt * sk->tl_cap * 4, fill_b = nsb * sk->tl_nt * 4;
   const uint64_t part_b = (uint64_t)sk->tl_nt * sk->tl_B * 4, ovf_b = (uint64_t)sk->tl_B * 8;
+  // wide lists: [nt][tl_wcap] entries, then nt counts
+  sk->tl_wcap = (uint32_t)(kTileWideTotal / sk->tl_nt);
+  const uint64_t wide_b = (uint64_t)sk->tl_nt * sk->tl_wcap * 8 + (uint64_t)sk->tl_nt * 4;
   if (vbdr_malloc(&sk->tl_rec, rec_b) != hipSuccess || vbdr_malloc(&sk->tl_fill, fill_b) != hipSuccess ||
-      vbdr_malloc(&sk->tl_part, part_b) != hipSuccess || vbdr_malloc(&sk->tl_ovf, ovf_b) != hipSuccess) {
+      vbdr_malloc(&sk->tl_part, part_b) != hipSuccess || vbdr_malloc(&sk->tl_ovf, ovf_b) != hipSuccess ||
+      vbdr_malloc(&sk->tl_wide, wide_b) != hipSuccess) {
     (void)hipGetLastError();
-    for (void* q : {(void*)sk->tl_rec, (void*)sk->tl_fill, (void*)sk->tl_part, (void*)sk->tl_ovf})
+    for (void* q : {(void*)sk->tl_rec, (void*)sk->tl_fill, (void*)sk->tl_part, (void*)sk->tl_ovf, (void*)sk->tl_wide})
       if (q) (void)hipFree(q);
-    sk->tl_rec = nullptr, sk->tl_fill = nullptr, sk->tl_part = nullptr, sk->tl_ovf = nullptr;
+    sk->tl_rec = nullptr, sk->tl_fill = nullptr, sk->tl_part = nullptr, sk->tl_ovf = nullptr, sk->tl_wide = nullptr;
     return vbdr_fail(VBDR_ENOMEM, "allocation of the tiled-estimate workspace failed");
   }
-  sk->bytes += rec_b + fill_b + part_b + ovf_b;
+  sk->bytes += rec_b + fill_b + part_b + ovf_b + wide_b;
   return VBDR_OK;
 }
 
@@ -1997,7 +2050,7 @@ int create_sketch(uint64_t m, uint32_t g, uint32_t k, uint64_t hash_seed, int la
       const double Eb = (double)(tile_chunk_hosts(lg) << lg) * (double)(1ull << sh) / (double)m;
       const uint32_t capb = ((uint32_t)(Eb + 4.0 * std::sqrt(Eb) + 4.0) + 3u) & ~3u;
       const size_t lds1 = tile_bin_lds(nt, capb, g);
-      const size_t lds2 = ((size_t)1 << sh) / 2 + 2 * kTileSub * 8;  // the tile and two accumulator buffers
+      const size_t lds2 = tile_gather_lds(sh);  // the tile and two accumulator buffers
       if (sh <= kTileMaxShift && B >= kTileSub && lds1 + 1024 <= (size_t)lds_max && lds2 <= (size_t)lds_max) {
         const double E = (double)kTileSub * g * (double)(1ull << sh) / (double)m;
         sk->tl_ok = true;
@@ -2121,6 +2174,7 @@ void vbdr_sketch_destroy(vbdr_sketch* sk) {
   if (sk->tl_fill) (void)hipFree(sk->tl_fill);
   if (sk->tl_part) (void)hipFree(sk->tl_part);
   if (sk->tl_ovf) (void)hipFree(sk->tl_ovf);
+  if (sk->tl_wide) (void)hipFree(sk->tl_wide);
   if (sk->psum) (void)hipFree(sk->psum);
   if (prev >= 0 && prev != sk->device) (void)hipSetDevice(prev);
   delete sk;
@@ -2354,10 +2408,15 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
       VBDR_LAUNCHED("k_est_tile_bin");
       // prefetch depth: the whole run when runs are near their expected length
       const auto gather = cap <= 12u * kDeferBlock ? k_est_tile_gather<12> : k_est_tile_gather<20>;
-      hipLaunchKernelGGL(gather, dim3(nt), dim3(kDeferBlock), ((size_t)1 << sk->tl_shift) / 2, st, sk->reg4,
+      hipLaunchKernelGGL(gather, dim3(nt), dim3(kDeferBlock), tile_gather_lds(sk->tl_shift), st, sk->reg4,
                          sk->reg, sk->mstride, sk->tl_shift, nt, nsb, cap, sk->tl_rec, sk->tl_fill, sk->tl_part, B,
-                         sk->tl_ovf);
+                         sk->tl_ovf, sk->tl_wide, sk->tl_wcap,
+                         reinterpret_cast<uint32_t*>(sk->tl_wide + (uint64_t)nt * sk->tl_wcap));
       VBDR_LAUNCHED("k_est_tile_gather");
+      hipLaunchKernelGGL(k_est_tile_wide, dim3(8, nt), dim3(256), 0, st, sk->tl_wide, sk->tl_wcap,
+                         reinterpret_cast<const uint32_t*>(sk->tl_wide + (uint64_t)nt * sk->tl_wcap), sk->reg,
+                         sk->tl_shift, sk->tl_ovf);
+      VBDR_LAUNCHED("k_est_tile_wide");
       hipLaunchKernelGGL(k_est_tile_final, dim3((nh + 255) / 256), dim3(256), 0, st, nh, g, (uint32_t)sk->m, nt, B,
                          sk->hist, sk->tl_part, sk->tl_ovf, out_dev + c);
       VBDR_LAUNCHED("k_est_tile_final");
