@@ -123,6 +123,50 @@ def cpu_baseline(w, layout, slice0, hosts_sample, n_active, Lc=0):
                         "estimate": round(t_est, 3)}}
 
 
+def _oracle_step_worker(job):
+    """One process of the all-cores baseline: the single-threaded oracle on
+    the same bounded sample as cpu_baseline; returns its scaled step time."""
+    import numpy as np
+    from oracle import oracle
+    w_m, w_g, w_k, seed, code, Lc, pairs, hosts, scale_scan, scale_est = job
+    t0 = time.perf_counter()
+    osk = oracle.Sketch(w_m, w_g, w_k, seed, code, Lc=Lc)
+    t1 = time.perf_counter()
+    osk.scan(pairs)
+    t2 = time.perf_counter()
+    osk.advance()
+    t3 = time.perf_counter()
+    osk.estimate(hosts)
+    t4 = time.perf_counter()
+    del osk
+    return (t2 - t1) * scale_scan + (t3 - t2) + (t4 - t3) * scale_est, t4 - t0
+
+
+def cpu_baseline_all_cores(w, layout, slice0, hosts_sample, n_active, Lc=0, max_workers=16):
+    """The same oracle sample run by one single-threaded process per host core
+    at once (at most max_workers, the host share of one GPU): the aggregate
+    rate of the CPU doing independent steps in parallel.  The oracle itself
+    stays single-threaded."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    from oracle import oracle
+    code = {"fast": oracle.GFAST, "small": oracle.GSMALL, "packed": oracle.GPACKED}[layout]
+    n = max(1, min(max_workers, os.cpu_count() or 1))
+    S = min(len(slice0), 1 << 22)
+    job = (w.m, w.g, w.k, w.seed, code, Lc, slice0[:S].copy(), hosts_sample, w.pairs_per_slice / S,
+           n_active / len(hosts_sample))
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(n, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_oracle_step_worker, [job] * n))
+    wall = time.perf_counter() - t0
+    step = max(r[0] for r in res)
+    return {"value": n * w.pairs_per_slice / step, "unit": "pairs/s", "cores": n, "kind": "oracle",
+            "sample": f"{n} single-threaded oracle processes at once, each on the cpu_baseline sample (scan of "
+                      f"{S} pairs, one advance of {w.m} BDRs, {len(hosts_sample)} host estimates), scaled to a "
+                      f"step; value = processes x pairs per step / the slowest process's scaled step",
+            "seconds_wall": round(wall, 2)}
+
+
 def scan_roofline(w, layout, ms):
     b = algorithmic_bytes("scan", w, layout, 0, 0)
     rate = b / (ms * 1e-3) / 1e9
@@ -280,6 +324,8 @@ def main():
                     help="recorders per BDR of the packed layout (LBP1 values above it are recorded at it)")
     ap.add_argument("--workload", default="line_rate", choices=["line_rate", "tiny", "batched", "stress"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the learned-vs-plain accuracy evaluation (profiling runs)")
     ap.add_argument("--overlap", action="store_true",
                     help="scan each slice on a second stream while the previous window is estimated")
     ap.add_argument("--first-slice", type=int, default=None,
@@ -516,7 +562,7 @@ def main():
         res["scan_with_apply_roofline"] = scan_roofline(w, args.layout, avg["scan"] + apply_ms)
     if res_young:
         res["young_pool"] = res_young
-    acc = learned_accuracy()
+    acc = None if args.no_accuracy else learned_accuracy()
     if acc:
         res["accuracy"] = acc
     if args.calibrate_copy:
@@ -533,6 +579,8 @@ def main():
         sample = rng.choice(act_last, size=min(2048, len(act_last)), replace=False)
         log("timing the CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(w, args.layout, slice0, sample, int(units), Lc)
+        log("timing the CPU oracle on every host core")
+        res["cpu_baseline_all_cores"] = cpu_baseline_all_cores(w, args.layout, slice0, sample, int(units), Lc)
     print(json.dumps(res), flush=True)
 
 
