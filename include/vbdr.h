@@ -312,6 +312,9 @@ int vbdr_export_state(vbdr_sketch *sk, uint8_t *dr_host, uint32_t *bs_host, uint
  * counter t into a sketch with the same parameters, for checkpoint/resume.
  * Packed layout: DR values are capped at 2^z - 1 (every value >= k is
  * inactive alike) and recorders above Lc are ignored.  Synchronous.
+ * VBDR_EINVAL when a register exceeds the recorders, when hist_host does
+ * not sum to m or is not the histogram of reg_host, or when bs_host has
+ * bits a small-layout sketch cannot hold.
  */
 int vbdr_import_state(vbdr_sketch *sk, const uint8_t *dr_host, const uint32_t *bs_host, const uint8_t *reg_host,
                       const uint64_t *hist_host, uint64_t t, void *stream);

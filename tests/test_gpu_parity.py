@@ -318,18 +318,22 @@ def test_tiled_estimate_edge_g(V, O, g, m):
     assert torch.equal(tiled, direct) and torch.equal(tiled2, direct) and torch.equal(part, direct)
 
 
-def test_tiled_estimate_high_registers(V, O):
+@pytest.mark.parametrize("g,lo", [(256, 0), (8192, 1), (1024, 2)])
+def test_tiled_estimate_high_registers(V, O, g, lo):
     """Registers of 15 and more do not fit the tiled estimate's nibble tile:
-    its gathers read them from the byte array.  Registers 0..L are planted
+    they are listed and read from the byte array.  Registers lo..L are planted
     through import (a third of them 15 or more); each sampled host's register
     histogram must be the one the oracle's getPhyIdx (Alg. 3) gives over the
     planted registers, its raw E_s the oracle's HyperLogLog of that histogram,
-    and every estimate path must give the same bits."""
-    m, g, k, seed = 1 << 22, 256, 3, 29
-    rng = np.random.default_rng(29)
+    and every estimate path must give the same bits.  Without zero registers
+    (lo >= 1) the tiled estimate keeps 16-bit per-tile sums; at g = 8192
+    (about 32 records of a host per tile, terms of 2^13 and 2^12 units) every
+    such sum exceeds 16 bits and goes to the host's overflow sum."""
+    m, k, seed = 1 << 22, 3, 29
+    rng = np.random.default_rng(29 + g)
     a = V.Sketch(m, g, k, seed, "small")
     st = a.state()
-    reg = rng.integers(0, 15, m).astype(np.uint8)
+    reg = rng.integers(lo, 15, m).astype(np.uint8)
     hi = rng.random(m) < 0.33
     reg[hi] = rng.integers(15, a.L + 1, int(hi.sum())).astype(np.uint8)
     st["reg"], st["hist"] = reg, np.bincount(reg, minlength=len(st["hist"])).astype(np.uint64)
@@ -340,7 +344,7 @@ def test_tiled_estimate_high_registers(V, O):
     out, raw, hh = b.estimate_ex(hd)
     raw, hh = raw.cpu().numpy(), hh.cpu().numpy()
     osk = O.Sketch(m, g, k, seed, LAYOUT_CODE["small"])
-    for j in range(0, len(hosts), 97):
+    for j in range(0, len(hosts), 97 if g <= 1024 else 499):
         idx = [osk.phy_idx(int(hosts[j]), i) for i in range(g)]
         want = np.bincount(reg[idx], minlength=hh.shape[1])
         assert np.array_equal(hh[j], want), j
@@ -552,3 +556,6 @@ def test_bad_arguments_on_device(V):
     with pytest.raises(V.VbdrError):
         sk.load_state({"dr": np.zeros((5000, sk.L), np.uint8), "reg": np.zeros(5000, np.uint8),
                        "hist": np.zeros(33, np.uint64), "t": 0})  # histogram does not sum to m
+    with pytest.raises(V.VbdrError):
+        sk.load_state({"dr": np.zeros((5000, sk.L), np.uint8), "reg": np.zeros(5000, np.uint8),
+                       "hist": np.array([4999, 1] + [0] * 31, np.uint64), "t": 0})  # not the registers' histogram
