@@ -1331,7 +1331,7 @@ __host__ __device__ __forceinline__ uint32_t tile_chunk_hosts(uint32_t lg) {
 
 // LDS bytes of pass 1 (layout at the kernel).
 inline size_t tile_bin_lds(uint32_t nt, uint32_t capb, uint32_t g) {
-  return ((size_t)(nt + 1) * (((capb + 4) & ~3u) | 4u) + 3 * (size_t)nt + 1 + 64 + g) * 4;
+  return ((size_t)(nt + 1) * (((capb + 4) & ~3u) | 4u) + (size_t)nt + 1 + 64 + g) * 4;
 }
 
 __device__ __forceinline__ unsigned long long sum_term(uint32_t r) {
@@ -1369,16 +1369,14 @@ __global__ void k_est_tile_clear(uint32_t* __restrict__ a, uint64_t na, uint32_t
 // Pass 1.  A chunk is hpc = min(kTileChunk / g, 64) consecutive hosts of one
 // sub-block.  Each (host, i) is hashed once and appended to the LDS bucket of
 // its tile (capb entries; an entry beyond it is gathered directly into the
-// host's overflow sum).  Wave 0 then reserves every bucket's place in the run
-// of (sub-block, tile), one atomic per bucket, and loads the next chunk's host
-// keys; the other waves copy the buckets out.  Wave 0 stores nothing, so its
-// waits for atomics and loads never wait for stores (the vector memory counter
-// is shared by both).  All chunks of a sub-block run on one XCD (workgroup b on
-// XCD b % 8), so that the partly written lines at the ends of a run's segments
-// merge in that XCD's L2.  Pairs past the chunk's end count into a spare
-// tile nt, and entries beyond a bucket's capacity go to a spare last slot, so
-// that the append is branch-free.  LDS: cnt[nt + 1], cntc[nt], base[nt],
-// kmix[64], bucket[nt + 1][capb + 1], s1[g].
+// host's overflow sum).  Then each wave reserves the places of its own
+// buckets in the runs of (sub-block, tile), one atomic per bucket, and copies
+// them out (wave 0 first computes the next chunk's host keys).  All chunks of
+// a sub-block run on one XCD (workgroup b on XCD b % 8), so that the partly
+// written lines at the ends of a run's segments merge in that XCD's L2.
+// Pairs past the chunk's end count into a spare tile nt, and entries beyond
+// a bucket's capacity go to a spare last slot, so that the append is
+// branch-free.  LDS: bucket[nt + 1][capb + 1], cnt[nt + 1], kmix[64], s1[g].
 // POW2: m = 2^(32 - mshift), so H(x, m, A) is the hash shifted right (the
 // multiply-shift map of a power of two) instead of a high multiply.
 template <bool POW2>
@@ -1388,15 +1386,12 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
     uint32_t* __restrict__ recs, uint32_t* __restrict__ fill, const uint8_t* __restrict__ reg,
     unsigned long long* __restrict__ ovf) {
   extern __shared__ uint32_t lds[];
-  constexpr uint32_t kCopyWaves = kTileBinBlock / 64 - 1;
   const uint32_t hpc = tile_chunk_hosts(lg);  // divides kTileSub
   // room for the spare slot; rows 16-byte aligned, 4 mod 8 words apart so that rows start on different banks
   const uint32_t bstride = ((capb + 4) & ~3u) | 4u;
   uint32_t* bucket = lds;
   uint32_t* cnt = bucket + (nt + 1) * bstride;
-  uint32_t* cntc = cnt + nt + 1;
-  uint32_t* base = cntc + nt;
-  uint32_t* kmix = base + nt;
+  uint32_t* kmix = cnt + nt + 1;
   uint32_t* s1l = kmix + 64;
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t tmask = (1u << shift) - 1;
@@ -1484,34 +1479,24 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
           atomicAdd(ovf_sb + slot0 + (((uint32_t)u * kTileBinBlock + tx) >> lg), sum_term(reg[pv[u]]));
     }
     __syncthreads();
-    if (wave == 0) {  // nt <= 256: four buckets per lane, reservations issued together
-      uint32_t cq[4], bq[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t t = lane + 64u * q;
-        cq[q] = 0;
-        bq[q] = 0;
-        if (t < nt) {
-          cq[q] = cnt[t] < capb ? cnt[t] : capb;
-          cnt[t] = 0;
-          if (cq[q]) bq[q] = atomicAdd(&fill[sb * nt + t], (cq[q] + 3u) & ~3u);  // whole quads
-        }
+    {  // every wave reserves the run places of its own bpw buckets (lane j:
+       // bucket t0 + j, one atomic) and copies them out, 16 lanes per bucket
+       // and four records (16 bytes) per lane, the tail quad padded; no
+       // barrier between reservation and copy, so one wave's atomics wait
+       // while others copy
+      const uint32_t bpw = (nt + 15) >> 4, t0 = wave * bpw;  // nt <= 256
+      uint32_t c_l = 0, b_l = 0;
+      if (lane < bpw && t0 + lane < nt) {
+        const uint32_t t = t0 + lane, c = cnt[t];
+        c_l = c < capb ? c : capb;
+        cnt[t] = 0;
+        if (c_l) b_l = atomicAdd(&fill[sb * nt + t], (c_l + 3u) & ~3u);  // whole quads
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t t = lane + 64u * q;
-        if (t < nt) {
-          cntc[t] = cq[q];
-          base[t] = bq[q];
-        }
-      }
-      kmix[lane] = host_of(c0n) ? mm3_key(hnext) : 0u;
-    }
-    __syncthreads();
-    if (wave != 0) {  // 16 lanes per bucket, four records (16 bytes) per lane; the tail quad padded
+      if (wave == 0) kmix[lane] = host_of(c0n) ? mm3_key(hnext) : 0u;  // before this wave's stores
       const uint32_t ql = lane & 15;
-      for (uint32_t t = 4 * (wave - 1) + (lane >> 4); t < nt; t += 4 * kCopyWaves) {
-        const uint32_t c = cntc[t], b0 = base[t];
+      for (uint32_t j0 = 0; j0 < bpw; j0 += 4) {
+        const uint32_t j = j0 + (lane >> 4), t = t0 + j;
+        const uint32_t c = (uint32_t)__shfl((int)c_l, (int)j), b0 = (uint32_t)__shfl((int)b_l, (int)j);  // 0 past the wave's buckets
         uint32_t* run = recs + ((uint64_t)sb * nt + t) * cap;
         for (uint32_t i = 4 * ql; i < c; i += 64) {
           uint4 v = *reinterpret_cast<const uint4*>(bucket + t * bstride + i);
@@ -1522,9 +1507,9 @@ __global__ __launch_bounds__(kTileBinBlock) __attribute__((amdgpu_waves_per_eu(4
             *reinterpret_cast<uint4*>(run + b0 + i) = v;
           } else {  // run full: gather directly
             const uint32_t r4[4] = {v.x, v.y, v.z, v.w};
-            for (int j = 0; j < 4; ++j)
-              if (r4[j] != kTilePad)
-                atomicAdd(ovf_sb + tile_rec_slot(r4[j]), sum_term(reg[((uint64_t)t << shift) + tile_rec_off(r4[j])]));
+            for (int e = 0; e < 4; ++e)
+              if (r4[e] != kTilePad)
+                atomicAdd(ovf_sb + tile_rec_slot(r4[e]), sum_term(reg[((uint64_t)t << shift) + tile_rec_off(r4[e])]));
           }
         }
       }
