@@ -57,17 +57,19 @@ def algorithmic_bytes(kind, w, layout, L, n_hosts, dr_bits=8):
     raise ValueError(kind)
 
 
-def tiled_design_bytes(w, n_hosts):
+def tiled_design_bytes(w, n_hosts, narrow=False):
     """HBM bytes the LDS-tiled estimate moves by construction: each (host, i)
     record written and read once (8 B), each (tile, host) partial sum written
-    and read once (8 B), host id and estimate (8 B).  Tiles: at most 256, of
-    2^s registers with s >= 12 the smallest that covers the padded pool."""
+    and read once (8 B, or 4 B in the 16-bit form the estimate takes when
+    registers 0..2 are under 1/64 of the pool), host id and estimate (8 B).
+    Tiles: at most 256, of 2^s registers with s >= 12 the smallest that
+    covers the padded pool."""
     mstride = (w.m + 4095) // 4096 * 4096
     s = 12
     while (1 << s) * 256 < mstride:
         s += 1
     nt = (mstride + (1 << s) - 1) >> s
-    return n_hosts * (8 * w.g + 8 * nt + 8)
+    return n_hosts * (8 * w.g + (4 if narrow else 8) * nt + 8)
 
 
 # gfx950 L2: 8 XCDs x 16 channels, one tag lookup per channel per clock at 2.4 GHz.
@@ -481,6 +483,10 @@ def main():
     torch.cuda.synchronize()
     elapsed, kms, timed_active = measure(S0)
     log(f"timed {K} steps from slice {S0} in {elapsed:.3f}s")
+    # the width of the tiled estimate's per-tile sums in the last timed step
+    pool_hist = sk.registers()[1]
+    low_regs = int(pool_hist[0] + pool_hist[1] + pool_hist[2])
+    narrow_sums = bool(64 * low_regs < w.m)
 
     # The deferred scan's updates are applied by the next advance, from LDS:
     # that share of the advance belongs to the scan stage.  Measured on the
@@ -517,7 +523,7 @@ def main():
     adv = "k_advance_packed" if args.layout == "packed" else "k_advance_defer" if info.scan_deferred else "k_advance"
     kernels = {"scan": "k_scan_defer" if info.scan_deferred else "k_scan",
                "advance": adv + " + k_hist_reset",
-               "estimate": ("k_est_tile_clear + k_est_tile_bin + k_est_tile_gather + k_est_tile_final"
+               "estimate": ("k_est_tile_clear + k_est_tile_bin + k_est_tile_gather + k_est_tile_wide + k_est_tile_final"
                             if info.est_tiled else
                             "k_estimate_part + k_estimate_final" if info.est_parts > 1 else "k_estimate")}
     traffic = traffic_from_counters(f"{dom}:{args.layout}:{w.name}", units)
@@ -526,10 +532,12 @@ def main():
                 "algorithmic_bytes_per_launch": alg}
     if dom == "estimate" and info.est_tiled:
         # the tiled estimate trades L2 gathers for streamed records and per-tile partial sums
-        b = tiled_design_bytes(w, units)
+        b = tiled_design_bytes(w, units, narrow_sums)
         rate = b / (avg["estimate"] * 1e-3) / 1e9
         roofline["design_bytes"] = {"per_launch": b, "achieved": round(rate, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                    "frac": round(rate / HBM_PEAK_GBS, 4)}
+                                    "frac": round(rate / HBM_PEAK_GBS, 4),
+                                    "partial_sums": "16-bit" if narrow_sums else "32-bit",
+                                    "pool_registers_0_to_2": round(low_regs / w.m, 5)}
     elif dom == "estimate":
         # the estimate moves few bytes; its limit is the L2 request rate of g random gathers per host
         gathers = units * w.g / (avg["estimate"] * 1e-3)

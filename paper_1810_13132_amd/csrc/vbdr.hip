@@ -1347,13 +1347,20 @@ __device__ __forceinline__ uint32_t pack_part32(uint32_t Us, uint32_t V, unsigne
   return 0u;
 }
 
-// The same sum in 16 bits when the pool holds no zero register (V = 0):
-// exact while Us < 0xFFFF, otherwise in the overflow sum and the entry 0.
-// Half the partial-sum traffic of the 32-bit form.
-__device__ __forceinline__ uint32_t pack_part16(uint32_t Us, unsigned long long* ovf_h) {
-  if (Us < 0xFFFFu) return Us;
-  atomicAdd(ovf_h, (unsigned long long)Us << 18);
+// The same sum in 16 bits: Us itself when V < 4 and the part of Us that
+// the nonzero registers add (Us - V 2^14, a zero register adding 2^14) is
+// below 2^14 - 1, so that Us >> 14 = V; otherwise the entry is 0 and the
+// whole sum goes to the overflow sum.  Used when registers 0..2 are rare in
+// the pool (tile_part_narrow), where it halves the partial-sum traffic.
+__device__ __forceinline__ uint32_t pack_part16(uint32_t Us, uint32_t V, unsigned long long* ovf_h) {
+  if (V < 4u && Us - (V << 14) < 0x3FFFu) return Us;
+  atomicAdd(ovf_h, ((unsigned long long)Us << 18) + ((unsigned long long)V << 48));
   return 0u;
+}
+// 16-bit per-tile sums when fewer than m/64 registers of the pool are 0, 1
+// or 2 (few escapes); pass 2 and pass 3 decide alike from the histogram.
+__device__ __forceinline__ bool tile_part_narrow(const unsigned long long* hist, uint64_t m) {
+  return 64ull * (hist[0] + hist[1] + hist[2]) < m;
 }
 
 // Zeroes a block's run lengths and overflow sums (as 32-bit words).
@@ -1548,9 +1555,10 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
                                                                  unsigned long long* __restrict__ ovf,
                                                                  uint2* __restrict__ wide, uint32_t wcap,
                                                                  uint32_t* __restrict__ wcnt,
-                                                                 const unsigned long long* __restrict__ hist) {
+                                                                 const unsigned long long* __restrict__ hist,
+                                                                 uint64_t m) {
   extern __shared__ uint32_t tile_w[];
-  const bool narrow = hist[0] == 0;  // no zero register in the pool: 16-bit sums (tile_part_narrow)
+  const bool narrow = tile_part_narrow(hist, m);  // 16-bit sums
   // per-host sums in units of 2^18 (host slot s at s + 1; 0 takes the
   // padding) and zero counts, double-buffered (one barrier per sub-block)
   uint32_t* accu2 = tile_w + (1u << shift) / 8;
@@ -1670,7 +1678,8 @@ __global__ __launch_bounds__(kDeferBlock) void k_est_tile_gather(const uint8_t* 
       static_assert(kDeferBlock == kTileSub / 2, "one zero-count word per thread");
       const uint32_t w = threadIdx.x, v = accv[w], h = sbk * kTileSub + 2 * w;
       if (narrow) {
-        const uint32_t lo = pack_part16(accu[2 * w + 1], ovf + h), hi = pack_part16(accu[2 * w + 2], ovf + h + 1);
+        const uint32_t lo = pack_part16(accu[2 * w + 1], v & 0xFFFFu, ovf + h),
+                       hi = pack_part16(accu[2 * w + 2], v >> 16, ovf + h + 1);
         *reinterpret_cast<uint32_t*>(reinterpret_cast<uint16_t*>(part) + (uint64_t)t * B + h) = lo | hi << 16;
       } else {
         uint2 pr;
@@ -1724,16 +1733,23 @@ __global__ __launch_bounds__(256) void k_est_tile_final(uint32_t nh, uint32_t g,
   V = o >> 48;
   unsigned long long Us = 0;  // in units of 2^18
   uint32_t t = 0;
-  if (hist[0] == 0) {  // 16-bit sums (pass 2 chose them from the same histogram)
+  if (tile_part_narrow(hist, m)) {  // 16-bit sums: the entry is Us, and V = Us >> 14 (pack_part16)
     const uint16_t* p16 = reinterpret_cast<const uint16_t*>(part);
     for (; t + 8 <= nt; t += 8) {
       uint32_t v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = p16[(uint64_t)(t + u) * B + h];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) Us += v[u];
+      for (int u = 0; u < 8; ++u) {
+        Us += v[u];
+        V += v[u] >> 14;
+      }
     }
-    for (; t < nt; ++t) Us += p16[(uint64_t)t * B + h];
+    for (; t < nt; ++t) {
+      const uint32_t v = p16[(uint64_t)t * B + h];
+      Us += v;
+      V += v >> 14;
+    }
   } else {
     for (; t + 8 <= nt; t += 8) {
       uint32_t v[8];
@@ -2430,7 +2446,7 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
       hipLaunchKernelGGL(gather, dim3(nt), dim3(kDeferBlock), tile_gather_lds(sk->tl_shift), st, sk->reg4,
                          sk->reg, sk->mstride, sk->tl_shift, nt, nsb, cap, sk->tl_rec, sk->tl_fill, sk->tl_part, B,
                          sk->tl_ovf, sk->tl_wide, sk->tl_wcap,
-                         reinterpret_cast<uint32_t*>(sk->tl_wide + (uint64_t)nt * sk->tl_wcap), sk->hist);
+                         reinterpret_cast<uint32_t*>(sk->tl_wide + (uint64_t)nt * sk->tl_wcap), sk->hist, sk->m);
       VBDR_LAUNCHED("k_est_tile_gather");
       hipLaunchKernelGGL(k_est_tile_wide, dim3(8, nt), dim3(256), 0, st, sk->tl_wide, sk->tl_wcap,
                          reinterpret_cast<const uint32_t*>(sk->tl_wide + (uint64_t)nt * sk->tl_wcap), sk->reg,

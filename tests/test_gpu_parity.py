@@ -318,22 +318,26 @@ def test_tiled_estimate_edge_g(V, O, g, m):
     assert torch.equal(tiled, direct) and torch.equal(tiled2, direct) and torch.equal(part, direct)
 
 
-@pytest.mark.parametrize("g,lo", [(256, 0), (8192, 1), (1024, 2)])
+@pytest.mark.parametrize("g,lo", [(256, 0), (8192, 3), (1024, 3)])
 def test_tiled_estimate_high_registers(V, O, g, lo):
     """Registers of 15 and more do not fit the tiled estimate's nibble tile:
     they are listed and read from the byte array.  Registers lo..L are planted
     through import (a third of them 15 or more); each sampled host's register
     histogram must be the one the oracle's getPhyIdx (Alg. 3) gives over the
     planted registers, its raw E_s the oracle's HyperLogLog of that histogram,
-    and every estimate path must give the same bits.  Without zero registers
-    (lo >= 1) the tiled estimate keeps 16-bit per-tile sums; at g = 8192
-    (about 32 records of a host per tile, terms of 2^13 and 2^12 units) every
-    such sum exceeds 16 bits and goes to the host's overflow sum."""
+    and every estimate path must give the same bits.  With lo = 3 and 0.5 % of
+    the registers set to 0, 1 or 2 the tiled estimate keeps 16-bit per-tile
+    sums (registers 0..2 below 1/64 of the pool) carrying zero counts; at g =
+    8192 (about 32 records of a host per tile) most of them exceed 16 bits and
+    go to the host's overflow sum."""
     m, k, seed = 1 << 22, 3, 29
     rng = np.random.default_rng(29 + g)
     a = V.Sketch(m, g, k, seed, "small")
     st = a.state()
     reg = rng.integers(lo, 15, m).astype(np.uint8)
+    if lo:
+        low = rng.random(m) < 0.005
+        reg[low] = rng.integers(0, lo, int(low.sum())).astype(np.uint8)
     hi = rng.random(m) < 0.33
     reg[hi] = rng.integers(15, a.L + 1, int(hi.sum())).astype(np.uint8)
     st["reg"], st["hist"] = reg, np.bincount(reg, minlength=len(st["hist"])).astype(np.uint64)
