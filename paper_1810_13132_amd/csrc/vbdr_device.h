@@ -87,6 +87,16 @@ __host__ __device__ __forceinline__ uint32_t swar_le_mask(uint32_t v, uint32_t b
   return ((even | odd) ^ 0x01010101u) * 0xFFu;
 }
 
+// Bit 7 of every byte whose value is below c, for 1 <= c <= 128 (cc = c in
+// every byte): (x | 0x80) - c cannot borrow across bytes, and its bit 7 is
+// set exactly when (x & 0x7F) >= c; a byte is below c when neither that bit
+// nor its own bit 7 is set.  Four operations against the eight or so of
+// swar_le_mask, for windows of k <= 128 slices (active DR: DR < k).
+__host__ __device__ __forceinline__ uint32_t swar_lt_bit7(uint32_t x, uint32_t cc) {
+  const uint32_t t = (x | 0x80808080u) - cc;
+  return ~(x | t) & 0x80808080u;
+}
+
 // Four register bytes (<= 32) -> four nibbles min(r, 15), byte j -> bits 4j..4j+3.
 __host__ __device__ __forceinline__ uint32_t swar_pack_nibbles(uint32_t r) {
   const uint32_t ge15 = ((r + 0x71717171u) & 0x80808080u) >> 7;  // 1 where r >= 15
@@ -266,7 +276,7 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
                                                 uint32_t gt_bias, const uint32_t* pm, uint32_t pm_stride,
                                                 bool use_seen, u32x4 dn0, u32x4 dn1, uint32_t R[8],
                                                 uint8_t* preg = nullptr, uint32_t* P = nullptr,
-                                                uint32_t* satw = nullptr, uint32_t sat_in = 0u) {
+                                                uint32_t* satw = nullptr, uint32_t sat_in = 0u, uint32_t kk = 0u) {
   uint32_t M[8], Q[8];
 #pragma unroll
   for (int w = 0; w < 8; ++w) {
@@ -323,17 +333,35 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
       continue;
     }
     u32x4 nd0, nd1;
+    if (kk) {  // k <= 128: the active test on bit 7; M holds bit-7 flags of the BDRs whose register is found
 #pragma unroll
-    for (int w = 0; w < 8; ++w) {
-      uint32_t x = w < 4 ? d0[w] : d1[w - 4];
-      if constexpr (!FAST) x &= ~swar_nibble_to_bytes((bits >> (4 * w)) & 0xFu);  // SetDR of the slice
-      uint32_t y = swar_sat_inc(x);                                                // SlideDR
-      if constexpr (FAST) y &= ~swar_nibble_to_bytes((fold >> (4 * w)) & 0xFu);   // SetDR
-      const uint32_t act = swar_le_mask(FAST ? y : x, gt_bias);                    // IsActiveDR
-      R[w] |= act & ~M[w] & ((uint32_t)i * 0x01010101u);
-      M[w] |= act;
-      if (!FAST && preg) Q[w] = (Q[w] & act) | (~act & ((uint32_t)(i - 1) * 0x01010101u));
-      if (w < 4) nd0[w] = y; else nd1[w - 4] = y;
+      for (int w = 0; w < 8; ++w) {
+        uint32_t x = w < 4 ? d0[w] : d1[w - 4];
+        if constexpr (!FAST) x &= ~swar_nibble_to_bytes((bits >> (4 * w)) & 0xFu);  // SetDR of the slice
+        uint32_t y = swar_sat_inc(x);                                                // SlideDR
+        if constexpr (FAST) y &= ~swar_nibble_to_bytes((fold >> (4 * w)) & 0xFu);   // SetDR
+        const uint32_t a7 = swar_lt_bit7(FAST ? y : x, kk);                          // IsActiveDR
+        R[w] += ((a7 & ~M[w]) >> 7) * (uint32_t)i;  // bytes still 0 take i: no carry between bytes
+        M[w] |= a7;
+        if (!FAST && preg) {
+          const uint32_t act = (a7 >> 7) * 0xFFu;
+          Q[w] = (Q[w] & act) | (~act & ((uint32_t)(i - 1) * 0x01010101u));
+        }
+        if (w < 4) nd0[w] = y; else nd1[w - 4] = y;
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        uint32_t x = w < 4 ? d0[w] : d1[w - 4];
+        if constexpr (!FAST) x &= ~swar_nibble_to_bytes((bits >> (4 * w)) & 0xFu);  // SetDR of the slice
+        uint32_t y = swar_sat_inc(x);                                                // SlideDR
+        if constexpr (FAST) y &= ~swar_nibble_to_bytes((fold >> (4 * w)) & 0xFu);   // SetDR
+        const uint32_t act = swar_le_mask(FAST ? y : x, gt_bias);                    // IsActiveDR
+        R[w] |= act & ~M[w] & ((uint32_t)i * 0x01010101u);
+        M[w] |= act;
+        if (!FAST && preg) Q[w] = (Q[w] & act) | (~act & ((uint32_t)(i - 1) * 0x01010101u));
+        if (w < 4) nd0[w] = y; else nd1[w - 4] = y;
+      }
     }
     // a saturated DR that was not set this slice stays 255: vectors that did not
     // change are not written back (most of the high planes, whose DRs are rarely set)

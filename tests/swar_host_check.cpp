@@ -1,5 +1,6 @@
 // Exhaustive CPU check of the SWAR byte helpers in vbdr_device.h (saturating
-// slide, fold mask, <= thr test, nibble packing) against per-byte definitions.
+// slide, fold mask, <= thr and bit-7 < c tests, nibble packing) against
+// per-byte definitions.
 #include "vbdr_device.h"
 #include <cstdio>
 using namespace vbdr;
@@ -19,6 +20,20 @@ int main() {
             uint32_t b = (x >> (8 * j)) & 0xFF;
             if (((le >> (8 * j)) & 0xFF) != (b <= (uint32_t)thr ? 0xFFu : 0u)) bad++;
             if (((inc >> (8 * j)) & 0xFF) != (b < 255 ? b + 1 : 255)) bad++;
+          }
+        }
+  }
+  // the bit-7 test below c for every c of a window k <= 128, every byte value in every position
+  for (uint32_t c = 1; c <= 128; ++c) {
+    const uint32_t cc = c * 0x01010101u;
+    for (int v = 0; v < 256; ++v)
+      for (int pos = 0; pos < 4; ++pos)
+        for (int rep = 0; rep < 4; ++rep) {
+          uint32_t x = (rnd() & ~(0xFFu << (8 * pos))) | ((uint32_t)v << (8 * pos));
+          uint32_t lt = swar_lt_bit7(x, cc);
+          for (int j = 0; j < 4; ++j) {
+            uint32_t b = (x >> (8 * j)) & 0xFF;
+            if (((lt >> (8 * j)) & 0xFF) != (b < c ? 0x80u : 0u)) bad++;
           }
         }
   }
