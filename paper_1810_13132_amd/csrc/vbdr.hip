@@ -586,8 +586,10 @@ __device__ __forceinline__ void advance_defer_tile(uint32_t tile, uint8_t* __res
   if (live) {
     uint32_t R[8];
     uint32_t* satw = sat ? sat + (base >> 5) : nullptr;
+    // windows of k <= 128 slices take the bit-7 active test (swar_lt_bit7)
+    const uint32_t kk = thr < 128u ? (thr + 1u) * 0x01010101u : 0u;
     advance_group32<FAST>(dr, mstride, seen, wstride, reg, reg4, base, L, swar_gt_bias(thr), pm + threadIdx.x,
-                          kDeferWords, use_seen, top0, top1, R, preg, P, satw, sat_ok ? *satw : 0u);
+                          kDeferWords, use_seen, top0, top1, R, preg, P, satw, sat_ok ? *satw : 0u, kk);
 #pragma unroll
     for (int j = 0; j < 32; ++j)
       if (base + j < m) atomicAdd(&lh[wave][lane & (kHistCopies - 1)][(R[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1u);
