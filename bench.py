@@ -19,6 +19,7 @@ launch belongs to a full-window step (warm-up or timed).
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -313,6 +314,42 @@ def run_stress(args):
            "superspreader_truth": [int(v) for v in truth[:w.n_heavy].cpu()],
            "superspreader_estimate": [float(v) for v in est[:w.n_heavy].cpu()],
            "slices_in_window": min(S0 + K, w.k)}
+    # the pool's own HyperLogLog estimate: the distinct pairs in the window
+    hist = sk.registers()[1].astype(np.float64)
+    alpha = 0.7213 / (1 + 1.079 / w.m)
+    em = alpha * w.m * w.m / float(np.sum(hist * np.exp2(-np.arange(len(hist)))))
+    if em <= 2.5 * w.m and hist[0] > 0:
+        em = w.m * math.log(w.m / hist[0])
+    res["pool_distinct_pairs_estimate"] = em
+    if os.path.exists(learn.STRESS_WEIGHTS):
+        # the stress-shape network (trained on synthetic stress windows) on the real stream's last window
+        params, lo, hi, meta = learn.load(learn.STRESS_WEIGHTS)
+        mlp = vbdr.MLP(params, lo, hi, meta.get("plain_above"))
+        lest, fb = sk.estimate_learned(mlp, hosts, with_fallback=True)
+        lest = lest.to(torch.float64)
+
+        def rate(fn):
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(5):
+                fn()
+            b.record()
+            b.synchronize()
+            return len(sel) * 5 / (a.elapsed_time(b) * 1e-3)
+
+        res["learned"] = {
+            "rms_rel_superspreaders": learn.rms_rel(lest[:w.n_heavy], truth[:w.n_heavy]),
+            "rms_rel_background": learn.rms_rel(lest[w.n_heavy:], truth[w.n_heavy:]),
+            "fallback_frac": float((fb == 1).float().mean()),
+            "kept_plain_frac": float((fb == 2).float().mean()),
+            "plain_above": meta.get("plain_above"),
+            "hosts_per_s_plain": rate(lambda: sk.estimate(hosts, out)),
+            "hosts_per_s_learned": rate(lambda: sk.estimate_learned(mlp, hosts)),
+            "weights": "paper_1810_13132_amd/weights/mlp_stress.npz",
+            "trained_on": meta.get("workload", "stress") + " synthetic windows " + str(meta.get("train_seeds"))}
+        mlp.close()
     print(json.dumps(res), flush=True)
 
 

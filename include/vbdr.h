@@ -360,12 +360,23 @@ typedef struct vbdr_trainer vbdr_trainer;
 int vbdr_mlp_create(const float *params_host, const float *env_lo, const float *env_hi, vbdr_mlp **out);
 void vbdr_mlp_destroy(vbdr_mlp *mlp); /* NULL-safe; synchronises the device */
 
+/* Where the plain estimate (Alg. 5 with the noise removed) is at least
+ * `threshold`, vbdr_estimate_learned keeps it and flags the host 2: for
+ * counts large enough that sharing noise no longer dominates the plain
+ * estimate, which a network trained on log counts does not match.
+ * threshold > 0; INFINITY (the default) turns the rule off.  The network
+ * must be on the current device; VBDR_EINVAL otherwise.  Synchronous. */
+int vbdr_mlp_set_plain_above(vbdr_mlp *mlp, float threshold);
+
 /* Features (n_hosts x 67 float, row-major, device) of the given hosts for the
  * last closed window, from the same register gathers as vbdr_estimate. */
 int vbdr_features(vbdr_sketch *sk, const uint32_t *hosts_dev, uint64_t n_hosts, float *feats_dev, void *stream);
 
 /* Learned estimate of n_hosts hosts into out_dev (float); used_fallback_dev
- * (n_hosts bytes, nullable) receives 1 where the plain estimate was used. */
+ * (n_hosts bytes, nullable) receives 1 where the plain estimate was used
+ * because a feature left the training envelope (or the output was not
+ * finite), 2 where it was kept as a large count (vbdr_mlp_set_plain_above),
+ * else 0. */
 int vbdr_estimate_learned(vbdr_sketch *sk, const vbdr_mlp *mlp, const uint32_t *hosts_dev, uint64_t n_hosts,
                           float *out_dev, uint8_t *used_fallback_dev, void *stream);
 

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -34,6 +35,7 @@ struct MlpDev {
   float b1[kHid], b2[kHid], w3[kHid], b3;  // w3 holds bf16-rounded values
   float env_lo[kIn], env_hi[kIn];
   int has_env;
+  float plain_above;  // hosts whose plain estimate is at least this keep it (+inf: none)
 };
 
 // float -> bf16 bits, round to nearest even (host and device).
@@ -275,10 +277,13 @@ __global__ __launch_bounds__(kInfBlock) __attribute__((amdgpu_waves_per_eu(5))) 
       float est = expf(part + mlp->b3) - 1.0f;
       int fb = bad | pool_bad;
       if (!isfinite(est)) fb = 1;
-      if (fb) {
+      const float above = mlp->plain_above;
+      if (fb || above < INFINITY) {
         const double Es = hll_estimate(U, c8[0], (double)g);
         const double n = noise_removed(Es, Em, (double)m, (double)g);
-        est = (float)(n > 0.0 ? n : 0.0);
+        const float plain = (float)(n > 0.0 ? n : 0.0);
+        if (!fb && plain >= above) fb = 2;  // a large count: the plain estimate is kept
+        if (fb) est = plain;
       }
       out[h] = est > 0.0f ? est : 0.0f;
       if (used_fallback) used_fallback[h] = (uint8_t)fb;
@@ -414,6 +419,7 @@ int vbdr_mlp_create(const float* params_host, const float* env_lo, const float* 
   }
   h->b3 = params_host[kOffB3];
   h->has_env = env_lo != nullptr;
+  h->plain_above = INFINITY;
   for (int k = 0; k < kIn; ++k) {
     h->env_lo[k] = env_lo ? env_lo[k] : 0.f;
     h->env_hi[k] = env_hi ? env_hi[k] : 0.f;
@@ -430,6 +436,18 @@ int vbdr_mlp_create(const float* params_host, const float* env_lo, const float* 
     return vbdr_fail(VBDR_EHIP, "upload of the MLP failed");
   }
   *out = mlp;
+  return VBDR_OK;
+}
+
+int vbdr_mlp_set_plain_above(vbdr_mlp* mlp, float threshold) {
+  if (!mlp) return vbdr_fail(VBDR_EINVAL, "mlp is NULL");
+  if (!(threshold > 0.0f)) return vbdr_fail(VBDR_EINVAL, "threshold must be positive (INFINITY: never)");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != mlp->device)
+    return vbdr_fail(VBDR_EINVAL, "the network lives on device %d, not the current one", mlp->device);
+  if (hipMemcpy(reinterpret_cast<uint8_t*>(mlp->dev) + offsetof(MlpDev, plain_above), &threshold, sizeof(float),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return vbdr_fail(VBDR_EHIP, "upload of the threshold failed");
   return VBDR_OK;
 }
 

@@ -11,9 +11,21 @@ feature kernels; the truth is the exact distinct count of the window's pairs
 (Definition 1), computed on the device with sort-unique.  Training runs the
 library's float32 Adam kernels.
 
+With --workload stress (m = 2^24, g = 2048): a stress window holds 10^10 and
+more distinct pairs, too many to replay and count exactly per training
+stream, so samples come from synthetic windows (stress_window): a window's
+registers depend only on the set of distinct pairs in it, so that set goes in
+as one slice, made of uniform background pairs and planted hosts whose
+opposite hosts are distinct by construction (the truth is their number).
+Training windows 0..31, evaluation windows 100..103; the stress benchmark
+then applies the network to the real stress stream (its pool holds about
+4.7·10^9 distinct pairs, inside the background range of the windows).
+
     python -m paper_1810_13132_amd.learn --out paper_1810_13132_amd/weights/mlp_tiny.npz
     python -m paper_1810_13132_amd.learn --workload mid --train-seeds 40 \
         --out paper_1810_13132_amd/weights/mlp_mid.npz
+    python -m paper_1810_13132_amd.learn --workload stress --train-seeds 32 \
+        --out paper_1810_13132_amd/weights/mlp_stress.npz
 """
 import argparse
 import json
@@ -30,7 +42,20 @@ from paper_1810_13132_amd import synth, vbdr
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(PKG, "weights", "mlp_tiny.npz")
 MID_WEIGHTS = os.path.join(PKG, "weights", "mlp_mid.npz")
-WORKLOADS = {"tiny": synth.TINY, "mid": synth.MID}
+STRESS_WEIGHTS = os.path.join(PKG, "weights", "mlp_stress.npz")
+WORKLOADS = {"tiny": synth.TINY, "mid": synth.MID, "stress": synth.STRESS}
+WEIGHTS = {"tiny": DEFAULT_WEIGHTS, "mid": MID_WEIGHTS, "stress": STRESS_WEIGHTS}
+# distinct background pairs of a synthetic stress window: log-uniform over this
+# range, around the pool occupancy of the stress stream's full window
+STRESS_BG = (2.5e9, 9e9)
+# above this plain estimate the stress network keeps the plain one.  The
+# sharing noise of the plain estimate is about the HyperLogLog error of a
+# host's g registers, each shared with E_m / m ~ 280 window pairs: 1.04 /
+# sqrt(g) x g x 280 ~ 1.3e4; 10^5 is ~7.5 of those, so a small host's plain
+# estimate stays below it, while a count above it is large against the noise
+# (the plain estimate's relative error is a few per cent there, which a
+# network trained on log counts does not reach)
+STRESS_PLAIN_ABOVE = 1e5
 
 
 def log(*a):
@@ -71,6 +96,89 @@ def stream_samples(seed: int, w=synth.TINY, layout="fast", mlp=None):
     return out
 
 
+def _as_i32(x: torch.Tensor) -> torch.Tensor:
+    """int64 values 0..2^32-1 as the int32 with the same 32 bits."""
+    return (((x + (1 << 31)) & 0xFFFFFFFF) - (1 << 31)).to(torch.int32)
+
+
+def _bijection32(x: torch.Tensor, key: int) -> torch.Tensor:
+    """A keyed bijection of 32-bit values held in int64 (odd multiplies and
+    xor-shifts, the constants of Wellons' lowbias32): distinct inputs give
+    distinct outputs.  Input generation only, not the estimator's hash."""
+    M = 0xFFFFFFFF
+    x = (x * 0x9E3779B1 + key) & M
+    x = x ^ (x >> 16)
+    x = (x * 0x7FEB352D) & M
+    x = x ^ (x >> 15)
+    x = (x * 0x846CA68B) & M
+    return x ^ (x >> 16)
+
+
+def stress_window(seed: int, w=synth.STRESS, layout="small", mlp=None, n_small=1 << 14, n_large=768,
+                  n_bg=None):
+    """One synthetic window of the stress shape (m, g of `w`): its distinct
+    pairs scanned as one slice of a k = 1 sketch, then closed.  Background:
+    n_bg uniform random pairs (aip below 2^31; log-uniform in STRESS_BG by
+    default).  Planted hosts (aip 2^31 and above, distinct): n_small with
+    Zipf(1.5) on 1..10^4 opposite hosts like the stream's background hosts and
+    n_large log-uniform on 10^4..10^7 like its superspreaders, the opposite
+    hosts of each distinct (a keyed bijection of 0..n-1).  Returns features,
+    truth (the planted counts), plain (and learned) estimates of the planted
+    hosts, and the background size."""
+    rng = np.random.default_rng(7919 + seed)
+    if n_bg is None:
+        n_bg = int(math.exp(rng.uniform(math.log(STRESS_BG[0]), math.log(STRESS_BG[1]))))
+    sk = vbdr.Sketch(w.m, w.g, 1, seed, layout)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(104729 + seed)
+    done, chunk = 0, 1 << 26
+    while done < n_bg:
+        c = min(chunk, n_bg - done)
+        pd = torch.randint(0, 1 << 32, (c, 2), dtype=torch.int64, device="cuda", generator=gen)
+        pd[:, 0] &= 0x7FFFFFFF
+        sk.scan_slice(_as_i32(pd).view(-1))
+        done += c
+        del pd
+    ks = np.arange(1, 10**4 + 1, dtype=np.float64)
+    cdf = np.cumsum(ks ** -1.5)
+    small = 1 + np.searchsorted(cdf / cdf[-1], rng.random(n_small))
+    large = np.exp(rng.uniform(math.log(1e4), math.log(1e7), n_large)).astype(np.int64)
+    counts = np.concatenate([small, large]).astype(np.int64)
+    addr = np.unique(rng.integers(0, 1 << 31, 2 * len(counts), dtype=np.int64))
+    addr = rng.permutation(addr)[:len(counts)] | (1 << 31)
+    keys = rng.integers(0, 1 << 32, len(counts), dtype=np.int64)
+    # the planted pairs, a block of hosts at a time (at most ~2^26 pairs)
+    i = 0
+    while i < len(counts):
+        j, tot = i, 0
+        while j < len(counts) and (tot == 0 or tot + counts[j] <= chunk):
+            tot += int(counts[j])
+            j += 1
+        cnt = torch.from_numpy(counts[i:j]).cuda()
+        start = torch.cumsum(cnt, 0) - cnt
+        host = torch.repeat_interleave(torch.arange(j - i, device="cuda"), cnt)
+        local = torch.arange(tot, device="cuda") - start[host]
+        bip = _bijection32(local, 0) ^ torch.from_numpy(keys[i:j]).cuda()[host]
+        aip = torch.from_numpy(addr[i:j]).cuda()[host]
+        sk.scan_slice(_as_i32(torch.stack([aip, bip], 1)).view(-1))
+        i = j
+    sk.advance_slice()
+    hosts = vbdr.to_device_u32(addr.astype(np.uint32))
+    rec = {"feats": sk.features(hosts), "truth": torch.from_numpy(counts).cuda(), "plain": sk.estimate(hosts),
+           "n_bg": n_bg, "n_large": n_large}
+    if mlp is not None:
+        rec["learned"], rec["fallback"] = sk.estimate_learned(mlp, hosts, with_fallback=True)
+    sk.close()
+    return rec
+
+
+def window_samples(seed: int, w, mlp=None):
+    """The samples of one training or evaluation seed of workload `w`."""
+    if w.name == "stress":
+        return [stress_window(seed, w, mlp=mlp)]
+    return stream_samples(seed, w, mlp=mlp)
+
+
 def rms_rel(est, truth):
     t = truth.to(torch.float64)
     keep = t >= 1
@@ -100,10 +208,10 @@ def train(train_seeds=range(100), n_samples=10**6, epochs=30, batch=4096, lr=3e-
     t0 = time.time()
     feats, targets = [], []
     for s in train_seeds:
-        for rec in stream_samples(s, w):
+        for rec in window_samples(s, w):
             feats.append(rec["feats"])
             targets.append(torch.log1p(rec["truth"].to(torch.float32)))
-        if s % 10 == 9:
+        if s % 10 == 9 or w.name == "stress":
             log(f"train seed {s}: {sum(len(t) for t in targets)} samples ({time.time() - t0:.1f}s)")
     X = torch.cat(feats)
     Y = torch.cat(targets)
@@ -131,11 +239,11 @@ def train(train_seeds=range(100), n_samples=10**6, epochs=30, batch=4096, lr=3e-
                                  "train_seeds": [min(train_seeds), max(train_seeds)], "workload": w.name}
 
 
-def evaluate(params, lo, hi, eval_seeds=range(100, 110), w=synth.TINY):
-    mlp = vbdr.MLP(params, lo, hi)
+def evaluate(params, lo, hi, eval_seeds=range(100, 110), w=synth.TINY, plain_above=None):
+    mlp = vbdr.MLP(params, lo, hi, plain_above)
     ests, truths, plains, fbs = [], [], [], []
     for s in eval_seeds:
-        for rec in stream_samples(s, w, mlp=mlp):
+        for rec in window_samples(s, w, mlp=mlp):
             ests.append(rec["learned"])
             plains.append(rec["plain"])
             truths.append(rec["truth"])
@@ -143,7 +251,15 @@ def evaluate(params, lo, hi, eval_seeds=range(100, 110), w=synth.TINY):
     est, plain, truth, fb = torch.cat(ests), torch.cat(plains), torch.cat(truths), torch.cat(fbs)
     res = {"samples": int(len(truth)), "samples_n_ge_1": int((truth >= 1).sum()),
            "rms_rel_plain": rms_rel(plain, truth), "rms_rel_learned": rms_rel(est, truth),
-           "fallback_frac": float(fb.float().mean()), "eval_seeds": [min(eval_seeds), max(eval_seeds)]}
+           "fallback_frac": float((fb == 1).float().mean()), "eval_seeds": [min(eval_seeds), max(eval_seeds)]}
+    if w.name == "stress":  # the planted heavy hosts apart (10^4..10^7), as the stress benchmark reports them
+        res["kept_plain_frac"] = float((fb == 2).float().mean())
+        big = truth >= 10**4
+        res["rms_rel_plain_large"] = rms_rel(plain[big], truth[big])
+        res["rms_rel_learned_large"] = rms_rel(est[big], truth[big])
+        res["rms_rel_plain_small"] = rms_rel(plain[~big], truth[~big])
+        res["rms_rel_learned_small"] = rms_rel(est[~big], truth[~big])
+        return res
     # estimation throughput on the same sketch shape with a full window, the
     # stream's hosts repeated to 2^18 estimates per launch, plain vs learned
     st = synth.Stream(w.scaled(seed=min(eval_seeds)))
@@ -186,16 +302,20 @@ def main():
     args = ap.parse_args()
     w = WORKLOADS[args.workload]
     if args.out is None:
-        args.out = DEFAULT_WEIGHTS if args.workload == "tiny" else MID_WEIGHTS
+        args.out = WEIGHTS[args.workload]
     if args.eval_only:
         params, lo, hi, meta = load(args.out)
+        if w.name == "stress":
+            meta["plain_above"] = STRESS_PLAIN_ABOVE
     else:
         params, lo, hi, meta = train(range(args.train_seeds), args.samples, args.epochs, w=w)
-    res = evaluate(params, lo, hi, w=w)
+        if w.name == "stress":
+            meta["plain_above"] = STRESS_PLAIN_ABOVE
+    res = evaluate(params, lo, hi, eval_seeds=range(100, 104) if w.name == "stress" else range(100, 110), w=w,
+                   plain_above=meta.get("plain_above"))
     meta["eval"] = res
-    if not args.eval_only:
-        os.makedirs(os.path.dirname(args.out), exist_ok=True)
-        np.savez(args.out, params=params, env_lo=lo, env_hi=hi, meta=np.array(json.dumps(meta)))
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    np.savez(args.out, params=params, env_lo=lo, env_hi=hi, meta=np.array(json.dumps(meta)))
     print(json.dumps(meta), flush=True)
 
 

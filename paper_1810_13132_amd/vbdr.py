@@ -65,7 +65,7 @@ EXPORTS = ["vbdr_sketch_create", "vbdr_sketch_create_layout", "vbdr_sketch_creat
            "vbdr_batch_set_tuning", "vbdr_batch_get_tuning", "vbdr_batch_step", "vbdr_select_hosts",
            "vbdr_export_now", "vbdr_import_now", "vbdr_now_max", "vbdr_enable_pcsa", "vbdr_estimate_kind",
            "vbdr_export_pcsa", "vbdr_test_fail_alloc", "vbdr_estimate_noalloc",
-           "vbdr_batch_set_mlp"]
+           "vbdr_batch_set_mlp", "vbdr_mlp_set_plain_above"]
 VOID_EXPORTS = ("vbdr_sketch_destroy", "vbdr_last_error", "vbdr_mlp_destroy", "vbdr_trainer_destroy",
                 "vbdr_batch_destroy", "vbdr_batch_sketch")
 MLP_IN, MLP_PARAMS = 67, 8577
@@ -98,6 +98,7 @@ def lib():
         L.vbdr_sketch_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.vbdr_mlp_create.argtypes = [vp, vp, vp, C.POINTER(vp)]
         L.vbdr_mlp_destroy.argtypes = [vp]
+        L.vbdr_mlp_set_plain_above.argtypes = [vp, C.c_float]
         L.vbdr_features.argtypes = [vp, vp, u64, vp, vp]
         L.vbdr_estimate_learned.argtypes = [vp, vp, vp, u64, vp, vp, vp]
         L.vbdr_trainer_create.argtypes = [vp, C.c_float, C.POINTER(vp)]
@@ -400,7 +401,7 @@ def _host_f32(a, n, name):
 class MLP:
     """A learned-estimator network on the current device (bf16 weights)."""
 
-    def __init__(self, params, env_lo=None, env_hi=None):
+    def __init__(self, params, env_lo=None, env_hi=None, plain_above=None):
         p = _host_f32(params, MLP_PARAMS, "params")
         lo = None if env_lo is None else _host_f32(env_lo, MLP_IN, "env_lo")
         hi = None if env_hi is None else _host_f32(env_hi, MLP_IN, "env_hi")
@@ -408,6 +409,12 @@ class MLP:
         _check(lib().vbdr_mlp_create(p.ctypes.data, None if lo is None else lo.ctypes.data,
                                      None if hi is None else hi.ctypes.data, C.byref(h)))
         self._h = h
+        if plain_above is not None:
+            self.set_plain_above(plain_above)
+
+    def set_plain_above(self, threshold: float):
+        """Keep the plain estimate where it is at least `threshold` (inf: never)."""
+        _check(lib().vbdr_mlp_set_plain_above(self._h, float(threshold)))
 
     def close(self):
         h = getattr(self, "_h", None)

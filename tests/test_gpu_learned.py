@@ -103,6 +103,32 @@ def test_learned_fallback_is_the_plain_estimate(V, O, M):
     assert not fb2.cpu().numpy().any()
 
 
+@pytest.mark.parametrize("m,layout", [(30011, "fast"), ((1 << 22) + 5, "small")])
+def test_learned_plain_above_keeps_large_counts(V, O, M, m, layout):
+    """With a threshold, hosts whose plain estimate reaches it keep the plain
+    estimate bit for bit (flag 2) and the others keep the network's output
+    (flag 0); no threshold (inf) gives the network's output everywhere.  The
+    second case takes the partitioned histogram path of large pools."""
+    sk, osk, hosts = _build(V, O, m, 128, 4, 5, layout)
+    params = _random_params(M, 4)
+    hd = V.to_device_u32(hosts)
+    plain = sk.estimate(hd)
+    out0, fb0 = sk.estimate_learned(V.MLP(params), hd, with_fallback=True)
+    assert not fb0.any()
+    thr = float(torch.quantile(plain.double(), 0.6))
+    cut = V.MLP(params, plain_above=thr)
+    out1, fb1 = sk.estimate_learned(cut, hd, with_fallback=True)
+    big = plain >= thr
+    assert 0 < int(big.sum()) < len(hosts)
+    assert torch.equal(fb1 == 2, big) and not (fb1 == 1).any()
+    assert torch.equal(out1[big], plain[big]) and torch.equal(out1[~big], out0[~big])
+    with pytest.raises(V.VbdrError):
+        cut.set_plain_above(0.0)
+    cut.set_plain_above(float("inf"))
+    out2, fb2 = sk.estimate_learned(cut, hd, with_fallback=True)
+    assert torch.equal(out2, out0) and not fb2.any()
+
+
 def test_train_gradient_matches_fp64(V, M):
     rng = np.random.default_rng(0)
     params = _random_params(M, 9)
