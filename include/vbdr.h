@@ -264,7 +264,10 @@ int vbdr_sketch_info(const vbdr_sketch *sk, vbdr_info *out);
  *                      runs take about 4*g bytes per host; default: as many
  *                      as the run buffer holds); for the tiled estimate,
  *                      hosts per block, rounded down to a multiple of 2048
- *                      (at least 2048, at most the default min(2^29/g, 2^19));
+ *                      (at least 2048, at most the default min(2^29/g, 2^19)),
+ *                      and its workspace is sized for that block (about
+ *                      4.3 g + 4 nt bytes per host of the block; this call
+ *                      reallocates it): a memory budget, at some speed;
  *   est_bin_cap        slots per run of the binned (per host and range) or
  *                      tiled (per 2048 hosts and tile) estimate, at most the
  *                      default; entries beyond it are gathered directly by

@@ -1938,13 +1938,37 @@ namespace {
 // sorted chunk (s1 goes to LDS only if it fits beside them).
 size_t defer_scan_lds(uint32_t tiles) { return (size_t)(2 * tiles + kDeferChunk) * 4; }
 
+// Hosts per block of the tiled estimate under the current tuning: the
+// default block (tl_B), or est_bin_hosts rounded down to whole sub-blocks.
+uint32_t tiled_block_hosts(const vbdr_sketch* sk) {
+  uint32_t B = sk->tl_B;
+  if (sk->tune.est_bin_hosts && sk->tune.est_bin_hosts < B)
+    B = sk->tune.est_bin_hosts < kTileSub ? kTileSub : sk->tune.est_bin_hosts / kTileSub * kTileSub;
+  return B;
+}
+
 // Workspaces of the LDS-tiled estimate (records, run lengths, partial and
-// overflow sums of one block of hosts), once the variant is selected.
+// overflow sums of one block of hosts, wide-register lists), once the
+// variant is selected, sized for the tuning's block: a smaller est_bin_hosts
+// gives a smaller workspace (the buffers are reallocated when it changes).
 int alloc_tiled(vbdr_sketch* sk) {
-  if (!sk->tl_ok || sk->tl_rec) return VBDR_OK;
-  const uint64_t nsb = sk->tl_B / kTileSub;
+  if (!sk->tl_ok) return VBDR_OK;
+  const uint32_t Bw = tiled_block_hosts(sk);
+  if (sk->tl_rec && sk->tl_Balloc == Bw) return VBDR_OK;
+  if (sk->tl_rec) {  // another block size: the old buffers go first (no kernel may still use them)
+    if (int rc = vbdr_check_device(sk)) return rc;
+    VBDR_HIP(hipDeviceSynchronize());
+    const uint64_t nsb0 = sk->tl_Balloc / kTileSub;
+    sk->bytes -= nsb0 * sk->tl_nt * sk->tl_cap * 4 + nsb0 * sk->tl_nt * 4 + (uint64_t)sk->tl_nt * sk->tl_Balloc * 4 +
+                 (uint64_t)sk->tl_Balloc * 8 + (uint64_t)sk->tl_nt * sk->tl_wcap * 8 + (uint64_t)sk->tl_nt * 4;
+    for (void* q : {(void*)sk->tl_rec, (void*)sk->tl_fill, (void*)sk->tl_part, (void*)sk->tl_ovf, (void*)sk->tl_wide})
+      (void)hipFree(q);
+    sk->tl_rec = nullptr, sk->tl_fill = nullptr, sk->tl_part = nullptr, sk->tl_ovf = nullptr, sk->tl_wide = nullptr;
+    sk->tl_Balloc = 0;
+  }
+  const uint64_t nsb = Bw / kTileSub;
   const uint64_t rec_b = nsb * sk->tl_nt * sk->tl_cap * 4, fill_b = nsb * sk->tl_nt * 4;
-  const uint64_t part_b = (uint64_t)sk->tl_nt * sk->tl_B * 4, ovf_b = (uint64_t)sk->tl_B * 8;
+  const uint64_t part_b = (uint64_t)sk->tl_nt * Bw * 4, ovf_b = (uint64_t)Bw * 8;
   // wide lists: [nt][tl_wcap] entries, then nt counts
   sk->tl_wcap = (uint32_t)(kTileWideTotal / sk->tl_nt);
   const uint64_t wide_b = (uint64_t)sk->tl_nt * sk->tl_wcap * 8 + (uint64_t)sk->tl_nt * 4;
@@ -1958,6 +1982,7 @@ int alloc_tiled(vbdr_sketch* sk) {
     return vbdr_fail(VBDR_ENOMEM, "allocation of the tiled-estimate workspace failed");
   }
   sk->bytes += rec_b + fill_b + part_b + ovf_b + wide_b;
+  sk->tl_Balloc = Bw;
   return VBDR_OK;
 }
 
@@ -2408,9 +2433,7 @@ int vbdr_estimate_ex(vbdr_sketch* sk, const uint32_t* hosts_dev, uint64_t n_host
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool extra = raw_es_dev || hist_dev;
   if (sk->tl_rec && sk->tune.est_binned == 3 && !extra && n_hosts < (1ull << 32)) {
-    uint32_t B = sk->tl_B;
-    if (sk->tune.est_bin_hosts && sk->tune.est_bin_hosts < B)
-      B = sk->tune.est_bin_hosts < kTileSub ? kTileSub : sk->tune.est_bin_hosts / kTileSub * kTileSub;
+    uint32_t B = sk->tl_Balloc;  // the block the workspace holds (tiled_block_hosts of the tuning)
     {  // blocks of equal size (whole sub-blocks): no small last block (line rate: 2^19 + 102,494 hosts 1.85 ms,
        // 2 x 313,391 1.81 ms)
       const uint64_t nblk = (n_hosts + B - 1) / B, even = (n_hosts + nblk - 1) / nblk;

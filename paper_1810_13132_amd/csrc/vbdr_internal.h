@@ -58,6 +58,7 @@ struct vbdr_sketch {
   unsigned long long* tl_ovf;     // [B] sums of run overflows
   uint2* tl_wide;                 // [nt][tl_wcap] records of registers >= 15 found by pass 2, then [nt] counts
   uint32_t tl_wcap;
+  uint32_t tl_Balloc;             // hosts per block the record, run-length and sum buffers hold (<= tl_B)
   uint32_t* def_rec;              // [def_tiles][def_cap] deferred scan records (pidx << 5 | LBP1-1)
   uint32_t* sat;                  // deferred scans: [wstride] bit r-1 = DR[r] of all 32 BDRs saturated (255, or 2^z - 1)
   unsigned long long* def_fill;   // [def_tiles + 1] records per tile; the last word flags direct updates

@@ -362,6 +362,32 @@ def test_tiled_estimate_high_registers(V, O, g, lo):
         assert torch.equal(b.estimate(hd), out), tune
 
 
+def test_tiled_workspace_follows_block_size(V):
+    """est_bin_hosts sizes the tiled estimate's workspace: a smaller block
+    frees most of it, the estimates stay bit for bit the same, and the
+    default tuning brings the full workspace back."""
+    m, g, k = 1 << 24, 1024, 4
+    sk = V.Sketch(m, g, k, 3, "small")
+    rng = np.random.default_rng(11)
+    aips = rng.integers(0, 2**32, 3000, dtype=np.uint64).astype(np.uint32)
+    for _ in range(3):
+        n = 1 << 20
+        pairs = np.stack([aips[rng.integers(0, len(aips), n)],
+                          rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)], 1).astype(np.uint32)
+        sk.scan_slice(V.to_device_u32(pairs.reshape(-1)))
+        sk.advance_slice()
+    hosts = _dev(V, np.concatenate([aips, rng.integers(0, 2**32, 9000, dtype=np.uint64).astype(np.uint32)]))
+    full = sk.info().workspace_bytes
+    ref = sk.estimate(hosts)
+    sk.set_tuning(est_binned=3, est_bin_hosts=4096)
+    small = sk.info().workspace_bytes
+    assert small < full / 4, (small, full)
+    assert torch.equal(sk.estimate(hosts), ref)
+    sk.set_tuning()
+    assert sk.info().workspace_bytes == full
+    assert torch.equal(sk.estimate(hosts), ref)
+
+
 def test_default_estimate_by_pool_size(V):
     """Pools from 2^24 BDRs default to the LDS-tiled estimate, smaller ones to
     the partitioned one; on the same sketch the tiled, partitioned and direct
