@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch_estimate(const BatchDesc* __r
     for (uint64_t h = lo + wave; h < hi; h += kBBlock / 64) {
       uint64_t U;
       uint32_t V;
-      host_harmonic<8>(mm3_key(D.hosts[h]), D.s1, D.g, D.m, D.reg, lane, U, V);
+      host_harmonic<8>(mm3_key(D.hosts[h]), D.s1, D.g, D.m, D.reg4, D.reg, lane, U, V);
       if (lane == 0) {
         const double Es = hll_estimate(U, V, (double)D.g);
         const double n = noise_removed(Es, Em, (double)D.m, (double)D.g);

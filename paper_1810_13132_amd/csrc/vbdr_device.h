@@ -417,19 +417,27 @@ __device__ __forceinline__ double pool_estimate(const unsigned long long* hist, 
 
 // Exact harmonic sum U = sum 2^(32-R) and zero count V of one host's g
 // registers (getPhyIdx of Alg. 3, register gathers of Alg. 5), summed over
-// the wave; kmix = mm3_key(aip).  Every lane returns the totals.
+// the wave; kmix = mm3_key(aip).  Every lane returns the totals.  The
+// registers are read from their nibble copy reg4, half the bytes of reg, so
+// that a larger share of a big pool stays in each XCD's L2; a nibble of 15
+// stands for 15 and more and is read again from reg.
 template <int UNROLL>
 __device__ __forceinline__ void host_harmonic(uint32_t kmix, const uint32_t* s1, uint32_t g, uint32_t m,
-                                              const uint8_t* reg, int lane, uint64_t& U, uint32_t& V) {
+                                              const uint8_t* reg4, const uint8_t* reg, int lane, uint64_t& U,
+                                              uint32_t& V) {
   U = 0;
   V = 0;
   for (uint32_t i0 = lane; i0 < g; i0 += 64 * UNROLL) {
-    uint32_t r[UNROLL];
+    uint32_t p[UNROLL], r[UNROLL];
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       const uint32_t i = i0 + 64u * u;
-      r[u] = i < g ? (uint32_t)reg[reduce_m(mm3_seeded(kmix, s1[i]), m)] : 255u;
+      p[u] = i < g ? reduce_m(mm3_seeded(kmix, s1[i]), m) : 0u;
+      r[u] = i < g ? ((uint32_t)reg4[p[u] >> 1] >> ((p[u] & 1u) << 2)) & 0xFu : 255u;
     }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u)
+      if (r[u] == 15u) r[u] = reg[p[u]];
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u)
       if (r[u] != 255u) {

@@ -162,6 +162,43 @@ def test_batch_deferred_member_overflow(V, layout):
             assert np.array_equal(sb[key], ss[key]), key
 
 
+def test_batch_estimate_reads_high_registers(V):
+    """The batch estimate gathers registers from their nibble copy, where 15
+    stands for 15 and more and sends the gather to the byte array.  DRs are
+    planted so that about a third of the registers come out 15 or more after
+    the step's advance (the highest recent LBP1 of a BDR is its register):
+    the batch must give the estimates of the same sketches stepped alone,
+    which gather the bytes."""
+    params = [dict(m=1 << 16, g=1024, k=8, hash_seed=11, layout="small"),
+              dict(m=(1 << 22) + 3, g=256, k=8, hash_seed=12, layout="small")]
+    rng = np.random.default_rng(13)
+    bt = V.Batch(params)
+    singles = [V.Sketch(**p) for p in params]
+    for b, s in zip(bt.sketches, singles):
+        st = s.state()
+        m, L = st["dr"].shape
+        top = rng.integers(1, 15, m)
+        hi = rng.random(m) < 0.33
+        top[hi] = rng.integers(15, L + 1, int(hi.sum()))
+        dr = np.full((m, L), 255, np.uint8)
+        dr[np.arange(m), top - 1] = rng.integers(0, 4, m).astype(np.uint8)  # set within the last 4 slices
+        reg = np.zeros(m, np.uint8)
+        st.update(dr=dr, reg=reg, hist=np.bincount(reg, minlength=len(st["hist"])).astype(np.uint64))
+        b.load_state(st)
+        s.load_state(st)
+    hosts = [rng.integers(0, 2**32, 3000, dtype=np.uint64).astype(np.uint32) for _ in params]
+    hd = [V.to_device_u32(h) for h in hosts]
+    pd = [V.to_device_u32(np.zeros(0, np.uint32)) for _ in params]
+    outs = [torch.empty(len(h), dtype=torch.float32, device="cuda") for h in hosts]
+    bt.step(pd, hd, outs)
+    for i, s in enumerate(singles):
+        s.advance_slice()
+        reg, _ = s.registers()
+        assert 0.25 < float((reg >= 15).mean()) < 0.4, i
+        assert np.array_equal(bt.sketches[i].registers()[0], reg), i
+        assert torch.equal(outs[i], s.estimate(hd[i])), i
+
+
 def test_batch_learned_members(V):
     """Members with a learned estimator (vbdr_batch_set_mlp) get the learned
     estimates of the same sketch stepped alone (bit for bit); the others keep
