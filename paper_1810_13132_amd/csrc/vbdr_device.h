@@ -286,8 +286,12 @@ __device__ __forceinline__ void advance_group32(uint8_t* dr, uint64_t mstride, u
   uint32_t folded = 0;
   uint32_t sn = 0;
   if (FAST && use_seen) sn = seen[(uint64_t)(L - 1) * wstride + (base >> 5)];
-  // two planes in flight: plane i is processed while i-1 and i-2 load (one
-  // plane of lookahead left too few bytes in flight per CU to cover latency).
+  // Loads run ahead of the plane being processed: plane i-2's load is issued
+  // before plane i's work.  The buffers rotate by copies, so the compiler
+  // waits for that load at the end of the step; about one plane is in flight
+  // while a plane is processed.  Deeper lookahead (three planes in fixed
+  // registers, bounded buffer loads and stores) measured the same time: the
+  // sweep is bound by its streams, not by this latency.
   // Bit r-1 of sat_in: the 32 DR[r] were all 255 after the last advance and
   // nothing but the advance has written DRs since; with no record of this
   // slice in that plane they are 255 now and stay 255, so they are neither
