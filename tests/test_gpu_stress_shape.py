@@ -3,7 +3,8 @@
 Pool m = 2^24 BDRs, g = 2048 (b = 11, L = 22), window k = 128: the shape
 the stress benchmark times.  Deferred scans and advances; the LDS-tiled
 estimate with 2^16-register tiles, two seeds per thread in its first pass
-(g is twice the pass's workgroup) and blocks of 2^18 hosts.  k = 128 is the
+(g is twice the pass's workgroup) and blocks of 2^18 hosts; the packed
+layout at Lc = 16 recorders of z = 8 bits.  k = 128 is the
 edge of the advance's bit-7 activity test: the fast layout's threshold
 k - 1 = 127 takes it, the small layout's threshold k = 128 takes the
 general comparison.  The stream is the stress workload's (Zipf(1.5)
@@ -49,12 +50,17 @@ def test_stress_shape_against_oracle(V):
     m, g, k, seed = w.m, w.g, w.k, w.seed
     st = synth.Stream(w)
     torch.cuda.set_device(0)
-    sks = {"fast": V.Sketch(m, g, k, seed, "fast"), "small": V.Sketch(m, g, k, seed, "small")}
+    Lc = 16
+    sks = {"fast": V.Sketch(m, g, k, seed, "fast"), "small": V.Sketch(m, g, k, seed, "small"),
+           "packed": V.Sketch(m, g, k, seed, "packed", Lc=Lc)}
     for name, sk in sks.items():
         info = sk.info()
         assert info.scan_deferred == 1 and info.est_tiled == 1, name
-        assert sk.L == 22, name
-    rp = {name: replay.WindowReplay(m, g, k, seed, name) for name in sks}
+        assert sk.L == 22 and sk.dr_bits == 8, name  # k = 128 needs z = 8 bits in the packed layout too
+    rp = {name: replay.WindowReplay(m, g, k, seed, name) for name in ("fast", "small")}
+
+    def expected(name):
+        return rp["small"].state(Lc=Lc) if name == "packed" else rp[name].state()
 
     t0 = time.time()
     last_seen = np.full(w.hosts, -1, dtype=np.int32)  # last slice with a pair of the host
@@ -77,19 +83,21 @@ def test_stress_shape_against_oracle(V):
             r.advance()
         if t in (k - 1, k + 1):
             for name, sk in sks.items():
-                gs, exp = sk.state(), rp[name].state()
+                gs, exp = sk.state(), expected(name)
                 assert gs["t"] == exp["t"] == t + 1, name
                 bad = np.argwhere(gs["dr"] != exp["dr"])
                 assert len(bad) == 0, f"{name}: {len(bad)} DRs differ after slice {t}, first {bad[:4].tolist()}"
                 assert not gs["bs"].any(), name
                 assert np.array_equal(gs["reg"], exp["reg"]), f"{name}: registers differ after slice {t}"
                 assert np.array_equal(gs["hist"], exp["hist"]), f"{name}: pool histogram differs after slice {t}"
-            _log(f"slice {t}: full state of both layouts equal ({time.time() - t0:.0f}s)")
+            _log(f"slice {t}: full state of 3 layouts equal ({time.time() - t0:.0f}s)")
         elif t in (0, k):
-            exp = rp["small"].registers()
-            assert np.array_equal(exp, rp["fast"].registers())
+            reg_b = rp["small"].registers()
+            assert np.array_equal(reg_b, rp["fast"].registers())
+            reg_p = rp["small"].registers(Lc=Lc)
             for name, sk in sks.items():
                 reg, hist = sk.registers()
+                exp = reg_p if name == "packed" else reg_b
                 assert np.array_equal(reg, exp), f"{name}: registers differ after slice {t}"
                 assert np.array_equal(hist, np.bincount(exp, minlength=33).astype(np.uint64)), name
             _log(f"slice {t}: registers equal ({time.time() - t0:.0f}s)")
@@ -120,13 +128,19 @@ def test_stress_shape_against_oracle(V):
     sample = np.unique(np.concatenate([rng.choice(n, 1 << 14, replace=False), edges, heavy]))
     reg = rp["small"].registers()
     ref, raw, hist = O.estimate_registers(m, g, seed, reg, hosts[sample], True, True)
-    pool = np.bincount(reg, minlength=33).astype(np.uint64)
-    em = O.hll_from_hist(pool, m)
-    floor = 1e-12 * (m * np.abs(raw) + g * em) / (m - g)
-    for name in ("fast", "small"):
+    reg_p = rp["small"].registers(Lc=Lc)
+    ref_p, raw_p = O.estimate_registers(m, g, seed, reg_p, hosts[sample], True)
+
+    def check(name, ref, raw, reg):
+        em = O.hll_from_hist(np.bincount(reg, minlength=33).astype(np.uint64), m)
+        floor = 1e-12 * (m * np.abs(raw) + g * em) / (m - g)
         got = outs[name][sample].astype(np.float64)
         bad = np.abs(got - ref.astype(np.float64)) > 1e-6 * np.abs(ref.astype(np.float64)) + floor
         assert not bad.any(), f"{name}: {int(bad.sum())} estimates off, e.g. {got[bad][:4]} vs {ref[bad][:4]}"
+
+    check("fast", ref, raw, reg)
+    check("small", ref, raw, reg)
+    check("packed", ref_p, raw_p, reg_p)
     ex_out, ex_raw, ex_hist = sks["small"].estimate_ex(V.to_device_u32(hosts[sample]))
     assert np.array_equal(ex_hist.cpu().numpy().astype(np.uint32), hist)
     np.testing.assert_allclose(ex_raw.cpu().numpy(), raw, rtol=1e-13, atol=0)
